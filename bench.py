@@ -1,0 +1,139 @@
+"""Benchmark: FP64 RK4 grid-point updates per second of the BSSN + radiation
+fluid hot path on one MI355X, on the 256^3 periodic configuration (box 16/H0,
+Gaussian curvature perturbation mu = 0.6, sigma = 2.0, CFL 0.25).
+
+One step = one classic RK4 step = 4 launches of the stage kernel
+(k_bssn_stage), inputs resident in HBM. Prints one JSON line with the
+roofline of that kernel (algorithmic bytes per launch / average launch time,
+measured with HIP events on the launch stream) and the CPU oracle timed on a
+bounded sample of the same workload.
+
+Extra modes (for profiling runs of committed code):
+  --copy-probe   only a plain device-to-device copy of known size (calibrates
+                 rocprofv3 FETCH_SIZE / WRITE_SIZE counters)
+  --no-cpu       skip the CPU baseline leg
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import torch
+
+METRIC = "grid-point RK4 updates/sec FP64 at 256^3 (+ batched runs/sec, adjoint cost)"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+# algorithmic HBM bytes per point per RK4 step: 16 passes over the 25 FP64 fields
+# (stage 1 reads u, writes acc and U2; stages 2-3 read U_s, u, acc and write acc, U_{s+1};
+#  stage 4 reads U4, acc and writes u): 16 * 25 * 8
+BYTES_PER_POINT_STEP = 3200.0
+LAUNCHES_PER_STEP = 4
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    return ap.parse_args()
+
+
+def copy_probe():
+    nbytes = 1 << 30
+    x = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": nbytes, "copy_probe_bytes_written": nbytes, "launches": 5}))
+
+
+def flops_per_point_step():
+    """Algorithmic FLOPs of one RK4 step per grid point, counted by the oracle's
+    operation-counting scalar on a small state (the count is data independent)."""
+    import oracle
+    from tests.inputs import fuzz_state
+    s = oracle.Setup(n=(8, 8, 8), L=(2.4, 2.4, 2.4))
+    return oracle.count_flops(s, fuzz_state(s.n, seed=1))["step_per_point"]
+
+
+def cpu_baseline(n_steps: int):
+    """The oracle (serial FP64 C++, OpenMP over z-planes) on a bounded sample of
+    the workload: RK4 steps on a 64^3 periodic grid with the benchmark's grid
+    spacing h = 1/16 and perturbation parameters; its cost per point is the
+    same as on the full grid."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    s = oracle.Setup(n=(64, 64, 64), L=(4.0, 4.0, 4.0))
+    u = oracle.init_fields(s, oracle.Init(mu=0.6, sigma=2.0))
+    dt = 0.25 * s.h[0]
+    oracle.rk4(s, u, 0.0, dt, 1, parallel=True)  # warm-up
+    t0 = time.perf_counter()
+    oracle.rk4(s, u, 0.0, dt, n_steps, parallel=True)
+    el = time.perf_counter() - t0
+    return {"value": 64 ** 3 * n_steps / el, "unit": "point-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n_steps} RK4 steps of the CPU oracle on a 64^3 periodic grid (h = 1/16, mu = 0.6, "
+                      f"sigma = 2.0), OpenMP over z-planes, {el:.1f} s"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (this build has no multi-GPU path); got --gpus {a.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+    if a.copy_probe:
+        copy_probe()
+        return
+    import paper_2606_02053_amd as P
+    n, L = a.n, 16.0
+    sol = P.Solver(n, L)
+    sol.init(mu=0.6, sigma=2.0)
+    dt = sol.default_dt()
+    for _ in range(a.warmup):
+        sol.step(dt)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()  # the library launches on this stream
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(a.steps):
+        sol.step(dt)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    st = sol.status()
+    if st["nonfinite"]:
+        raise RuntimeError(f"non-finite values during the benchmark: {st}")
+    npts = n ** 3
+    ms_step = ms / a.steps
+    value = npts * a.steps / (ms / 1e3)
+    launch_s = ms / 1e3 / (a.steps * LAUNCHES_PER_STEP)
+    bytes_launch = BYTES_PER_POINT_STEP / LAUNCHES_PER_STEP * npts
+    achieved = bytes_launch / launch_s / 1e9
+    fl = flops_per_point_step()
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "k_bssn_stage", "avg_launch_ms": round(launch_s * 1e3, 4),
+            "fp64_tflops_algorithmic": round(fl * npts * a.steps / (ms / 1e3) / 1e12, 2),
+            "fp64_frac": round(fl * npts * a.steps / (ms / 1e3) / 1e12 / FP64_PEAK_TFLOPS, 4)}
+    out = {"metric": METRIC, "value": value, "unit": "point-updates/s", "n_gpus": 1, "steps": a.steps,
+           "warmup": a.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"BSSN + radiation fluid (P = rho/3) classic RK4, {n}^3 periodic grid, L = 16/H0, "
+                                  f"Gaussian zeta mu = 0.6 sigma = 2.0, CFL 0.25, KO eps 0.1",
+                      "grid": n, "dt": dt, "parallelism": "single GPU"},
+           "roofline": roof}
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(a.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

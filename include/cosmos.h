@@ -1,0 +1,169 @@
+/*
+ * cosmos.h -- C ABI of the MI355X (gfx950) library for the COSMOS evolution
+ * hot path: the 3+1 Einstein equations in a BSSN (chi) form coupled to a
+ * radiation fluid, on a periodic uniform Cartesian grid, in FP64.
+ *
+ * Paper passages the operations follow (the paper's sections; its displayed
+ * equations are unnumbered):
+ *   - "Physical system settings": Einstein equations G = 8 pi T with the
+ *     perfect-fluid stress tensor T = (rho + P) u u + P g, linear equation of
+ *     state P = w rho and the fluid equation of motion div T = 0, rewritten in
+ *     the textbook 3+1 form; the initial-data paragraph (long-wavelength
+ *     growing mode characterised by the curvature perturbation zeta(x), fluid
+ *     distribution chosen so that the constraints hold, no elliptic solver);
+ *   - "Statement of need" / "Examples": a box of size L.
+ * The discretisation (4th-order centred differences, lopsided shift
+ * advection, Kreiss-Oliger dissipation, periodic ghost zones of width 3,
+ * classic RK4) is not fixed by the paper; see the per-function notes.
+ *
+ * Conventions shared by every entry point
+ *   - State layout: 25 FP64 fields, structure of arrays, u[f][k][j][i] with
+ *     i (x) fastest; field stride n0*n1*n2 values. Field order (enum
+ *     cosmos_field): chi, gt_xx, gt_xy, gt_xz, gt_yy, gt_yz, gt_zz, K,
+ *     At_xx..At_zz, Gt^x, Gt^y, Gt^z, alpha, beta^x, beta^y, beta^z,
+ *     Et = chi^(-3/2) E, St_i = chi^(-3/2) S_i.
+ *   - Grid: periodic, vertex centred, x_i = -L/2 + i*h with h = L/n per axis;
+ *     point (n0/2, n1/2, n2/2) is the centre. n >= 8 on every axis.
+ *   - Memory: every pointer argument named u, dudt, lam*, du0, norms_dev,
+ *     H_out, M_out, ws or arena is DEVICE memory owned by the caller and must
+ *     be 8-byte aligned (ws and arena 256-byte aligned). The library never
+ *     allocates, frees or retains caller memory. Descriptor structs are HOST
+ *     memory, read during the call only.
+ *   - Streams: `stream` is a hipStream_t passed as void* (NULL = default
+ *     stream). Every call validates its arguments synchronously and returns a
+ *     status; the work itself is enqueued asynchronously on `stream`.
+ *   - Errors: a negative return value is a cosmos_status_code; the reason is
+ *     available from cosmos_last_error() (thread local). Data-dependent
+ *     failures found on the device (non-finite values, fluid-recovery
+ *     failures, lapse collapse) are counted in the workspace and read with
+ *     cosmos_status(), which synchronises the stream.
+ *   - Threading: calls are re-entrant across host threads and streams as long
+ *     as concurrent calls use distinct workspaces.
+ */
+#ifndef COSMOS_H
+#define COSMOS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define COSMOS_NFIELDS 25
+#define COSMOS_ABI_VERSION 1
+
+enum cosmos_status_code {
+  COSMOS_OK = 0,
+  COSMOS_EINVAL = -1,      /* invalid argument (null/misaligned pointer, n < 8, L <= 0, dt <= 0, small workspace) */
+  COSMOS_EHIP = -2,        /* a HIP runtime call failed */
+  COSMOS_ENOMEM = -3,      /* size overflow */
+  COSMOS_ENONFINITE = -4,  /* returned by cosmos_status_check when non-finite values were seen */
+  COSMOS_EPRIM = -5,       /* returned by cosmos_status_check when the fluid recovery failed */
+  COSMOS_EUNSUPPORTED = -6 /* option not implemented (e.g. an unknown fluid scheme) */
+};
+
+enum cosmos_field {
+  COSMOS_CHI = 0, COSMOS_GT = 1, COSMOS_TRK = 7, COSMOS_AT = 8, COSMOS_GAM = 14,
+  COSMOS_ALPHA = 17, COSMOS_BETA = 18, COSMOS_ET = 21, COSMOS_ST = 22
+};
+
+/* Periodic box: n[a] points and length L[a] along axis a (x, y, z). */
+typedef struct {
+  int32_t n[3];
+  double L[3];
+} cosmos_grid;
+
+/* Evolution parameters.
+ *   w        equation of state P = w rho ("Physical system settings"); 1/3 for radiation
+ *   H0       Hubble rate of the background at t = 0 (units: lengths in 1/H0)
+ *   eta      damping of the Gamma-driver shift condition
+ *   ko_eps   Kreiss-Oliger dissipation strength (6th difference / 64 / h)
+ *   lapse_bg 1: d_t alpha = beta.grad alpha - 2 alpha (K - K_bg(t)), K_bg = -3 H0 / (1 + 2 H0 t),
+ *            which keeps alpha = 1 on the radiation background; 0: plain 1+log (K_bg = 0)
+ *   evolve_shift 1: d_t beta^i = beta.grad beta^i + 3/4 Gt^i - eta beta^i; 0: shift frozen
+ *   fluid_scheme 0: centred 4th-order flux divergence (the only scheme implemented)
+ *   alpha_collapse  a point with alpha below this value after a step counts as collapsed (0: off) */
+typedef struct {
+  double w, H0, eta, ko_eps;
+  int32_t lapse_bg, evolve_shift, fluid_scheme, reserved;
+  double alpha_collapse;
+} cosmos_params;
+
+/* Initial data (paper: "Physical system settings", initial-data paragraph).
+ * zeta profile: 0 = Gaussian mu exp(-r^2 / 2 sigma^2) about `center`, 1 = single mode
+ * mu sin(2 pi x / L_x), 2 = Gaussian in s_a = (L_a / pi) sin(pi x_a / L_a) (smooth, periodic).
+ * density_mode: 0 = energy density from the Hamiltonian constraint, E = (R + 2/3 K^2) / 16 pi;
+ *               1 = uniform E = 3 H0^2 / 8 pi (constraint violating; for experiments).
+ * noise_amp A > 0 multiplies E by (1 + A xi_p), xi_p uniform in [-1, 1) from the counter-based
+ * SplitMix64 generator (Steele, Lea & Flood 2014): xi_p = 2 (SM64(seed, p) >> 11) 2^-53 - 1,
+ * SM64(seed, p) = the (p+1)-th output of SplitMix64 started at `seed`, p = i + n0 (j + n1 k). */
+typedef struct {
+  double mu, sigma, center[3], noise_amp;
+  uint64_t seed;
+  int32_t profile, density_mode;
+} cosmos_init;
+
+/* Bytes of device workspace needed by cosmos_rhs / cosmos_rk4_step / cosmos_constraints /
+ * cosmos_adjoint_step on this grid (3 state-sized stage buffers, the status counters and the
+ * reduction and adjoint scratch). Returns 0 for an invalid grid. */
+size_t cosmos_workspace_bytes(const cosmos_grid* grid);
+
+/* Zero the status counters held in the workspace (asynchronous). */
+int cosmos_status_reset(void* ws, void* stream);
+
+/* Synchronise `stream` and copy the status counters to host out[4]:
+ * out[0] points with a non-finite value seen after an RK4 step or in cosmos_constraints,
+ * out[1] fluid-recovery failures (E <= 0 or negative discriminant; the recovery then uses
+ *        P = 0, v = 0, respectively a clamped discriminant), out[2] points with
+ *        alpha < alpha_collapse after a step, out[3] RK4 steps taken since the last reset. */
+int cosmos_status(void* ws, void* stream, int64_t out[4]);
+
+/* Initial data: fills u (25 * N3 values) with the leading-order long-wavelength growing mode of
+ * a curvature perturbation zeta on the radiation FLRW background: chi = e^{-2 zeta}, gt = delta,
+ * K = -3 H0, At = 0, Gt = 0, alpha = 1, beta = 0, fluid at rest, E from the Hamiltonian
+ * constraint (no elliptic solve), Et = chi^(-3/2) E. */
+int cosmos_init_fields(const cosmos_grid* grid, const cosmos_params* params, const cosmos_init* init,
+                       double* u, void* stream);
+
+/* d u0 / d theta for theta = mu (which = 0) or sigma (which = 1): derivative of the initial
+ * data above with respect to the perturbation amplitude or width (du0: 25 * N3 values). */
+int cosmos_init_tangent(const cosmos_grid* grid, const cosmos_params* params, const cosmos_init* init,
+                        int which, double* du0, void* stream);
+
+/* Discrete right-hand side du/dt at time t (dudt: 25 * N3 values, must not alias u):
+ * BSSN chi-form evolution equations with 1+log lapse and Gamma-driver shift, perfect-fluid
+ * sources and conservative fluid equations (Et, St_i) with a centred flux divergence, all
+ * derivatives by 4th-order centred differences, shift advection beta^k d_k by lopsided
+ * radius-3 stencils chosen by the sign of beta^k, plus Kreiss-Oliger dissipation on every
+ * evolved field; periodic ghost zones of width 3. ws is used for the status counters. */
+int cosmos_rhs(const cosmos_grid* grid, const cosmos_params* params, double t, const double* u,
+               double* dudt, void* ws, void* stream);
+
+/* One classic RK4 step of size dt from time t, in place on u:
+ * u <- u + dt/6 (k1 + 2 k2 + 2 k3 + k4). The stage update is fused into the right-hand-side
+ * kernels (k is never stored): 4 launches, 3 state-sized buffers in ws. */
+int cosmos_rk4_step(const cosmos_grid* grid, const cosmos_params* params, double t, double dt,
+                    double* u, void* ws, void* stream);
+
+/* Hamiltonian and momentum constraints of u and their grid norms:
+ *   H   = R + 2/3 K^2 - At_ij At^ij - 16 pi E
+ *   M_i = gt^jk (d_j At_ki - Gt^l_jk At_li - Gt^l_ji At_kl) - 3/(2 chi) At^j_i d_j chi - 2/3 d_i K - 8 pi S_i
+ * norms_dev[8] (device) = { sqrt(mean H^2), max |H|, sqrt(mean |M|^2), max |M|,
+ *   sqrt(mean Hn^2) with Hn = H / (|R| + 2/3 K^2 + At.At + 16 pi |E|) (0 where that is 0),
+ *   number of points with a non-finite state value, H or M, min alpha, argmin alpha (lowest
+ *   linear index among ties) }. H_out (N3) and M_out (3 * N3, component-major) are optional
+ *   (NULL to skip). The reduction is deterministic (fixed order, no floating-point atomics). */
+int cosmos_constraints(const cosmos_grid* grid, const cosmos_params* params, const double* u,
+                       double* norms_dev, double* H_out, double* M_out, void* ws, void* stream);
+
+/* Human-readable reason for the last error on this thread ("" if none). */
+const char* cosmos_last_error(void);
+
+/* COSMOS_ABI_VERSION of the loaded library. */
+int cosmos_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* COSMOS_H */

@@ -1,0 +1,12 @@
+"""MI355X (gfx950) implementation of the COSMOS evolution hot path.
+
+The 3+1 Einstein equations in a BSSN (chi) form coupled to a radiation fluid
+(P = w rho), on a periodic Cartesian grid, in FP64 HIP kernels behind the C ABI
+of include/cosmos.h. This package is the thin Python side: ctypes marshalling
+(``_lib``) and small drivers that own device buffers (``solver``).
+"""
+from ._lib import (COSMOS_EINVAL, COSMOS_EHIP, COSMOS_OK, NFIELDS, CosmosError, cosmos_abi_version,  # noqa: F401
+                   cosmos_adjoint_step, cosmos_adjoint_workspace_bytes, cosmos_constraints, cosmos_init_fields,
+                   cosmos_init_tangent, cosmos_rhs, cosmos_rk4_step, cosmos_status, cosmos_status_reset,
+                   cosmos_workspace_bytes, last_error, make_grid, make_init, make_params, npts)
+from .solver import Solver  # noqa: F401

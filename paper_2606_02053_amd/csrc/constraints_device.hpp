@@ -1,0 +1,214 @@
+// Hamiltonian and momentum constraints (paper, "Physical system settings":
+// the constraint part of the Einstein equations, which the initial data
+// satisfy) and their deterministic grid reductions.
+//   H   = R + 2/3 K^2 - At_ij At^ij - 16 pi E
+//   M_i = gt^jk (d_j At_ki - Gt^l_jk At_li - Gt^l_ji At_kl) - 3/(2 chi) At^j_i d_j chi - 2/3 d_i K - 8 pi S_i
+// Reduction: per-block tree in LDS, then one block folds the block partials in
+// a fixed order -- no floating-point atomics, bitwise reproducible.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "bssn_device.hpp"
+
+namespace cosmos {
+
+// partial record: sum H^2, sum |M|^2, sum Hn^2, max |H|, max |M|, #non-finite, min alpha, argmin alpha
+constexpr int kRedRecord = 8;
+
+__device__ __forceinline__ void constraint_point(const double* __restrict__ U, size_t fs, const Nbr& nb,
+                                                 const DevParams& P, double& H, double M[3], double& Hn,
+                                                 bool& nonfinite) {
+  const int c = nb.base;
+  nonfinite = false;
+  for (int f = 0; f < NF; ++f) nonfinite = nonfinite || !isfinite(ldq(U + (size_t)f * fs, c));
+  const double chi = ldq(U + F_CHI * fs, c);
+  const double K = ldq(U + F_K * fs, c);
+  double gt[6], gi[6], At[6], St[3];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    gt[s] = ldq(U + (F_GT + s) * fs, c);
+    At[s] = ldq(U + (F_AT + s) * fs, c);
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) St[i] = ldq(U + (F_ST + i) * fs, c);
+  inv_sym(gt, gi);
+  Fluid fl;
+  recover(P.w, chi, gi, ldq(U + F_ET * fs, c), St, fl);
+  const double nob[3] = {0.0, 0.0, 0.0};
+
+  double dgt[6][3], Ric[6];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    FieldDerivs d;
+    field_derivs<true, false, false>(U + (F_GT + s) * fs, nb, P, nob, d);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) dgt[s][a] = d.d1[a];
+    Ric[s] = -0.5 * contract_sym(gi, d.d2);
+  }
+  double Gu[3][6], Gd[3];
+  connection_and_quadratic_ricci(dgt, gi, Gu, Gd, Ric);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    FieldDerivs d;
+    field_derivs<false, false, false>(U + (F_GAM + k) * fs, nb, P, nob, d);
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+      const int i = SI(s), j = SJ(s);
+      Ric[s] += 0.5 * (gt[S(k, i)] * d.d1[j] + gt[S(k, j)] * d.d1[i]);
+    }
+  }
+  double dchi[3];
+  {
+    FieldDerivs d;
+    field_derivs<true, false, false>(U + F_CHI * fs, nb, P, nob, d);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) dchi[a] = d.d1[a];
+    ricci_conformal_factor(chi, dchi, d.d2, gt, gi, Gu, Ric);
+  }
+  const double R = chi * contract_sym(gi, Ric);
+
+  double Amix[3][3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) Amix[k][j] = gi[S(k, 0)] * At[S(0, j)] + gi[S(k, 1)] * At[S(1, j)] + gi[S(k, 2)] * At[S(2, j)];
+  double AA = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) AA += Amix[i][j] * Amix[j][i];
+  H = R + (2.0 / 3.0) * K * K - AA - 16.0 * PI_D * fl.E;
+
+  double dK[3];
+  {
+    FieldDerivs d;
+    field_derivs<false, false, false>(U + F_K * fs, nb, P, nob, d);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) dK[a] = d.d1[a];
+  }
+  double dAt[6][3];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    FieldDerivs d;
+    field_derivs<false, false, false>(U + (F_AT + s) * fs, nb, P, nob, d);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) dAt[s][a] = d.d1[a];
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        double term = dAt[S(k, i)][j];
+#pragma unroll
+        for (int l = 0; l < 3; ++l) term -= Gu[l][S(j, k)] * At[S(l, i)] + Gu[l][S(j, i)] * At[S(k, l)];
+        acc += gi[S(j, k)] * term;
+      }
+    acc -= (1.5 / chi) * (Amix[0][i] * dchi[0] + Amix[1][i] * dchi[1] + Amix[2][i] * dchi[2]);
+    acc -= (2.0 / 3.0) * dK[i] + 8.0 * PI_D * fl.S[i];
+    M[i] = acc;
+  }
+  const double den = fabs(R) + (2.0 / 3.0) * K * K + AA + 16.0 * PI_D * fabs(fl.E);
+  Hn = (den > 0.0) ? H / den : 0.0;
+  nonfinite = nonfinite || !isfinite(H) || !isfinite(M[0]) || !isfinite(M[1]) || !isfinite(M[2]);
+}
+
+struct Red {
+  double sH2, sM2, sHn2, mH, mM, nbad, minA, arg;
+};
+
+__device__ __forceinline__ Red red_neutral() { return {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, INFINITY, 1e300}; }
+
+// b follows a in index order; max ignores NaN (keeps the accumulated value);
+// the argmin keeps the lowest index among equal minima.
+__device__ __forceinline__ Red red_combine(const Red& a, const Red& b) {
+  Red r;
+  r.sH2 = a.sH2 + b.sH2;
+  r.sM2 = a.sM2 + b.sM2;
+  r.sHn2 = a.sHn2 + b.sHn2;
+  r.mH = (a.mH < b.mH) ? b.mH : a.mH;
+  r.mM = (a.mM < b.mM) ? b.mM : a.mM;
+  r.nbad = a.nbad + b.nbad;
+  const bool takeb = (b.minA < a.minA) || (b.minA == a.minA && b.arg < a.arg);
+  r.minA = takeb ? b.minA : a.minA;
+  r.arg = takeb ? b.arg : a.arg;
+  return r;
+}
+
+__device__ __forceinline__ void red_store(double* p, const Red& r) {
+  p[0] = r.sH2; p[1] = r.sM2; p[2] = r.sHn2; p[3] = r.mH; p[4] = r.mM; p[5] = r.nbad; p[6] = r.minA; p[7] = r.arg;
+}
+__device__ __forceinline__ Red red_load(const double* p) { return {p[0], p[1], p[2], p[3], p[4], p[5], p[6], p[7]}; }
+
+// Fixed-shape tree over the 256 entries of a block (entry t combines with t + stride).
+__device__ __forceinline__ Red block_tree(Red mine, Red* sh) {
+  const int t = threadIdx.x;
+  sh[t] = mine;
+  __syncthreads();
+  for (int stride = 128; stride > 0; stride >>= 1) {
+    if (t < stride) sh[t] = red_combine(sh[t], sh[t + stride]);
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_constraints(const double* __restrict__ U, size_t fs, DevParams P,
+                                                      double* __restrict__ Hout, double* __restrict__ Mout,
+                                                      double* __restrict__ part) {
+  __shared__ Red sh[256];
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  Red mine = red_neutral();
+  if (p < (int)fs) {
+    const int i = p % P.n[0];
+    const int jk = p / P.n[0];
+    const int j = jk % P.n[1];
+    const int k = jk / P.n[1];
+    Nbr nb;
+    make_nbr(nb, i, j, k, P.n);
+    double H, M[3], Hn;
+    bool bad;
+    constraint_point(U, fs, nb, P, H, M, Hn, bad);
+    const double Mn = sqrt(M[0] * M[0] + M[1] * M[1] + M[2] * M[2]);
+    if (Hout) Hout[p] = H;
+    if (Mout)
+      for (int q = 0; q < 3; ++q) Mout[(size_t)q * fs + p] = M[q];
+    const double aH = fabs(H);
+    mine.sH2 = H * H;
+    mine.sM2 = Mn * Mn;
+    mine.sHn2 = Hn * Hn;
+    mine.mH = (0.0 < aH) ? aH : 0.0;  // NaN never wins
+    mine.mM = (0.0 < Mn) ? Mn : 0.0;
+    mine.nbad = bad ? 1.0 : 0.0;
+    const double a = ldq(U + F_ALP * fs, p);
+    if (a < INFINITY) {
+      mine.minA = a;
+      mine.arg = (double)p;
+    }
+  }
+  const Red r = block_tree(mine, sh);
+  if (threadIdx.x == 0) red_store(part + (size_t)blockIdx.x * kRedRecord, r);
+}
+
+__global__ __launch_bounds__(256) void k_reduce_partials(const double* __restrict__ part, int nblocks, size_t N3,
+                                                          double* __restrict__ norms) {
+  __shared__ Red sh[256];
+  Red acc = red_neutral();
+  for (int b = threadIdx.x; b < nblocks; b += 256) acc = red_combine(acc, red_load(part + (size_t)b * kRedRecord));
+  const Red r = block_tree(acc, sh);
+  if (threadIdx.x == 0) {
+    const double n = (double)N3;
+    norms[0] = sqrt(r.sH2 / n);
+    norms[1] = r.mH;
+    norms[2] = sqrt(r.sM2 / n);
+    norms[3] = r.mM;
+    norms[4] = sqrt(r.sHn2 / n);
+    norms[5] = r.nbad;
+    norms[6] = r.minA;
+    norms[7] = (r.arg < 1e300) ? r.arg : -1.0;
+  }
+}
+
+}  // namespace cosmos

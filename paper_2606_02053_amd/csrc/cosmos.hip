@@ -1,0 +1,290 @@
+// libcosmos: C ABI and gfx950 kernels of the COSMOS evolution hot path.
+// The ABI (argument meaning, layout, ownership, errors) is documented in
+// include/cosmos.h; the physics and stencils in bssn_device.hpp.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "cosmos.h"
+#include "bssn_device.hpp"
+#include "init_device.hpp"
+#include "constraints_device.hpp"
+
+using namespace cosmos;
+
+// ---------------------------------------------------------------- errors
+static thread_local std::string g_last_error;
+
+static int set_error(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                 \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess) return set_error(COSMOS_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+// ---------------------------------------------------------------- workspace layout
+// [status: 8 x int64 | reduction partials | acc | stage A | stage B]
+namespace {
+constexpr size_t kAlign = 256;
+constexpr int kBlock = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  size_t status, partials, acc, A, B, total;
+};
+
+bool grid_ok(const cosmos_grid* g) {
+  if (!g) return false;
+  for (int a = 0; a < 3; ++a)
+    if (g->n[a] < 8 || g->n[a] > 2048 || !(g->L[a] > 0.0) || !std::isfinite(g->L[a])) return false;
+  return (int64_t)g->n[0] * g->n[1] * g->n[2] < (int64_t)1 << 31;
+}
+
+size_t npts(const cosmos_grid* g) { return (size_t)g->n[0] * g->n[1] * g->n[2]; }
+size_t nblocks(const cosmos_grid* g) { return (npts(g) + kBlock - 1) / kBlock; }
+
+Layout layout(const cosmos_grid* g) {
+  Layout L;
+  const size_t state = (size_t)NF * npts(g) * sizeof(double);
+  L.status = 0;
+  L.partials = align_up(8 * sizeof(int64_t));
+  L.acc = align_up(L.partials + nblocks(g) * kRedRecord * sizeof(double));
+  L.A = align_up(L.acc + state);
+  L.B = align_up(L.A + state);
+  L.total = align_up(L.B + state);
+  return L;
+}
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+int check_common(const cosmos_grid* g, const cosmos_params* p) {
+  if (!grid_ok(g)) return set_error(COSMOS_EINVAL, "invalid grid (need 8 <= n <= 2048, L > 0, n0*n1*n2 < 2^31)");
+  if (!p) return set_error(COSMOS_EINVAL, "params is NULL");
+  if (!std::isfinite(p->w) || !std::isfinite(p->H0) || !std::isfinite(p->eta) || !std::isfinite(p->ko_eps) ||
+      !(p->w > 0.0))
+    return set_error(COSMOS_EINVAL, "invalid params (w must be > 0; all values finite)");
+  if (p->fluid_scheme != 0) return set_error(COSMOS_EUNSUPPORTED, "fluid_scheme %d not implemented", p->fluid_scheme);
+  return COSMOS_OK;
+}
+
+int check_state(const void* ptr, const char* name) {
+  if (!ptr) return set_error(COSMOS_EINVAL, "%s is NULL", name);
+  if (!aligned(ptr, 8)) return set_error(COSMOS_EINVAL, "%s is not 8-byte aligned", name);
+  return COSMOS_OK;
+}
+
+int check_ws(const cosmos_grid* g, const void* ws) {
+  if (!ws) return set_error(COSMOS_EINVAL, "workspace is NULL");
+  if (!aligned(ws, kAlign)) return set_error(COSMOS_EINVAL, "workspace is not 256-byte aligned");
+  return COSMOS_OK;
+}
+
+DevParams dev_params(const cosmos_grid* g, const cosmos_params* p) {
+  DevParams d;
+  d.w = p->w;
+  d.H0 = p->H0;
+  d.eta = p->eta;
+  d.ko_eps = p->ko_eps;
+  d.alpha_collapse = p->alpha_collapse;
+  d.lapse_bg = p->lapse_bg;
+  d.evolve_shift = p->evolve_shift;
+  double h[3];
+  for (int a = 0; a < 3; ++a) {
+    d.n[a] = g->n[a];
+    h[a] = g->L[a] / g->n[a];
+    d.i12h[a] = 1.0 / (12.0 * h[a]);
+    d.i12h2[a] = 1.0 / (12.0 * h[a] * h[a]);
+    d.iko[a] = p->ko_eps / (64.0 * h[a]);
+  }
+  d.i144[0] = 1.0 / (144.0 * h[0] * h[1]);
+  d.i144[1] = 1.0 / (144.0 * h[0] * h[2]);
+  d.i144[2] = 1.0 / (144.0 * h[1] * h[2]);
+  return d;
+}
+}  // namespace
+
+// ---------------------------------------------------------------- stage kernel
+// One kernel for every use of the right-hand side; `mode` (uniform) selects the epilogue:
+// 0: dudt = f(U)
+// 1: first RK4 stage   acc = U + ca k,  out = U + cn k          (U = u_n)
+// 2: middle stages     acc += ca k,     out = u_n + cn k
+// 3: last stage        out = acc + ca k (out = u_n's buffer), non-finite / collapse counts
+struct StageSink {
+  const double* un;
+  double* acc;
+  double* out;
+  size_t fs;
+  int c, mode;
+  double ca, cn, acol;
+  bool bad = false, coll = false;
+  __device__ __forceinline__ void put(int f, double r) {
+    const size_t fo = (size_t)f * fs;  // uniform: field base offsets live in SGPRs
+    if (mode == 0) {
+      stq(out + fo, c, r);
+    } else if (mode == 1) {
+      const double u0 = ldq(un + fo, c);
+      stq(acc + fo, c, u0 + ca * r);
+      stq(out + fo, c, u0 + cn * r);
+    } else if (mode == 2) {
+      const double u0 = ldq(un + fo, c);
+      stq(acc + fo, c, ldq(acc + fo, c) + ca * r);
+      stq(out + fo, c, u0 + cn * r);
+    } else {
+      const double v = ldq(acc + fo, c) + ca * r;
+      stq(out + fo, c, v);
+      bad = bad || !isfinite(v);
+      if (f == F_ALP) coll = v < acol;
+    }
+  }
+};
+
+__global__ __launch_bounds__(kBlock) void k_bssn_stage(const double* U, const double* un, double* acc, double* out,
+                                                        size_t fs, DevParams P, double t, double ca, double cn,
+                                                        int mode, unsigned long long* status) {
+  const int p = blockIdx.x * kBlock + threadIdx.x;
+  if (p >= (int)fs) return;
+  const int i = p % P.n[0];
+  const int jk = p / P.n[0];
+  const int j = jk % P.n[1];
+  const int k = jk / P.n[1];
+  Nbr nb;
+  make_nbr(nb, i, j, k, P.n);
+  StageSink sink{un, acc, out, fs, p, mode, ca, cn, P.alpha_collapse};
+  bool fail = false;
+  bssn_rhs_stream(U, fs, nb, P, t, sink, fail);
+  if (fail) atomicAdd(&status[1], 1ull);
+  if (mode == 3) {
+    if (sink.bad) atomicAdd(&status[0], 1ull);
+    if (sink.coll) atomicAdd(&status[2], 1ull);
+    if (p == 0) atomicAdd(&status[3], 1ull);
+  }
+}
+
+// ---------------------------------------------------------------- ABI
+extern "C" {
+
+int cosmos_abi_version(void) { return COSMOS_ABI_VERSION; }
+
+const char* cosmos_last_error(void) { return g_last_error.c_str(); }
+
+size_t cosmos_workspace_bytes(const cosmos_grid* grid) {
+  if (!grid_ok(grid)) return 0;
+  return layout(grid).total;
+}
+
+int cosmos_status_reset(void* ws, void* stream) {
+  if (!ws || !aligned(ws, kAlign)) return set_error(COSMOS_EINVAL, "invalid workspace");
+  HIP_TRY(hipMemsetAsync(ws, 0, 8 * sizeof(int64_t), (hipStream_t)stream));
+  return COSMOS_OK;
+}
+
+int cosmos_status(void* ws, void* stream, int64_t out[4]) {
+  if (!ws || !aligned(ws, kAlign) || !out) return set_error(COSMOS_EINVAL, "invalid workspace or output");
+  int64_t h[8];
+  HIP_TRY(hipMemcpyAsync(h, ws, sizeof(h), hipMemcpyDeviceToHost, (hipStream_t)stream));
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  for (int q = 0; q < 4; ++q) out[q] = h[q];
+  return COSMOS_OK;
+}
+
+int cosmos_init_fields(const cosmos_grid* grid, const cosmos_params* params, const cosmos_init* init, double* u,
+                       void* stream) {
+  int rc;
+  if ((rc = check_common(grid, params)) || (rc = check_state(u, "u"))) return rc;
+  if (!init) return set_error(COSMOS_EINVAL, "init is NULL");
+  if (!(init->sigma > 0.0) || init->profile < 0 || init->profile > 2 || init->density_mode < 0 ||
+      init->density_mode > 1)
+    return set_error(COSMOS_EINVAL, "invalid init (sigma > 0, profile 0..2, density_mode 0..1)");
+  InitArgs a = make_init_args(grid, params, init);
+  hipLaunchKernelGGL(k_init, dim3(nblocks(grid)), dim3(kBlock), 0, (hipStream_t)stream, a, u, -1);
+  HIP_TRY(hipGetLastError());
+  return COSMOS_OK;
+}
+
+int cosmos_init_tangent(const cosmos_grid* grid, const cosmos_params* params, const cosmos_init* init, int which,
+                        double* du0, void* stream) {
+  int rc;
+  if ((rc = check_common(grid, params)) || (rc = check_state(du0, "du0"))) return rc;
+  if (!init || which < 0 || which > 1) return set_error(COSMOS_EINVAL, "init is NULL or which not in {0, 1}");
+  if (!(init->sigma > 0.0) || init->profile < 0 || init->profile > 2 || init->density_mode < 0 ||
+      init->density_mode > 1)
+    return set_error(COSMOS_EINVAL, "invalid init (sigma > 0, profile 0..2, density_mode 0..1)");
+  InitArgs a = make_init_args(grid, params, init);
+  hipLaunchKernelGGL(k_init, dim3(nblocks(grid)), dim3(kBlock), 0, (hipStream_t)stream, a, du0, which);
+  HIP_TRY(hipGetLastError());
+  return COSMOS_OK;
+}
+
+int cosmos_rhs(const cosmos_grid* grid, const cosmos_params* params, double t, const double* u, double* dudt,
+               void* ws, void* stream) {
+  int rc;
+  if ((rc = check_common(grid, params)) || (rc = check_state(u, "u")) || (rc = check_state(dudt, "dudt")) ||
+      (rc = check_ws(grid, ws)))
+    return rc;
+  if (u == dudt) return set_error(COSMOS_EINVAL, "dudt must not alias u");
+  if (!std::isfinite(t)) return set_error(COSMOS_EINVAL, "t is not finite");
+  const DevParams P = dev_params(grid, params);
+  auto* status = (unsigned long long*)ws;
+  hipLaunchKernelGGL(k_bssn_stage, dim3(nblocks(grid)), dim3(kBlock), 0, (hipStream_t)stream, u, nullptr, nullptr,
+                     dudt, npts(grid), P, t, 0.0, 0.0, 0, status);
+  HIP_TRY(hipGetLastError());
+  return COSMOS_OK;
+}
+
+int cosmos_rk4_step(const cosmos_grid* grid, const cosmos_params* params, double t, double dt, double* u, void* ws,
+                    void* stream) {
+  int rc;
+  if ((rc = check_common(grid, params)) || (rc = check_state(u, "u")) || (rc = check_ws(grid, ws))) return rc;
+  if (!(dt > 0.0) || !std::isfinite(dt) || !std::isfinite(t)) return set_error(COSMOS_EINVAL, "dt must be > 0, t finite");
+  const Layout L = layout(grid);
+  char* w = (char*)ws;
+  double* acc = (double*)(w + L.acc);
+  double* A = (double*)(w + L.A);
+  double* B = (double*)(w + L.B);
+  auto* status = (unsigned long long*)(w + L.status);
+  const DevParams P = dev_params(grid, params);
+  const size_t fs = npts(grid);
+  const dim3 gdim(nblocks(grid)), bdim(kBlock);
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_bssn_stage, gdim, bdim, 0, s, u, u, acc, A, fs, P, t, dt / 6.0, dt / 2.0, 1, status);
+  hipLaunchKernelGGL(k_bssn_stage, gdim, bdim, 0, s, A, u, acc, B, fs, P, t + dt / 2.0, dt / 3.0, dt / 2.0, 2, status);
+  hipLaunchKernelGGL(k_bssn_stage, gdim, bdim, 0, s, B, u, acc, A, fs, P, t + dt / 2.0, dt / 3.0, dt, 2, status);
+  hipLaunchKernelGGL(k_bssn_stage, gdim, bdim, 0, s, A, nullptr, acc, u, fs, P, t + dt, dt / 6.0, 0.0, 3, status);
+  HIP_TRY(hipGetLastError());
+  return COSMOS_OK;
+}
+
+int cosmos_constraints(const cosmos_grid* grid, const cosmos_params* params, const double* u, double* norms_dev,
+                       double* H_out, double* M_out, void* ws, void* stream) {
+  int rc;
+  if ((rc = check_common(grid, params)) || (rc = check_state(u, "u")) || (rc = check_state(norms_dev, "norms_dev")) ||
+      (rc = check_ws(grid, ws)))
+    return rc;
+  if ((H_out && !aligned(H_out, 8)) || (M_out && !aligned(M_out, 8)))
+    return set_error(COSMOS_EINVAL, "H_out / M_out not 8-byte aligned");
+  const Layout L = layout(grid);
+  double* part = (double*)((char*)ws + L.partials);
+  const DevParams P = dev_params(grid, params);
+  const size_t nb = nblocks(grid);
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_constraints, dim3(nb), dim3(kBlock), 0, s, u, npts(grid), P, H_out, M_out, part);
+  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kBlock), 0, s, part, (int)nb, npts(grid), norms_dev);
+  HIP_TRY(hipGetLastError());
+  return COSMOS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,143 @@
+// Initial data on the device (paper, "Physical system settings", initial-data
+// paragraph): leading-order long-wavelength growing mode of a curvature
+// perturbation zeta(x) on the radiation FLRW background. gamma_ij =
+// e^{2 zeta} delta_ij (chi = e^{-2 zeta}, gt = delta), K = -3 H0, At = 0,
+// Gt = 0, alpha = 1, beta = 0, fluid at rest, and the energy density fixed by
+// the Hamiltonian constraint, E = (R + 2/3 K^2) / 16 pi with
+// R = -e^{-2 zeta} (4 lap zeta + 2 |grad zeta|^2) -- no elliptic solve.
+//
+// The same kernel also gives d u0 / d mu and d u0 / d sigma: it evaluates the
+// closed form on value-tangent pairs (Tan) seeded in the chosen parameter.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "bssn_device.hpp"
+
+namespace cosmos {
+
+struct InitArgs {
+  int n[3];
+  double L[3], h[3];
+  double H0;
+  double mu, sigma, center[3], noise;
+  uint64_t seed;
+  int profile, density_mode;
+};
+
+inline InitArgs make_init_args(const cosmos_grid* g, const cosmos_params* p, const cosmos_init* in) {
+  InitArgs a;
+  for (int d = 0; d < 3; ++d) {
+    a.n[d] = g->n[d];
+    a.L[d] = g->L[d];
+    a.h[d] = g->L[d] / g->n[d];
+    a.center[d] = in->center[d];
+  }
+  a.H0 = p->H0;
+  a.mu = in->mu;
+  a.sigma = in->sigma;
+  a.noise = in->noise_amp;
+  a.seed = in->seed;
+  a.profile = in->profile;
+  a.density_mode = in->density_mode;
+  return a;
+}
+
+// value + tangent
+struct Tan {
+  double v, d;
+};
+__device__ __forceinline__ Tan operator+(Tan a, Tan b) { return {a.v + b.v, a.d + b.d}; }
+__device__ __forceinline__ Tan operator-(Tan a, Tan b) { return {a.v - b.v, a.d - b.d}; }
+__device__ __forceinline__ Tan operator*(Tan a, Tan b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+__device__ __forceinline__ Tan operator*(double s, Tan a) { return {s * a.v, s * a.d}; }
+__device__ __forceinline__ Tan operator/(Tan a, Tan b) {
+  const double q = a.v / b.v;
+  return {q, (a.d - q * b.d) / b.v};
+}
+__device__ __forceinline__ Tan texp(Tan a) {
+  const double e = exp(a.v);
+  return {e, e * a.d};
+}
+__device__ __forceinline__ Tan tsqrt(Tan a) {
+  const double r = sqrt(a.v);
+  return {r, a.d / (2.0 * r)};
+}
+__device__ __forceinline__ Tan tc(double x) { return {x, 0.0}; }
+
+// SplitMix64 (Steele, Lea & Flood 2014) used as a counter-based generator:
+// the (p+1)-th output of the sequence started from `seed`.
+__device__ __forceinline__ uint64_t sm64(uint64_t seed, uint64_t p) {
+  uint64_t z = seed + (p + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// which = -1: write the initial data; 0 / 1: write its derivative in mu / sigma.
+__global__ __launch_bounds__(256) void k_init(InitArgs a, double* __restrict__ u, int which) {
+  const size_t N3 = (size_t)a.n[0] * a.n[1] * a.n[2];
+  const size_t p = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= N3) return;
+  const int i = (int)(p % a.n[0]);
+  const int j = (int)((p / a.n[0]) % a.n[1]);
+  const int k = (int)(p / ((size_t)a.n[0] * a.n[1]));
+  const double x[3] = {-0.5 * a.L[0] + i * a.h[0] - a.center[0], -0.5 * a.L[1] + j * a.h[1] - a.center[1],
+                       -0.5 * a.L[2] + k * a.h[2] - a.center[2]};
+  const Tan mu = {a.mu, which == 0 ? 1.0 : 0.0};
+  const Tan sg = {a.sigma, which == 1 ? 1.0 : 0.0};
+  Tan zeta, lap, grad2;
+  if (a.profile == 0) {  // Gaussian
+    const double r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+    const Tan s2 = sg * sg;
+    zeta = mu * texp(tc(-r2) / (2.0 * s2));
+    lap = zeta * (tc(r2) / (s2 * s2) - tc(3.0) / s2);
+    grad2 = zeta * zeta * tc(r2) / (s2 * s2);
+  } else if (a.profile == 1) {  // single sinusoidal mode along x
+    const double kx = 2.0 * PI_D / a.L[0];
+    const double sn = sin(kx * x[0]), cs = cos(kx * x[0]);
+    zeta = mu * tc(sn);
+    lap = tc(-kx * kx) * zeta;
+    grad2 = mu * mu * tc(kx * kx * cs * cs);
+  } else {  // Gaussian in s_a = (L_a / pi) sin(pi x_a / L_a)
+    const Tan s2 = sg * sg;
+    double sa[3], ca[3], kk[3], q2 = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      kk[d] = PI_D / a.L[d];
+      sa[d] = sin(kk[d] * x[d]) / kk[d];
+      ca[d] = cos(kk[d] * x[d]);
+      q2 += sa[d] * sa[d];
+    }
+    zeta = mu * texp(tc(-q2) / (2.0 * s2));
+    Tan l = tc(0.0), gg = tc(0.0);
+    for (int d = 0; d < 3; ++d) {
+      // d_a zeta = -zeta s c / sigma^2;  d_a^2 zeta = zeta (s c)^2 / sigma^4 - zeta (c^2 - k^2 s^2) / sigma^2
+      const double sc = sa[d] * ca[d];
+      l = l + zeta * tc(sc * sc) / (s2 * s2) - zeta * tc(ca[d] * ca[d] - kk[d] * kk[d] * sa[d] * sa[d]) / s2;
+      gg = gg + zeta * zeta * tc(sc * sc) / (s2 * s2);
+    }
+    lap = l;
+    grad2 = gg;
+  }
+  const Tan chi = texp(-2.0 * zeta);
+  const Tan R = tc(0.0) - chi * (4.0 * lap + 2.0 * grad2);
+  const double K = -3.0 * a.H0;
+  Tan E = (a.density_mode == 0) ? (R + tc((2.0 / 3.0) * K * K)) / tc(16.0 * PI_D)
+                                : tc(3.0 * a.H0 * a.H0 / (8.0 * PI_D));
+  if (a.noise != 0.0) {
+    const double xi = 2.0 * ((double)(sm64(a.seed, p) >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
+    E = E * tc(1.0 + a.noise * xi);
+  }
+  const Tan Et = E / (chi * tsqrt(chi));
+  const bool tangent = which >= 0;
+  double out[NF];
+  for (int f = 0; f < NF; ++f) out[f] = 0.0;
+  out[F_CHI] = tangent ? chi.d : chi.v;
+  out[F_K] = tangent ? 0.0 : K;
+  out[F_ALP] = tangent ? 0.0 : 1.0;
+  if (!tangent) out[F_GT + 0] = out[F_GT + 3] = out[F_GT + 5] = 1.0;
+  out[F_ET] = tangent ? Et.d : Et.v;
+  for (int f = 0; f < NF; ++f) u[(size_t)f * N3 + p] = out[f];
+}
+
+}  // namespace cosmos

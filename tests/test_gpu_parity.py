@@ -1,0 +1,216 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Metric (per field f): ||gpu_f - oracle_f||_inf / max(||oracle_f||_inf, 1e-3),
+maximised over the 25 fields; the floor covers fields that are identically
+zero (shift, traceless curvature, connection functions, fluid momentum at
+t = 0). Bars: 1e-11 for one right-hand side and one RK4 step, 1e-9 after 100
+steps. Integer outputs (status counters, argmin) are compared exactly.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from tests.inputs import fuzz_state, sample_points
+
+pytestmark = pytest.mark.gpu
+
+
+def err_fields(gpu, ref):
+    gpu = np.asarray(gpu).reshape(25, -1)
+    ref = np.asarray(ref).reshape(25, -1)
+    d = np.abs(gpu - ref).max(axis=1)
+    s = np.maximum(np.abs(ref).max(axis=1), 1e-3)
+    return (d / s).max(), d / s
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2606_02053_amd as P
+    assert torch.cuda.is_available()
+    return P
+
+
+def mk(P, orc, n, L, **kw):
+    s = orc.Setup(n=n, L=L, **kw)
+    solver = P.Solver(n, L, P.make_params(**{k: v for k, v in kw.items()}))
+    return s, solver
+
+
+def to_dev(u):
+    return torch.from_numpy(np.ascontiguousarray(u)).cuda()
+
+
+@pytest.mark.parametrize("n,L", [((8, 8, 8), (2.4, 2.4, 2.4)), ((12, 16, 10), (3.0, 3.5, 2.5)),
+                                 ((32, 32, 32), (10.0, 10.0, 10.0))])
+def test_rhs_fuzz(P, orc, n, L):
+    s, sol = mk(P, orc, n, L)
+    u = fuzz_state(n, seed=101)
+    sol.set_state(to_dev(u))
+    for t in (0.0, 0.37):
+        g = sol.rhs(t=t).cpu().numpy()
+        r, _ = orc.rhs(s, u, t=t, parallel=True)
+        e, per = err_fields(g, r)
+        assert e < 1e-11, per
+
+
+def test_rhs_fuzz_options(P, orc):
+    n, L = (12, 10, 14), (2.5, 2.0, 3.0)
+    for kw in (dict(lapse_bg=0), dict(evolve_shift=0), dict(ko_eps=0.0), dict(w=0.2, eta=2.0, H0=0.5)):
+        s, sol = mk(P, orc, n, L, **kw)
+        u = fuzz_state(n, seed=7)
+        sol.set_state(to_dev(u))
+        g = sol.rhs(t=0.2).cpu().numpy()
+        r, _ = orc.rhs(s, u, t=0.2)
+        e, per = err_fields(g, r)
+        assert e < 1e-11, (kw, per)
+
+
+@pytest.mark.parametrize("profile,noise", [(0, 1e-6), (1, 0.0), (2, 0.0)])
+def test_init_parity(P, orc, profile, noise):
+    n, L = (16, 12, 20), (10.0, 8.0, 12.0)
+    s, sol = mk(P, orc, n, L)
+    ini = dict(mu=0.3, sigma=1.2, noise_amp=noise, seed=2606, profile=profile, center=(0.1, -0.2, 0.3))
+    g = sol.init(**ini).cpu().numpy()
+    r = orc.init_fields(s, orc.Init(**ini))
+    e, per = err_fields(g, r)
+    assert e < 1e-13, per
+    for which in (0, 1):
+        du = torch.empty_like(sol.u)
+        P.cosmos_init_tangent(sol.grid, sol.params, P.make_init(**ini), which, du)
+        rt = orc.init_tangent(s, orc.Init(**ini), which)
+        e, per = err_fields(du.cpu().numpy(), rt)
+        assert e < 1e-12, (which, per)
+
+
+def test_rk4_one_step_fuzz(P, orc):
+    n, L = (16, 12, 14), (3.0, 2.5, 2.8)
+    s, sol = mk(P, orc, n, L)
+    u = fuzz_state(n, seed=5)
+    sol.set_state(to_dev(u), t=0.1)
+    dt = 0.25 * min(s.h)
+    sol.step(dt)
+    r, _ = orc.rk4(s, u, 0.1, dt, 1, parallel=True)
+    e, per = err_fields(sol.u.cpu().numpy(), r)
+    assert e < 1e-11, per
+
+
+def c1_setup(P, orc):
+    """32^3 periodic box of side 10, Gaussian zeta (mu 0.1, sigma 1), 1e-6 white noise on E."""
+    n, L = (32, 32, 32), (10.0, 10.0, 10.0)
+    s, sol = mk(P, orc, n, L)
+    ini = dict(mu=0.1, sigma=1.0, noise_amp=1e-6, seed=2606)
+    return s, sol, ini
+
+
+def test_c1_ten_steps_and_hundred(P, orc):
+    s, sol, ini = c1_setup(P, orc)
+    sol.init(**ini)
+    u0 = orc.init_fields(s, orc.Init(**ini))
+    dt = 0.25 * s.h[0]
+    sol.step(dt)
+    r1, _ = orc.rk4(s, u0, 0.0, dt, 1, parallel=True)
+    e1, per = err_fields(sol.u.cpu().numpy(), r1)
+    assert e1 < 1e-11, per
+    sol.run(9, dt)
+    r10, _ = orc.rk4(s, r1, dt, dt, 9, parallel=True)
+    e10, per = err_fields(sol.u.cpu().numpy(), r10)
+    assert e10 < 1e-10, per
+    sol.run(90, dt)
+    r100, _ = orc.rk4(s, r10, 10 * dt, dt, 90, parallel=True)
+    e100, per = err_fields(sol.u.cpu().numpy(), r100)
+    print(f"C1 parity: 1 step {e1:.3e}, 10 steps {e10:.3e}, 100 steps {e100:.3e}")
+    assert e100 < 1e-9, per
+    st = sol.status()
+    assert st["steps"] == 100 and st["nonfinite"] == 0 and st["prim_fail"] == 0
+
+
+def test_constraints_parity(P, orc):
+    n, L = (16, 20, 12), (4.0, 5.0, 3.0)
+    s, sol = mk(P, orc, n, L)
+    u = fuzz_state(n, seed=9)
+    sol.set_state(to_dev(u))
+    norms, H, M = sol.constraints(want_fields=True)
+    rn, rH, rM = orc.constraints(s, u, want_fields=True)
+    norms = norms.numpy()
+    assert np.allclose(norms[:5], rn[:5], rtol=1e-12, atol=0), (norms, rn)
+    assert norms[5] == rn[5] == 0 and norms[6] == rn[6] and norms[7] == rn[7]
+    Hs = np.abs(rH).max()
+    assert np.abs(H.cpu().numpy() - rH).max() < 1e-12 * Hs
+    Ms = np.abs(rM).max()
+    assert np.abs(M.cpu().numpy() - rM).max() < 1e-12 * Ms
+    # initial data: momentum constraint exactly zero, H at truncation level
+    s2, sol2, ini = c1_setup(P, orc)
+    sol2.init(**ini)
+    g = sol2.constraints().numpy()
+    r = orc.constraints(s2, orc.init_fields(s2, orc.Init(**ini)))
+    assert g[3] == 0.0 and r[3] == 0.0
+    assert g[0] == pytest.approx(r[0], rel=1e-11)
+    assert g[7] == r[7] and g[6] == r[6]
+
+
+def test_determinism_bitwise(P, orc):
+    s, sol, ini = c1_setup(P, orc)
+    outs = []
+    for _ in range(2):
+        sol.init(**ini)
+        sol.run(5)
+        outs.append((sol.u.clone(), sol.constraints().clone()))
+    assert torch.equal(outs[0][0], outs[1][0])
+    assert torch.equal(outs[0][1], outs[1][1])
+
+
+def test_status_counts_match_oracle(P, orc):
+    n, L = (12, 12, 12), (3.0, 3.0, 3.0)
+    s, sol = mk(P, orc, n, L)
+    u = fuzz_state(n, seed=3)
+    # invalid fluid states: negative energy at two points, superluminal momentum at one
+    u[orc.ET, 2, 3, 4] = -0.5
+    u[orc.ET, 7, 1, 0] = -0.1
+    u[orc.ST, 5, 5, 5] = 50.0
+    sol.set_state(to_dev(u))
+    P.cosmos_status_reset(sol.ws)
+    dt = 0.25 * min(s.h)
+    sol.step(dt)
+    st = sol.status()
+    _, pf = orc.rk4(s, u, 0.0, dt, 1)
+    assert st["prim_fail"] == pf and pf > 0
+    # a non-finite value spreads through the stencils; count points after one step
+    v = fuzz_state(n, seed=4)
+    v[orc.TRK, 6, 6, 6] = np.nan
+    sol.set_state(to_dev(v))
+    P.cosmos_status_reset(sol.ws)
+    sol.step(dt)
+    st = sol.status()
+    r, _ = orc.rk4(s, v, 0.0, dt, 1)
+    bad = int((~np.isfinite(r.reshape(25, -1))).any(axis=0).sum())
+    assert st["nonfinite"] == bad and bad > 0
+    norms = sol.constraints().numpy()
+    rn = orc.constraints(s, r)
+    assert norms[5] == rn[5]
+
+
+def test_bench_configuration_sampled(P, orc):
+    """256^3, L = 16, Gaussian zeta mu = 0.6, sigma = 2: initial data, one RHS and one RK4 step
+    in the launch configuration the benchmark times, checked at sampled points."""
+    n, L = (256, 256, 256), (16.0, 16.0, 16.0)
+    s, sol = mk(P, orc, n, L)
+    ini = dict(mu=0.6, sigma=2.0)
+    sol.init(**ini)
+    pts = sample_points(n, 24, seed=1)
+    idx = torch.from_numpy(pts).cuda()
+    g0 = sol.u.reshape(25, -1)[:, idx].T.cpu().numpy()
+    r0 = orc.init_at_points(s, orc.Init(**ini), pts)
+    assert np.abs(g0 - r0).max() < 1e-13 * np.abs(r0).max()
+    u0 = orc.init_fields(s, orc.Init(**ini))
+    rhs = sol.rhs(t=0.0).reshape(25, -1)[:, idx].T.cpu().numpy()
+    rr = orc.rhs_at_points(s, u0, pts, t=0.0)
+    scale = np.maximum(np.abs(rr).max(axis=0), 1e-3)
+    assert (np.abs(rhs - rr).max(axis=0) / scale).max() < 1e-11
+    dt = 0.25 * s.h[0]
+    sol.step(dt)
+    g1 = sol.u.reshape(25, -1)[:, idx[:8]].T.cpu().numpy()
+    r1 = orc.rk4_at_points(s, u0, pts[:8], 0.0, dt)
+    scale = np.maximum(np.abs(r1).max(axis=0), 1e-3)
+    assert (np.abs(g1 - r1).max(axis=0) / scale).max() < 1e-11
