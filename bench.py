@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--no-tune", action="store_true", help="use the default tile instead of the autotuned one")
     return ap.parse_args()
 
 
@@ -93,10 +94,15 @@ def main():
         copy_probe()
         return
     import paper_2606_02053_amd as P
+    from paper_2606_02053_amd import autotune
     n, L = a.n, 16.0
     sol = P.Solver(n, L)
     sol.init(mu=0.6, sigma=2.0)
     dt = sol.default_dt()
+    kv, tile, order = 0, (16, 4, 4), 0
+    if not a.no_tune:  # untimed: picks kernel variant and brick (cached per arch and grid)
+        (kv, tile, order), _ = autotune.tune(sol.grid, sol.params, sol.u, dt)
+    sol.params = autotune.with_tile(sol.params, kv, tile, order)
     for _ in range(a.warmup):
         sol.step(dt)
     torch.cuda.synchronize()
@@ -128,7 +134,9 @@ def main():
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"BSSN + radiation fluid (P = rho/3) classic RK4, {n}^3 periodic grid, L = 16/H0, "
                                   f"Gaussian zeta mu = 0.6 sigma = 2.0, CFL 0.25, KO eps 0.1",
-                      "grid": n, "dt": dt, "parallelism": "single GPU"},
+                      "grid": n, "dt": dt, "kernel_variant": "lds-staged" if kv == 0 else "direct",
+                      "tile": list(tile), "tile_order": "xcd" if order == 0 else "linear",
+                      "parallelism": "single GPU"},
            "roofline": roof}
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(a.cpu_steps)

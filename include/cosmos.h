@@ -83,11 +83,18 @@ typedef struct {
  *            which keeps alpha = 1 on the radiation background; 0: plain 1+log (K_bg = 0)
  *   evolve_shift 1: d_t beta^i = beta.grad beta^i + 3/4 Gt^i - eta beta^i; 0: shift frozen
  *   fluid_scheme 0: centred 4th-order flux divergence (the only scheme implemented)
- *   alpha_collapse  a point with alpha below this value after a step counts as collapsed (0: off) */
+ *   variant  stage-kernel implementation: 0 = LDS-staged bricks (default; bricks 16x4x4, 16x8x2,
+ *            8x8x4, 8x4x8), 1 = direct loads through the caches (any brick); same results
+ *   alpha_collapse  a point with alpha below this value after a step counts as collapsed (0: off)
+ *   tile_x, tile_y, tile_z  brick owned by one 256-thread workgroup of the stage kernel
+ *            (tile_x * tile_y * tile_z must be 256; all 0 = default 16 x 4 x 4); results do not
+ *            depend on the tile (bitwise), only the speed does
+ *   tile_order 0: XCD-aware brick order (each of the 8 XCDs walks one contiguous slab); 1: linear */
 typedef struct {
   double w, H0, eta, ko_eps;
-  int32_t lapse_bg, evolve_shift, fluid_scheme, reserved;
+  int32_t lapse_bg, evolve_shift, fluid_scheme, variant;
   double alpha_collapse;
+  int32_t tile_x, tile_y, tile_z, tile_order;
 } cosmos_params;
 
 /* Initial data (paper: "Physical system settings", initial-data paragraph).

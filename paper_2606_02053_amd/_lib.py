@@ -32,7 +32,9 @@ class cosmos_grid(ctypes.Structure):
 class cosmos_params(ctypes.Structure):
     _fields_ = [("w", ctypes.c_double), ("H0", ctypes.c_double), ("eta", ctypes.c_double),
                 ("ko_eps", ctypes.c_double), ("lapse_bg", ctypes.c_int32), ("evolve_shift", ctypes.c_int32),
-                ("fluid_scheme", ctypes.c_int32), ("reserved", ctypes.c_int32), ("alpha_collapse", ctypes.c_double)]
+                ("fluid_scheme", ctypes.c_int32), ("variant", ctypes.c_int32), ("alpha_collapse", ctypes.c_double),
+                ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32), ("tile_z", ctypes.c_int32),
+                ("tile_order", ctypes.c_int32)]
 
 
 class cosmos_init(ctypes.Structure):
@@ -122,8 +124,9 @@ def make_grid(n, L) -> cosmos_grid:
 
 
 def make_params(w=1.0 / 3.0, H0=1.0, eta=1.0, ko_eps=0.1, lapse_bg=1, evolve_shift=1, fluid_scheme=0,
-                alpha_collapse=0.0) -> cosmos_params:
-    return cosmos_params(w, H0, eta, ko_eps, lapse_bg, evolve_shift, fluid_scheme, 0, alpha_collapse)
+                alpha_collapse=0.0, tile=(0, 0, 0), tile_order=0, variant=0) -> cosmos_params:
+    return cosmos_params(w, H0, eta, ko_eps, lapse_bg, evolve_shift, fluid_scheme, variant, alpha_collapse,
+                         int(tile[0]), int(tile[1]), int(tile[2]), int(tile_order))
 
 
 def make_init(mu=0.1, sigma=1.0, center=(0.0, 0.0, 0.0), noise_amp=0.0, seed=2606, profile=0,

@@ -49,6 +49,36 @@ struct DevParams {
   double iko[3];    // ko_eps / (64 h_a)
 };
 
+// Brick decomposition of the grid for the stage kernel: a workgroup of
+// bx*by*bz (= 256) threads owns one bx x by x bz brick, one point per thread
+// (x fastest within the brick, so a wave covers whole x-rows). With
+// xcd_order the flat brick sequence is cut into 8 contiguous chunks, chunk q
+// served by the workgroups with blockIdx % 8 == q: the hardware deals
+// consecutive workgroups round-robin to the 8 XCDs, so each XCD then walks one
+// contiguous slab and the stencil halos of a brick are found in its own L2.
+struct Tile {
+  int bx, by, bz;
+  int nbx, nby, nbz;
+  int nbricks, per, xcd_order;
+};
+
+// Maps (blockIdx, threadIdx) to a grid point; false for padding workgroups
+// and for threads beyond the edge of a partial brick.
+__device__ __forceinline__ bool tile_point(const Tile& T, const int n[3], int& i, int& j, int& k) {
+  int brick = blockIdx.x;
+  if (T.xcd_order) brick = (blockIdx.x & 7) * T.per + (blockIdx.x >> 3);
+  if (brick >= T.nbricks) return false;
+  const int bxi = brick % T.nbx;
+  const int byz = brick / T.nbx;
+  const int byi = byz % T.nby;
+  const int bzi = byz / T.nby;
+  const int t = threadIdx.x;
+  i = bxi * T.bx + t % T.bx;
+  j = byi * T.by + (t / T.bx) % T.by;
+  k = bzi * T.bz + t / (T.bx * T.by);
+  return i < n[0] && j < n[1] && k < n[2];
+}
+
 // Linear neighbour offsets of one point on the periodic grid (the ghost-zone
 // fill as an index wrap: valid for |offset| <= 3 < n).
 struct Nbr {
@@ -316,71 +346,121 @@ __device__ __forceinline__ void ricci_conformal_factor(double chi, const double 
 }
 
 // ---------------------------------------------------------------- streaming right-hand side
+// Long-lived per-point intermediates live in an LDS record (slot k of thread t
+// at rec[k * stride + t]: consecutive lanes hit consecutive banks). Each phase
+// reloads what it needs after the phase fence and writes back what later phases
+// use, so the registers hold one phase's working set only.
+enum : int {
+  R_GI = 0,     // 6  conformal inverse metric gt^ij
+  R_E = 6,      // 1  E (normal-observer energy density)
+  R_S = 7,      // 3  S_i
+  R_P = 10,     // 1  pressure
+  R_IX = 11,    // 1  1 / X
+  R_SUP = 12,   // 3  S^i
+  R_DB = 15,    // 9  d_a beta^i at 3 i + a
+  R_RG = 24,    // 3  accumulated Gt^i right-hand side
+  R_RIC = 27,   // 6  R_ij (accumulated)
+  R_SG = 33,    // 3  S^jk d_i gt_jk
+  R_GU = 36,    // 18 Gt^k_ij at 6 k + ij (holds d_a gt_ij at 3 ij + a before the connection phase)
+  R_GD = 54,    // 3  Gt^k computed from the metric
+  R_DCHI = 57,  // 3  d_a chi
+  R_DAL = 60,   // 3  d_a alpha
+  R_X = 63,     // 6  -D_iD_j alpha + alpha (R_ij - 8 pi S_ij)
+  R_D2A = 69,   // 1  D^i D_i alpha
+  R_AUP = 70,   // 6  At^ij
+  R_COUNT = 76
+};
+
+struct Rec {
+  double* p;
+  int stride;
+  __device__ __forceinline__ double& operator[](int k) const { return p[k * stride]; }
+};
+
+// S^jk = S^j S^k / X + P chi gt^jk from the record
+__device__ __forceinline__ double rec_Sjk(const Rec& R, double chi, int s) {
+  return R[R_SUP + SI(s)] * R[R_SUP + SJ(s)] * R[R_IX] + R[R_P] * chi * R[R_GI + s];
+}
+
 // Sink interface: put(f, value) receives the final right-hand side of field f at this point.
 template <class Sink>
-__device__ __forceinline__ void bssn_rhs_stream(const double* U, size_t fs, const Nbr& nb,
-                                                const DevParams& P, double t, Sink& sink, bool& prim_fail) {
+__device__ __forceinline__ void bssn_rhs_stream(const double* U, size_t fs, const Nbr& nb, const DevParams& P,
+                                                double t, const Rec& R, Sink& sink, bool& prim_fail) {
   const int c = nb.base;
-  // ---- point values
+  // centre values kept in registers for the whole evaluation
   const double chi = ldq(U + F_CHI * fs, c);
   const double K = ldq(U + F_K * fs, c);
   const double alpha = ldq(U + F_ALP * fs, c);
-  double gt[6], gi[6], beta[3];
+  double gt[6], beta[3];
 #pragma unroll
   for (int s = 0; s < 6; ++s) gt[s] = ldq(U + (F_GT + s) * fs, c);
 #pragma unroll
   for (int i = 0; i < 3; ++i) beta[i] = ldq(U + (F_BET + i) * fs, c);
-  inv_sym(gt, gi);
 
-  // ---- matter at the point
-  Fluid fl;
+  // ---- inverse metric and matter at the point
   {
-    double St[3];
+    double gi[6], St[3];
+    inv_sym(gt, gi);
 #pragma unroll
     for (int i = 0; i < 3; ++i) St[i] = ldq(U + (F_ST + i) * fs, c);
+    Fluid fl;
     prim_fail = recover(P.w, chi, gi, ldq(U + F_ET * fs, c), St, fl);
-  }
-  // S^jk = S^j S^k / X + P chi gt^jk
-  double Sjk[6];
 #pragma unroll
-  for (int s = 0; s < 6; ++s) Sjk[s] = fl.Sup[SI(s)] * fl.Sup[SJ(s)] * fl.invX + fl.P * chi * gi[s];
+    for (int s = 0; s < 6; ++s) R[R_GI + s] = gi[s];
+    R[R_E] = fl.E;
+    R[R_P] = fl.P;
+    R[R_IX] = fl.invX;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      R[R_S + i] = fl.S[i];
+      R[R_SUP + i] = fl.Sup[i];
+      R[R_RG + i] = 0.0;
+      R[R_SG + i] = 0.0;
+    }
+  }
 
-  COSMOS_PHASE();
-  // ---- shift: first derivatives kept; second derivatives consumed into the Gt^i source
-  double db[3][3];  // db[i][a] = d_a beta^i
-  double rg[3] = {0.0, 0.0, 0.0};
+  // ---- shift: d beta kept; second derivatives consumed into the Gt^i source
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     COSMOS_PHASE();
+    double gi[6];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) gi[s] = R[R_GI + s];
     FieldDerivs d;
     field_derivs<true, true>(U + (F_BET + i) * fs, nb, P, beta, d);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) db[i][a] = d.d1[a];
-    // gt^jk d_j d_k beta^i
-    rg[i] += contract_sym(gi, d.d2);
-    // 1/3 gt^lj d_j d_i beta^i (summed over i as the loop runs)
+    for (int a = 0; a < 3; ++a) R[R_DB + 3 * i + a] = d.d1[a];
+    // gt^jk d_j d_k beta^i  and  1/3 gt^lj d_j d_i beta^i (summed over i as the loop runs)
+    R[R_RG + i] += contract_sym(gi, d.d2);
 #pragma unroll
     for (int l = 0; l < 3; ++l)
-      rg[l] += (gi[S(l, 0)] * d.d2[S(0, i)] + gi[S(l, 1)] * d.d2[S(1, i)] + gi[S(l, 2)] * d.d2[S(2, i)]) * (1.0 / 3.0);
+      R[R_RG + l] += (gi[S(l, 0)] * d.d2[S(0, i)] + gi[S(l, 1)] * d.d2[S(1, i)] + gi[S(l, 2)] * d.d2[S(2, i)]) * (1.0 / 3.0);
     double r = 0.0;
     if (P.evolve_shift) r = d.advko + (0.75 * ldq(U + (F_GAM + i) * fs, c) - P.eta * beta[i]);
     sink.put(F_BET + i, r);
   }
-  const double divb = db[0][0] + db[1][1] + db[2][2];
 
-  COSMOS_PHASE();
-  // ---- conformal metric
-  double dgt[6][3];
-  double Ric[6];
+  // ---- conformal metric: d gt parked in the connection slots, -1/2 gt^lm d_l d_m gt_ij into R_ij
 #pragma unroll
   for (int s = 0; s < 6; ++s) {
     COSMOS_PHASE();
+    double gi[6], db[3][3];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) gi[q] = R[R_GI + q];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) db[q / 3][q % 3] = R[R_DB + q];
     FieldDerivs d;
     field_derivs<true, true>(U + (F_GT + s) * fs, nb, P, beta, d);
+    const double wsym = (s == 0 || s == 3 || s == 5) ? 1.0 : 2.0;
+    const double Sjk = rec_Sjk(R, chi, s);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) dgt[s][a] = d.d1[a];
-    Ric[s] = -0.5 * contract_sym(gi, d.d2);
+    for (int a = 0; a < 3; ++a) {
+      R[R_GU + 3 * s + a] = d.d1[a];
+      R[R_SG + a] += wsym * Sjk * d.d1[a];
+    }
+    R[R_RIC + s] = -0.5 * contract_sym(gi, d.d2);
     const int i = SI(s), j = SJ(s);
+    const double divb = db[0][0] + db[1][1] + db[2][2];
     double r = d.advko;
 #pragma unroll
     for (int k = 0; k < 3; ++k) r += gt[S(i, k)] * db[k][j] + gt[S(j, k)] * db[k][i];
@@ -388,56 +468,79 @@ __device__ __forceinline__ void bssn_rhs_stream(const double* U, size_t fs, cons
     r -= 2.0 * alpha * ldq(U + (F_AT + s) * fs, c);
     sink.put(F_GT + s, r);
   }
-  // fluid geometric source: sg_i = S^jk d_i gt_jk
-  double sg[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    double d[6];
-#pragma unroll
-    for (int s = 0; s < 6; ++s) d[s] = dgt[s][a];
-    sg[a] = (Sjk[0] * d[0] + Sjk[3] * d[3] + Sjk[5] * d[5]) + 2.0 * (Sjk[1] * d[1] + Sjk[2] * d[2] + Sjk[4] * d[4]);
-  }
-  COSMOS_PHASE();
-  // conformal Christoffels and the Ricci terms quadratic in them
-  double Gu[3][6], Gd[3];
-  connection_and_quadratic_ricci(dgt, gi, Gu, Gd, Ric);
 
+  // ---- conformal Christoffels and the Ricci terms quadratic in them
   COSMOS_PHASE();
-  // ---- connection functions: d_j Gt^k into the Ricci tensor; advection kept for later
-  double rgam_adv[3];
+  {
+    double gi[6], dgt[6][3], Gu[3][6], Gd[3], Ric[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      gi[q] = R[R_GI + q];
+      Ric[q] = R[R_RIC + q];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) dgt[q][a] = R[R_GU + 3 * q + a];
+    }
+    connection_and_quadratic_ricci(dgt, gi, Gu, Gd, Ric);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      R[R_RIC + q] = Ric[q];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) R[R_GU + 6 * k + q] = Gu[k][q];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) R[R_GD + k] = Gd[k];
+  }
+
+  // ---- connection functions: d_j Gt^k into R_ij; advection + dissipation into the Gt^k accumulator
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     COSMOS_PHASE();
     double d1[3];
-    rgam_adv[k] = field_advko<true>(U + (F_GAM + k) * fs, nb, P, beta, d1);
+    R[R_RG + k] += field_advko<true>(U + (F_GAM + k) * fs, nb, P, beta, d1);
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
       const int i = SI(s), j = SJ(s);
-      Ric[s] += 0.5 * (gt[S(k, i)] * d1[j] + gt[S(k, j)] * d1[i]);
+      R[R_RIC + s] += 0.5 * (gt[S(k, i)] * d1[j] + gt[S(k, j)] * d1[i]);
     }
   }
 
-  COSMOS_PHASE();
   // ---- conformal factor
-  double dchi[3];
+  COSMOS_PHASE();
   {
+    double gi[6], Gu[3][6], Ric[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      gi[q] = R[R_GI + q];
+      Ric[q] = R[R_RIC + q];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) Gu[k][q] = R[R_GU + 6 * k + q];
+    }
     FieldDerivs d;
     field_derivs<true, true>(U + F_CHI * fs, nb, P, beta, d);
+    ricci_conformal_factor(chi, d.d1, d.d2, gt, gi, Gu, Ric);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) dchi[a] = d.d1[a];
-    ricci_conformal_factor(chi, dchi, d.d2, gt, gi, Gu, Ric);
+    for (int q = 0; q < 6; ++q) R[R_RIC + q] = Ric[q];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) R[R_DCHI + a] = d.d1[a];
+    const double divb = R[R_DB + 0] + R[R_DB + 4] + R[R_DB + 8];
     sink.put(F_CHI, d.advko + (2.0 / 3.0) * chi * (alpha * K - divb));
   }
 
+  // ---- lapse: D_iD_j alpha, its trace, and X_ij = -D_iD_j alpha + alpha (R_ij - 8 pi S_ij)
   COSMOS_PHASE();
-  // ---- lapse
-  double dal[3], D2a;
-  double X[6];  // becomes -D_iD_j alpha + alpha (R_ij - 8 pi S_ij)
   {
+    double gi[6], Gu[3][6], dchi[3];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      gi[q] = R[R_GI + q];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) Gu[k][q] = R[R_GU + 6 * k + q];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) dchi[a] = R[R_DCHI + a];
     FieldDerivs d;
     field_derivs<true, true>(U + F_ALP * fs, nb, P, beta, d);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) dal[a] = d.d1[a];
+    const double* dal = d.d1;
     double cda = 0.0;
 #pragma unroll
     for (int k = 0; k < 3; ++k)
@@ -451,29 +554,34 @@ __device__ __forceinline__ void bssn_rhs_stream(const double* U, size_t fs, cons
       DDa[s] = (d.d2[s] - (Gu[0][s] * dal[0] + Gu[1][s] * dal[1] + Gu[2][s] * dal[2])) +
                ih * ((dchi[i] * dal[j] + dchi[j] * dal[i]) - gt[s] * cda);
     }
-    D2a = chi * contract_sym(gi, DDa);
+    R[R_D2A] = chi * contract_sym(gi, DDa);
     const double Kbg = P.lapse_bg ? -3.0 * P.H0 / (1.0 + 2.0 * P.H0 * t) : 0.0;
     sink.put(F_ALP, d.advko - 2.0 * alpha * (K - Kbg));
     const double ichi = 1.0 / chi;
+    const double ix = R[R_IX], pr = R[R_P];
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
-      const double Sij = fl.S[SI(s)] * fl.S[SJ(s)] * fl.invX + fl.P * gt[s] * ichi;
-      X[s] = -DDa[s] + alpha * (Ric[s] - 8.0 * PI_D * Sij);
+      const double Sij = R[R_S + SI(s)] * R[R_S + SJ(s)] * ix + pr * gt[s] * ichi;
+      R[R_X + s] = -DDa[s] + alpha * (R[R_RIC + s] - 8.0 * PI_D * Sij);
     }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) R[R_DAL + a] = dal[a];
   }
 
+  // ---- trace K: d K feeds the Gt^i source; At^ij, At.At and the K right-hand side
   COSMOS_PHASE();
-  // ---- trace K: its gradient feeds the Gt^i source
   {
+    double gi[6], At[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      gi[q] = R[R_GI + q];
+      At[q] = ldq(U + (F_AT + q) * fs, c);
+    }
     double dK[3];
     const double r_adv = field_advko<true>(U + F_K * fs, nb, P, beta, dK);
 #pragma unroll
     for (int i = 0; i < 3; ++i)
-      rg[i] -= (4.0 / 3.0) * alpha * (gi[S(i, 0)] * dK[0] + gi[S(i, 1)] * dK[1] + gi[S(i, 2)] * dK[2]);
-    // traceless curvature and its contractions
-    double At[6];
-#pragma unroll
-    for (int s = 0; s < 6; ++s) At[s] = ldq(U + (F_AT + s) * fs, c);
+      R[R_RG + i] -= (4.0 / 3.0) * alpha * (gi[S(i, 0)] * dK[0] + gi[S(i, 1)] * dK[1] + gi[S(i, 2)] * dK[2]);
     double Amix[3][3];  // Amix[k][j] = gt^kl At_lj
 #pragma unroll
     for (int k = 0; k < 3; ++k)
@@ -484,87 +592,109 @@ __device__ __forceinline__ void bssn_rhs_stream(const double* U, size_t fs, cons
     for (int s = 0; s < 6; ++s) {
       const int i = SI(s), j = SJ(s);
       Aup[s] = Amix[i][0] * gi[S(0, j)] + Amix[i][1] * gi[S(1, j)] + Amix[i][2] * gi[S(2, j)];
+      R[R_AUP + s] = Aup[s];
     }
     const double AA = contract_sym(At, Aup);
-    const double E = fl.E;
-    const double Str = (fl.Sup[0] * fl.S[0] + fl.Sup[1] * fl.S[1] + fl.Sup[2] * fl.S[2]) * fl.invX + 3.0 * fl.P;
-    sink.put(F_K, r_adv + (-D2a + alpha * (AA + K * K * (1.0 / 3.0)) + 4.0 * PI_D * alpha * (E + Str)));
+    const double Str = (R[R_SUP + 0] * R[R_S + 0] + R[R_SUP + 1] * R[R_S + 1] + R[R_SUP + 2] * R[R_S + 2]) * R[R_IX] +
+                       3.0 * R[R_P];
+    sink.put(F_K, r_adv + (-R[R_D2A] + alpha * (AA + K * K * (1.0 / 3.0)) + 4.0 * PI_D * alpha * (R[R_E] + Str)));
+  }
 
-  COSMOS_PHASE();
-    // At_ij
-    const double trX = contract_sym(gi, X);
+  // ---- traceless extrinsic curvature
 #pragma unroll
-    for (int s = 0; s < 6; ++s) {
-      COSMOS_PHASE();
-      const int i = SI(s), j = SJ(s);
-      double d1[3];
-      double r = field_advko<true>(U + (F_AT + s) * fs, nb, P, beta, d1);
+  for (int s = 0; s < 6; ++s) {
+    COSMOS_PHASE();
+    double gi[6], At[6], X[6], db[3][3];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) r += At[S(i, k)] * db[k][j] + At[S(j, k)] * db[k][i];
-      r -= (2.0 / 3.0) * At[s] * divb;
-      r += chi * (X[s] - gt[s] * trX * (1.0 / 3.0));
-      const double AAij = At[S(i, 0)] * Amix[0][j] + At[S(i, 1)] * Amix[1][j] + At[S(i, 2)] * Amix[2][j];
-      r += alpha * (K * At[s] - 2.0 * AAij);
-      sink.put(F_AT + s, r);
+    for (int q = 0; q < 6; ++q) {
+      gi[q] = R[R_GI + q];
+      At[q] = ldq(U + (F_AT + q) * fs, c);
+      X[q] = R[R_X + q];
     }
-
-  COSMOS_PHASE();
-    // Gt^i
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      double r = rgam_adv[i] + rg[i];
-      r -= Gd[0] * db[i][0] + Gd[1] * db[i][1] + Gd[2] * db[i][2];
-      r += (2.0 / 3.0) * Gd[i] * divb;
-      r -= 2.0 * (Aup[S(i, 0)] * dal[0] + Aup[S(i, 1)] * dal[1] + Aup[S(i, 2)] * dal[2]);
-      double inner = contract_sym(Gu[i], Aup);
-      inner -= (1.5 / chi) * (Aup[S(i, 0)] * dchi[0] + Aup[S(i, 1)] * dchi[1] + Aup[S(i, 2)] * dchi[2]);
-      r += 2.0 * alpha * inner;
-      r -= 16.0 * PI_D * alpha * (gi[S(i, 0)] * fl.S[0] + gi[S(i, 1)] * fl.S[1] + gi[S(i, 2)] * fl.S[2]);
-      sink.put(F_GAM + i, r);
-    }
+    for (int q = 0; q < 9; ++q) db[q / 3][q % 3] = R[R_DB + q];
+    const int i = SI(s), j = SJ(s);
+    double d1[3];
+    double r = field_advko<true>(U + (F_AT + s) * fs, nb, P, beta, d1);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) r += At[S(i, k)] * db[k][j] + At[S(j, k)] * db[k][i];
+    r -= (2.0 / 3.0) * At[s] * (db[0][0] + db[1][1] + db[2][2]);
+    r += chi * (X[s] - gt[s] * contract_sym(gi, X) * (1.0 / 3.0));
+    double AAij = 0.0;  // At_ik gt^kl At_lj
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      AAij += At[S(i, k)] * (gi[S(k, 0)] * At[S(0, j)] + gi[S(k, 1)] * At[S(1, j)] + gi[S(k, 2)] * At[S(2, j)]);
+    r += alpha * (K * At[s] - 2.0 * AAij);
+    sink.put(F_AT + s, r);
+  }
 
+  // ---- connection functions: final right-hand side
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    COSMOS_PHASE();
+    double Aup[6], Gu[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      Aup[q] = R[R_AUP + q];
+      Gu[q] = R[R_GU + 6 * i + q];
+    }
+    const double divb = R[R_DB + 0] + R[R_DB + 4] + R[R_DB + 8];
+    double r = R[R_RG + i];
+    r -= R[R_GD + 0] * R[R_DB + 3 * i + 0] + R[R_GD + 1] * R[R_DB + 3 * i + 1] + R[R_GD + 2] * R[R_DB + 3 * i + 2];
+    r += (2.0 / 3.0) * R[R_GD + i] * divb;
+    r -= 2.0 * (Aup[S(i, 0)] * R[R_DAL + 0] + Aup[S(i, 1)] * R[R_DAL + 1] + Aup[S(i, 2)] * R[R_DAL + 2]);
+    double inner = contract_sym(Gu, Aup);
+    inner -= (1.5 / chi) * (Aup[S(i, 0)] * R[R_DCHI + 0] + Aup[S(i, 1)] * R[R_DCHI + 1] + Aup[S(i, 2)] * R[R_DCHI + 2]);
+    r += 2.0 * alpha * inner;
+    r -= 16.0 * PI_D * alpha *
+         (R[R_GI + S(i, 0)] * R[R_S + 0] + R[R_GI + S(i, 1)] * R[R_S + 1] + R[R_GI + S(i, 2)] * R[R_S + 2]);
+    sink.put(F_GAM + i, r);
+  }
+
+  // ---- fluid: flux divergence, geometric sources, dissipation
+  double div[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double Fm2[4], Fm1[4], Fp1[4], Fp2[4];
+    COSMOS_PHASE();
+    flux_at(U, fs, c + nb.d[a][1], a, P.w, Fm2);
+    COSMOS_PHASE();
+    flux_at(U, fs, c + nb.d[a][2], a, P.w, Fm1);
+    COSMOS_PHASE();
+    flux_at(U, fs, c + nb.d[a][4], a, P.w, Fp1);
+    COSMOS_PHASE();
+    flux_at(U, fs, c + nb.d[a][5], a, P.w, Fp2);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) div[q] += ((Fm2[q] - Fp2[q]) + 8.0 * (Fp1[q] - Fm1[q])) * P.i12h[a];
+  }
+  const double nbeta[3] = {0.0, 0.0, 0.0};
+  const double im32 = 1.0 / (chi * sqrt(chi));
   COSMOS_PHASE();
-    // ---- fluid: sources, flux divergence, dissipation
-    const double im32 = 1.0 / (chi * sqrt(chi));
+  {
     double KS = 0.0;
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
-      const double Kij = (At[s] + gt[s] * K * (1.0 / 3.0)) / chi;
-      KS += (s == 0 || s == 3 || s == 5 ? 1.0 : 2.0) * Kij * Sjk[s];
+      const double Kij = (ldq(U + (F_AT + s) * fs, c) + gt[s] * K * (1.0 / 3.0)) / chi;
+      KS += (s == 0 || s == 3 || s == 5 ? 1.0 : 2.0) * Kij * rec_Sjk(R, chi, s);
     }
-    double div[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      double Fm2[4], Fm1[4], Fp1[4], Fp2[4];
-      COSMOS_PHASE();
-      flux_at(U, fs, c + nb.d[a][1], a, P.w, Fm2);
-      COSMOS_PHASE();
-      flux_at(U, fs, c + nb.d[a][2], a, P.w, Fm1);
-      COSMOS_PHASE();
-      flux_at(U, fs, c + nb.d[a][4], a, P.w, Fp1);
-      COSMOS_PHASE();
-      flux_at(U, fs, c + nb.d[a][5], a, P.w, Fp2);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) div[q] += ((Fm2[q] - Fp2[q]) + 8.0 * (Fp1[q] - Fm1[q])) * P.i12h[a];
-    }
-    const double nbeta[3] = {0.0, 0.0, 0.0};
     double dummy[3];
-    COSMOS_PHASE();
-    {
-      const double ko = field_advko<false>(U + F_ET * fs, nb, P, nbeta, dummy);
-      const double Sda = fl.Sup[0] * dal[0] + fl.Sup[1] * dal[1] + fl.Sup[2] * dal[2];
-      sink.put(F_ET, ko + (im32 * (alpha * KS - Sda) - div[0]));
-    }
-    const double sgt = contract_sym(Sjk, gt);
-    const double ichi = 1.0 / chi, ichi2 = ichi * ichi;
+    const double ko = field_advko<false>(U + F_ET * fs, nb, P, nbeta, dummy);
+    const double Sda = R[R_SUP + 0] * R[R_DAL + 0] + R[R_SUP + 1] * R[R_DAL + 1] + R[R_SUP + 2] * R[R_DAL + 2];
+    sink.put(F_ET, ko + (im32 * (alpha * KS - Sda) - div[0]));
+  }
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      COSMOS_PHASE();
-      const double ko = field_advko<false>(U + (F_ST + i) * fs, nb, P, nbeta, dummy);
-      double src = -E * dal[i] + (fl.S[0] * db[0][i] + fl.S[1] * db[1][i] + fl.S[2] * db[2][i]);
-      src += 0.5 * alpha * (sg[i] * ichi - sgt * dchi[i] * ichi2);
-      sink.put(F_ST + i, ko + (im32 * src - div[1 + i]));
-    }
+  for (int i = 0; i < 3; ++i) {
+    COSMOS_PHASE();
+    double sgt = 0.0;
+#pragma unroll
+    for (int s = 0; s < 6; ++s) sgt += (s == 0 || s == 3 || s == 5 ? 1.0 : 2.0) * rec_Sjk(R, chi, s) * gt[s];
+    double dummy[3];
+    const double ko = field_advko<false>(U + (F_ST + i) * fs, nb, P, nbeta, dummy);
+    double src = -R[R_E] * R[R_DAL + i] +
+                 (R[R_S + 0] * R[R_DB + 0 + i] + R[R_S + 1] * R[R_DB + 3 + i] + R[R_S + 2] * R[R_DB + 6 + i]);
+    const double ichi = 1.0 / chi;
+    src += 0.5 * alpha * (R[R_SG + i] * ichi - sgt * R[R_DCHI + i] * (ichi * ichi));
+    sink.put(F_ST + i, ko + (im32 * src - div[1 + i]));
   }
 }
 

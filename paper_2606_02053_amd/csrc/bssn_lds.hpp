@@ -1,0 +1,486 @@
+// LDS-staged stage kernel: one 256-thread workgroup owns a BX x BY x BZ brick
+// (one point per thread). The 25 fields are visited in a fixed order; for each
+// field the workgroup copies the brick plus its periodic halo of width 3 (the
+// ghost-zone fill, done as an index wrap while loading) from HBM into an LDS
+// buffer with ~NH/256 independent coalesced loads per thread, and every thread
+// then forms that field's derivatives at its point from LDS with
+// compile-time-offset reads. The copy of the next field is issued before the
+// current field's arithmetic and written to the second LDS buffer after it, so
+// its latency hides behind the FP64 work. Long-lived per-point intermediates
+// live in a per-thread LDS record (R3_* slots).
+//
+// The arithmetic is that of bssn_rhs_stream in bssn_device.hpp (same
+// operations in the same order); only where the operands come from differs, so
+// the two variants agree up to the compiler's FMA-contraction choices.
+#pragma once
+#include "bssn_device.hpp"
+
+namespace cosmos {
+
+enum : int {
+  R3_GI = 0,     // 6  gt^ij
+  R3_E = 6,      // 1  E
+  R3_S = 7,      // 3  S_i
+  R3_P = 10,     // 1  P
+  R3_IX = 11,    // 1  1 / X
+  R3_DB = 12,    // 9  d_a beta^i at 3 i + a
+  R3_RG = 21,    // 3  accumulated Gt^i right-hand side
+  R3_RX = 24,    // 6  R_ij, then X_ij = -D_iD_j alpha + alpha (R_ij - 8 pi S_ij)
+  R3_SG = 30,    // 3  S^jk d_i gt_jk
+  R3_GU = 33,    // 18 d_a gt_ij at 3 ij + a, then Gt^k_ij at 6 k + ij
+  R3_DCHI = 51,  // 3
+  R3_DAL = 54,   // 3
+  R3_D2A = 57,   // 1
+  R3_COUNT = 58
+};
+
+template <int BX, int BY, int BZ>
+struct Brick {
+  static constexpr int HX = BX + 6, HY = BY + 6, HZ = BZ + 6;
+  static constexpr int NH = HX * HY * HZ;       // halo-box points
+  static constexpr int NQ = (NH + 255) / 256;   // loads per thread per field
+  static constexpr int SY = HX, SZ = HX * HY;   // LDS strides
+  static constexpr int LDS_DOUBLES = R3_COUNT * 256 + 2 * NH;
+  static_assert(BX * BY * BZ == 256, "one point per thread");
+  static_assert(LDS_DOUBLES * 8 <= 160 * 1024, "LDS budget");
+};
+
+// Stencil taps read from the LDS halo box: c points at the thread's centre.
+template <class B>
+__device__ __forceinline__ void lds_line(const double* c, int a, double v[7]) {
+  const int st = a == 0 ? 1 : (a == 1 ? B::SY : B::SZ);
+#pragma unroll
+  for (int o = 0; o < 7; ++o) v[o] = c[(o - 3) * st];
+}
+
+template <class B>
+__device__ __forceinline__ double lds_mixed(const double* c, int a, int b, double i144) {
+  const int sa = a == 0 ? 1 : (a == 1 ? B::SY : B::SZ);
+  const int sb = b == 0 ? 1 : (b == 1 ? B::SY : B::SZ);
+  const int oa[4] = {-2, -1, 1, 2};
+  double in[4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    const double* r = c + oa[p] * sa;
+    in[p] = (r[-2 * sb] - r[2 * sb]) + 8.0 * (r[sb] - r[-sb]);
+  }
+  return ((in[0] - in[3]) + 8.0 * (in[2] - in[1])) * i144;
+}
+
+template <class B, bool SECOND, bool ADV, bool KO = true>
+__device__ __forceinline__ void lds_derivs(const double* c, const DevParams& P, const double beta[3], FieldDerivs& r) {
+  double acc = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double v[7];
+    lds_line<B>(c, a, v);
+    r.d1[a] = op_d1(v, P.i12h[a]);
+    if (SECOND) r.d2[S(a, a)] = op_d2(v, P.i12h2[a]);
+    if (ADV) acc += op_adv(v, beta[a], P.i12h[a]);
+    if (KO) acc += op_ko(v, P.iko[a]);
+  }
+  r.advko = acc;
+  if (SECOND) {
+    r.d2[S(0, 1)] = lds_mixed<B>(c, 0, 1, P.i144[0]);
+    r.d2[S(0, 2)] = lds_mixed<B>(c, 0, 2, P.i144[1]);
+    r.d2[S(1, 2)] = lds_mixed<B>(c, 1, 2, P.i144[2]);
+  }
+}
+
+// Cooperative copy of one field's halo box: prefetch into registers, later commit to LDS.
+template <class B>
+struct HaloCopy {
+  int goff[B::NQ];  // linear grid index of this thread's halo-box points (wrapped)
+  double v[B::NQ];
+  __device__ __forceinline__ void init(int i0, int j0, int k0, const int n[3]) {
+#pragma unroll
+    for (int q = 0; q < B::NQ; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      const int ee = e < B::NH ? e : 0;
+      const int hx = ee % B::HX, hy = (ee / B::HX) % B::HY, hz = ee / (B::HX * B::HY);
+      // |offset| <= 3 + brick size; wrap twice to be safe for bricks larger than the grid
+      int x = i0 + hx - 3, y = j0 + hy - 3, z = k0 + hz - 3;
+      x = ((x % n[0]) + n[0]) % n[0];
+      y = ((y % n[1]) + n[1]) % n[1];
+      z = ((z % n[2]) + n[2]) % n[2];
+      goff[q] = x + n[0] * (y + n[1] * z);
+    }
+  }
+  __device__ __forceinline__ void fetch(const double* F) {
+#pragma unroll
+    for (int q = 0; q < B::NQ; ++q)
+      if (threadIdx.x + 256 * q < B::NH) v[q] = ldq(F, goff[q]);
+  }
+  __device__ __forceinline__ void commit(double* buf) const {
+#pragma unroll
+    for (int q = 0; q < B::NQ; ++q)
+      if (threadIdx.x + 256 * q < B::NH) buf[threadIdx.x + 256 * q] = v[q];
+  }
+};
+
+// The whole right-hand side of one point with LDS-staged stencils. All threads
+// of the workgroup must call it (it contains barriers); `active` marks threads
+// whose point lies inside the grid.
+template <class B, class Sink>
+__device__ __forceinline__ void bssn_rhs_lds(const double* U, size_t fs, const DevParams& P, double t, int i0, int j0,
+                                             int k0, int c, bool active, double* rec_base, double* buf0, double* buf1,
+                                             Sink& sink, bool& prim_fail) {
+  const Rec R{rec_base + threadIdx.x, 256};
+  const int lx = threadIdx.x % (B::HX - 6), ly = (threadIdx.x / (B::HX - 6)) % (B::HY - 6),
+            lz = threadIdx.x / ((B::HX - 6) * (B::HY - 6));
+  const int cidx = (lx + 3) + B::SY * ((ly + 3) + B::HY * (lz + 3));
+  HaloCopy<B> hc;
+  hc.init(i0, j0, k0, P.n);
+
+  // centre values (registers); inactive threads read a valid point and never store
+  const int cc = active ? c : 0;
+  const double chi = ldq(U + F_CHI * fs, cc);
+  const double K = ldq(U + F_K * fs, cc);
+  const double alpha = ldq(U + F_ALP * fs, cc);
+  double gt[6], beta[3];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) gt[s] = ldq(U + (F_GT + s) * fs, cc);
+#pragma unroll
+  for (int q = 0; q < 3; ++q) beta[q] = ldq(U + (F_BET + q) * fs, cc);
+
+  hc.fetch(U + (F_BET + 0) * fs);
+  {
+    double gi[6], St[3];
+    inv_sym(gt, gi);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) St[q] = ldq(U + (F_ST + q) * fs, cc);
+    Fluid fl;
+    prim_fail = active && recover(P.w, chi, gi, ldq(U + F_ET * fs, cc), St, fl);
+#pragma unroll
+    for (int s = 0; s < 6; ++s) R[R3_GI + s] = gi[s];
+    R[R3_E] = fl.E;
+    R[R3_P] = fl.P;
+    R[R3_IX] = fl.invX;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      R[R3_S + q] = fl.S[q];
+      R[R3_RG + q] = 0.0;
+      R[R3_SG + q] = 0.0;
+    }
+  }
+  hc.commit(buf0);
+  __syncthreads();
+
+  // Field visiting order (one staged field per phase); the phase p field is in
+  // buffer p & 1 and the next one is fetched while p is processed.
+  int phase = 0;
+  auto cur = [&]() -> const double* { return ((phase & 1) ? buf1 : buf0) + cidx; };
+  auto advance = [&](int next_field) {
+    // called at the end of a phase: commit the prefetched next field, swap buffers
+    (void)next_field;
+    hc.commit((phase & 1) ? buf0 : buf1);
+    __syncthreads();
+    ++phase;
+  };
+  auto S_up = [&](int j) {  // S^j = chi gt^jk S_k
+    return chi * (R[R3_GI + S(j, 0)] * R[R3_S + 0] + R[R3_GI + S(j, 1)] * R[R3_S + 1] + R[R3_GI + S(j, 2)] * R[R3_S + 2]);
+  };
+  auto Sjk_at = [&](int s) { return S_up(SI(s)) * S_up(SJ(s)) * R[R3_IX] + R[R3_P] * chi * R[R3_GI + s]; };
+
+  // ---- shift
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    hc.fetch(U + (i < 2 ? F_BET + i + 1 : F_GT) * fs);
+    if (active) {
+      double gi[6];
+#pragma unroll
+      for (int s = 0; s < 6; ++s) gi[s] = R[R3_GI + s];
+      FieldDerivs d;
+      lds_derivs<B, true, true>(cur(), P, beta, d);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) R[R3_DB + 3 * i + a] = d.d1[a];
+      R[R3_RG + i] += contract_sym(gi, d.d2);
+#pragma unroll
+      for (int l = 0; l < 3; ++l)
+        R[R3_RG + l] +=
+            (gi[S(l, 0)] * d.d2[S(0, i)] + gi[S(l, 1)] * d.d2[S(1, i)] + gi[S(l, 2)] * d.d2[S(2, i)]) * (1.0 / 3.0);
+      double r = 0.0;
+      if (P.evolve_shift) r = d.advko + (0.75 * ldq(U + (F_GAM + i) * fs, c) - P.eta * beta[i]);
+      sink.put(F_BET + i, r);
+    }
+    advance(0);
+  }
+
+  // ---- conformal metric
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    hc.fetch(U + (s < 5 ? F_GT + s + 1 : F_GAM) * fs);
+    if (active) {
+      double gi[6], db[3][3];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) gi[q] = R[R3_GI + q];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) db[q / 3][q % 3] = R[R3_DB + q];
+      FieldDerivs d;
+      lds_derivs<B, true, true>(cur(), P, beta, d);
+      const double wsym = (s == 0 || s == 3 || s == 5) ? 1.0 : 2.0;
+      const double Sjk = Sjk_at(s);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        R[R3_GU + 3 * s + a] = d.d1[a];
+        R[R3_SG + a] += wsym * Sjk * d.d1[a];
+      }
+      R[R3_RX + s] = -0.5 * contract_sym(gi, d.d2);
+      const int i = SI(s), j = SJ(s);
+      const double divb = db[0][0] + db[1][1] + db[2][2];
+      double r = d.advko;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) r += gt[S(i, k)] * db[k][j] + gt[S(j, k)] * db[k][i];
+      r -= (2.0 / 3.0) * gt[s] * divb;
+      r -= 2.0 * alpha * ldq(U + (F_AT + s) * fs, c);
+      sink.put(F_GT + s, r);
+    }
+    if (s == 5 && active) {  // connection and the quadratic Ricci terms (pure algebra)
+      COSMOS_PHASE();
+      double gi[6], dgt[6][3], Gu[3][6], Gd[3], Ric[6];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        gi[q] = R[R3_GI + q];
+        Ric[q] = R[R3_RX + q];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) dgt[q][a] = R[R3_GU + 3 * q + a];
+      }
+      connection_and_quadratic_ricci(dgt, gi, Gu, Gd, Ric);
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        R[R3_RX + q] = Ric[q];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) R[R3_GU + 6 * k + q] = Gu[k][q];
+      }
+    }
+    advance(0);
+  }
+
+  // ---- connection functions
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    hc.fetch(U + (k < 2 ? F_GAM + k + 1 : F_CHI) * fs);
+    if (active) {
+      FieldDerivs d;
+      lds_derivs<B, false, true>(cur(), P, beta, d);
+      R[R3_RG + k] += d.advko;
+#pragma unroll
+      for (int s = 0; s < 6; ++s) {
+        const int i = SI(s), j = SJ(s);
+        R[R3_RX + s] += 0.5 * (gt[S(k, i)] * d.d1[j] + gt[S(k, j)] * d.d1[i]);
+      }
+    }
+    advance(0);
+  }
+
+  // ---- conformal factor
+  hc.fetch(U + F_ALP * fs);
+  if (active) {
+    double gi[6], Gu[3][6], Ric[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      gi[q] = R[R3_GI + q];
+      Ric[q] = R[R3_RX + q];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) Gu[k][q] = R[R3_GU + 6 * k + q];
+    }
+    FieldDerivs d;
+    lds_derivs<B, true, true>(cur(), P, beta, d);
+    ricci_conformal_factor(chi, d.d1, d.d2, gt, gi, Gu, Ric);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) R[R3_RX + q] = Ric[q];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) R[R3_DCHI + a] = d.d1[a];
+    const double divb = R[R3_DB + 0] + R[R3_DB + 4] + R[R3_DB + 8];
+    sink.put(F_CHI, d.advko + (2.0 / 3.0) * chi * (alpha * K - divb));
+  }
+  advance(0);
+
+  // ---- lapse
+  hc.fetch(U + F_K * fs);
+  if (active) {
+    double gi[6], Gu[3][6], dchi[3];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      gi[q] = R[R3_GI + q];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) Gu[k][q] = R[R3_GU + 6 * k + q];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) dchi[a] = R[R3_DCHI + a];
+    FieldDerivs d;
+    lds_derivs<B, true, true>(cur(), P, beta, d);
+    const double* dal = d.d1;
+    double cda = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int l = 0; l < 3; ++l) cda += gi[S(k, l)] * dchi[k] * dal[l];
+    const double ih = 0.5 / chi;
+    double DDa[6];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+      const int i = SI(s), j = SJ(s);
+      DDa[s] = (d.d2[s] - (Gu[0][s] * dal[0] + Gu[1][s] * dal[1] + Gu[2][s] * dal[2])) +
+               ih * ((dchi[i] * dal[j] + dchi[j] * dal[i]) - gt[s] * cda);
+    }
+    R[R3_D2A] = chi * contract_sym(gi, DDa);
+    const double Kbg = P.lapse_bg ? -3.0 * P.H0 / (1.0 + 2.0 * P.H0 * t) : 0.0;
+    sink.put(F_ALP, d.advko - 2.0 * alpha * (K - Kbg));
+    const double ichi = 1.0 / chi;
+    const double ix = R[R3_IX], pr = R[R3_P];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+      const double Sij = R[R3_S + SI(s)] * R[R3_S + SJ(s)] * ix + pr * gt[s] * ichi;
+      R[R3_RX + s] = -DDa[s] + alpha * (R[R3_RX + s] - 8.0 * PI_D * Sij);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) R[R3_DAL + a] = dal[a];
+  }
+  advance(0);
+
+  // ---- trace K, and the final Gt^i right-hand side
+  hc.fetch(U + F_AT * fs);
+  if (active) {
+    double gi[6], At[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      gi[q] = R[R3_GI + q];
+      At[q] = ldq(U + (F_AT + q) * fs, c);
+    }
+    FieldDerivs d;
+    lds_derivs<B, false, true>(cur(), P, beta, d);
+    double Amix[3][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) Amix[k][j] = gi[S(k, 0)] * At[S(0, j)] + gi[S(k, 1)] * At[S(1, j)] + gi[S(k, 2)] * At[S(2, j)];
+    double Aup[6];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+      const int i = SI(s), j = SJ(s);
+      Aup[s] = Amix[i][0] * gi[S(0, j)] + Amix[i][1] * gi[S(1, j)] + Amix[i][2] * gi[S(2, j)];
+    }
+    const double AA = contract_sym(At, Aup);
+    double Sup[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) Sup[q] = S_up(q);
+    const double Str = (Sup[0] * R[R3_S + 0] + Sup[1] * R[R3_S + 1] + Sup[2] * R[R3_S + 2]) * R[R3_IX] + 3.0 * R[R3_P];
+    sink.put(F_K, d.advko + (-R[R3_D2A] + alpha * (AA + K * K * (1.0 / 3.0)) + 4.0 * PI_D * alpha * (R[R3_E] + Str)));
+    // Gt^i: every remaining term
+    const double divb = R[R3_DB + 0] + R[R3_DB + 4] + R[R3_DB + 8];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      double Gu[6];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) Gu[q] = R[R3_GU + 6 * i + q];
+      double Gd[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        double g[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) g[q] = R[R3_GU + 6 * k + q];
+        Gd[k] = contract_sym(gi, g);
+      }
+      double r = R[R3_RG + i];
+      r -= (4.0 / 3.0) * alpha * (gi[S(i, 0)] * d.d1[0] + gi[S(i, 1)] * d.d1[1] + gi[S(i, 2)] * d.d1[2]);
+      r -= Gd[0] * R[R3_DB + 3 * i + 0] + Gd[1] * R[R3_DB + 3 * i + 1] + Gd[2] * R[R3_DB + 3 * i + 2];
+      r += (2.0 / 3.0) * Gd[i] * divb;
+      r -= 2.0 * (Aup[S(i, 0)] * R[R3_DAL + 0] + Aup[S(i, 1)] * R[R3_DAL + 1] + Aup[S(i, 2)] * R[R3_DAL + 2]);
+      double inner = contract_sym(Gu, Aup);
+      inner -= (1.5 / chi) * (Aup[S(i, 0)] * R[R3_DCHI + 0] + Aup[S(i, 1)] * R[R3_DCHI + 1] + Aup[S(i, 2)] * R[R3_DCHI + 2]);
+      r += 2.0 * alpha * inner;
+      r -= 16.0 * PI_D * alpha * (gi[S(i, 0)] * R[R3_S + 0] + gi[S(i, 1)] * R[R3_S + 1] + gi[S(i, 2)] * R[R3_S + 2]);
+      sink.put(F_GAM + i, r);
+    }
+  }
+  advance(0);
+
+  // ---- traceless extrinsic curvature
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    hc.fetch(U + (s < 5 ? F_AT + s + 1 : F_ET) * fs);
+    if (active) {
+      double gi[6], At[6], X[6], db[3][3];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        gi[q] = R[R3_GI + q];
+        At[q] = ldq(U + (F_AT + q) * fs, c);
+        X[q] = R[R3_RX + q];
+      }
+#pragma unroll
+      for (int q = 0; q < 9; ++q) db[q / 3][q % 3] = R[R3_DB + q];
+      const int i = SI(s), j = SJ(s);
+      FieldDerivs d;
+      lds_derivs<B, false, true>(cur(), P, beta, d);
+      double r = d.advko;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) r += At[S(i, k)] * db[k][j] + At[S(j, k)] * db[k][i];
+      r -= (2.0 / 3.0) * At[s] * (db[0][0] + db[1][1] + db[2][2]);
+      r += chi * (X[s] - gt[s] * contract_sym(gi, X) * (1.0 / 3.0));
+      double AAij = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        AAij += At[S(i, k)] * (gi[S(k, 0)] * At[S(0, j)] + gi[S(k, 1)] * At[S(1, j)] + gi[S(k, 2)] * At[S(2, j)]);
+      r += alpha * (K * At[s] - 2.0 * AAij);
+      sink.put(F_AT + s, r);
+    }
+    advance(0);
+  }
+
+  // ---- fluid: flux divergence (fluxes formed at the axis neighbours), sources, dissipation
+  const double nbeta[3] = {0.0, 0.0, 0.0};
+  const double im32 = 1.0 / (chi * sqrt(chi));
+  double div[4] = {0.0, 0.0, 0.0, 0.0};
+  hc.fetch(U + F_ST * fs);
+  if (active) {
+    Nbr nb;
+    const int i = c % P.n[0], jk = c / P.n[0];
+    make_nbr(nb, i, jk % P.n[1], jk / P.n[1], P.n);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      double Fm2[4], Fm1[4], Fp1[4], Fp2[4];
+      COSMOS_PHASE();
+      flux_at(U, fs, c + nb.d[a][1], a, P.w, Fm2);
+      COSMOS_PHASE();
+      flux_at(U, fs, c + nb.d[a][2], a, P.w, Fm1);
+      COSMOS_PHASE();
+      flux_at(U, fs, c + nb.d[a][4], a, P.w, Fp1);
+      COSMOS_PHASE();
+      flux_at(U, fs, c + nb.d[a][5], a, P.w, Fp2);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) div[q] += ((Fm2[q] - Fp2[q]) + 8.0 * (Fp1[q] - Fm1[q])) * P.i12h[a];
+    }
+    COSMOS_PHASE();
+    double KS = 0.0;
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+      const double Kij = (ldq(U + (F_AT + s) * fs, c) + gt[s] * K * (1.0 / 3.0)) / chi;
+      KS += (s == 0 || s == 3 || s == 5 ? 1.0 : 2.0) * Kij * Sjk_at(s);
+    }
+    FieldDerivs d;
+    lds_derivs<B, false, false>(cur(), P, nbeta, d);
+    const double Sda = S_up(0) * R[R3_DAL + 0] + S_up(1) * R[R3_DAL + 1] + S_up(2) * R[R3_DAL + 2];
+    sink.put(F_ET, d.advko + (im32 * (alpha * KS - Sda) - div[0]));
+  }
+  advance(0);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    if (i < 2) hc.fetch(U + (F_ST + i + 1) * fs);
+    if (active) {
+      double sgt = 0.0;
+#pragma unroll
+      for (int s = 0; s < 6; ++s) sgt += (s == 0 || s == 3 || s == 5 ? 1.0 : 2.0) * Sjk_at(s) * gt[s];
+      FieldDerivs d;
+      lds_derivs<B, false, false>(cur(), P, nbeta, d);
+      double src = -R[R3_E] * R[R3_DAL + i] +
+                   (R[R3_S + 0] * R[R3_DB + 0 + i] + R[R3_S + 1] * R[R3_DB + 3 + i] + R[R3_S + 2] * R[R3_DB + 6 + i]);
+      const double ichi = 1.0 / chi;
+      src += 0.5 * alpha * (R[R3_SG + i] * ichi - sgt * R[R3_DCHI + i] * (ichi * ichi));
+      sink.put(F_ST + i, d.advko + (im32 * src - div[1 + i]));
+    }
+    if (i < 2) advance(0);
+  }
+}
+
+}  // namespace cosmos

@@ -14,6 +14,7 @@
 #include "bssn_device.hpp"
 #include "init_device.hpp"
 #include "constraints_device.hpp"
+#include "bssn_lds.hpp"
 
 using namespace cosmos;
 
@@ -78,6 +79,7 @@ int check_common(const cosmos_grid* g, const cosmos_params* p) {
       !(p->w > 0.0))
     return set_error(COSMOS_EINVAL, "invalid params (w must be > 0; all values finite)");
   if (p->fluid_scheme != 0) return set_error(COSMOS_EUNSUPPORTED, "fluid_scheme %d not implemented", p->fluid_scheme);
+  if (p->variant != 0 && p->variant != 1) return set_error(COSMOS_EINVAL, "variant must be 0 (LDS-staged) or 1 (direct)");
   return COSMOS_OK;
 }
 
@@ -92,6 +94,25 @@ int check_ws(const cosmos_grid* g, const void* ws) {
   if (!aligned(ws, kAlign)) return set_error(COSMOS_EINVAL, "workspace is not 256-byte aligned");
   return COSMOS_OK;
 }
+
+// Brick shape from the params (0 = default 16 x 4 x 4, XCD-ordered).
+int make_tile(const cosmos_grid* g, const cosmos_params* p, Tile& T) {
+  T.bx = p->tile_x ? p->tile_x : 16;
+  T.by = p->tile_y ? p->tile_y : 4;
+  T.bz = p->tile_z ? p->tile_z : 4;
+  T.xcd_order = p->tile_order == 0 ? 1 : (p->tile_order == 1 ? 0 : -1);
+  if (T.bx < 1 || T.by < 1 || T.bz < 1 || T.bx * T.by * T.bz != kBlock || T.xcd_order < 0)
+    return set_error(COSMOS_EINVAL, "tile %dx%dx%d (order %d) invalid: need tile_x*tile_y*tile_z == %d, order 0 or 1",
+                     T.bx, T.by, T.bz, p->tile_order, kBlock);
+  T.nbx = (g->n[0] + T.bx - 1) / T.bx;
+  T.nby = (g->n[1] + T.by - 1) / T.by;
+  T.nbz = (g->n[2] + T.bz - 1) / T.bz;
+  T.nbricks = T.nbx * T.nby * T.nbz;
+  T.per = (T.nbricks + 7) / 8;
+  return COSMOS_OK;
+}
+
+unsigned tile_blocks(const Tile& T) { return T.xcd_order ? 8u * (unsigned)T.per : (unsigned)T.nbricks; }
 
 DevParams dev_params(const cosmos_grid* g, const cosmos_params* p) {
   DevParams d;
@@ -153,19 +174,18 @@ struct StageSink {
 };
 
 __global__ __launch_bounds__(kBlock) void k_bssn_stage(const double* U, const double* un, double* acc, double* out,
-                                                        size_t fs, DevParams P, double t, double ca, double cn,
+                                                        size_t fs, DevParams P, Tile T, double t, double ca, double cn,
                                                         int mode, unsigned long long* status) {
-  const int p = blockIdx.x * kBlock + threadIdx.x;
-  if (p >= (int)fs) return;
-  const int i = p % P.n[0];
-  const int jk = p / P.n[0];
-  const int j = jk % P.n[1];
-  const int k = jk / P.n[1];
+  int i, j, k;
+  if (!tile_point(T, P.n, i, j, k)) return;
+  const int p = i + P.n[0] * (j + P.n[1] * k);
   Nbr nb;
   make_nbr(nb, i, j, k, P.n);
+  __shared__ double lds_rec[R_COUNT * kBlock];
+  const Rec rec{lds_rec + threadIdx.x, kBlock};
   StageSink sink{un, acc, out, fs, p, mode, ca, cn, P.alpha_collapse};
   bool fail = false;
-  bssn_rhs_stream(U, fs, nb, P, t, sink, fail);
+  bssn_rhs_stream(U, fs, nb, P, t, rec, sink, fail);
   if (fail) atomicAdd(&status[1], 1ull);
   if (mode == 3) {
     if (sink.bad) atomicAdd(&status[0], 1ull);
@@ -173,6 +193,57 @@ __global__ __launch_bounds__(kBlock) void k_bssn_stage(const double* U, const do
     if (p == 0) atomicAdd(&status[3], 1ull);
   }
 }
+
+template <int BX, int BY, int BZ>
+__global__ __launch_bounds__(kBlock) void k_bssn_stage_lds(const double* U, const double* un, double* acc, double* out,
+                                                            size_t fs, DevParams P, Tile T, double t, double ca,
+                                                            double cn, int mode, unsigned long long* status) {
+  using B = Brick<BX, BY, BZ>;
+  __shared__ double smem[B::LDS_DOUBLES];
+  int brick = blockIdx.x;
+  if (T.xcd_order) brick = (blockIdx.x & 7) * T.per + (blockIdx.x >> 3);
+  if (brick >= T.nbricks) return;  // uniform over the workgroup
+  const int bxi = brick % T.nbx, byz = brick / T.nbx;
+  const int i0 = bxi * BX, j0 = (byz % T.nby) * BY, k0 = (byz / T.nby) * BZ;
+  const int i = i0 + threadIdx.x % BX, j = j0 + (threadIdx.x / BX) % BY, k = k0 + threadIdx.x / (BX * BY);
+  const bool active = i < P.n[0] && j < P.n[1] && k < P.n[2];
+  const int c = active ? i + P.n[0] * (j + P.n[1] * k) : 0;
+  StageSink sink{un, acc, out, fs, c, mode, ca, cn, P.alpha_collapse};
+  bool fail = false;
+  bssn_rhs_lds<B>(U, fs, P, t, i0, j0, k0, c, active, smem, smem + R3_COUNT * 256, smem + R3_COUNT * 256 + B::NH,
+                  sink, fail);
+  if (!active) return;
+  if (fail) atomicAdd(&status[1], 1ull);
+  if (mode == 3) {
+    if (sink.bad) atomicAdd(&status[0], 1ull);
+    if (sink.coll) atomicAdd(&status[2], 1ull);
+    if (c == 0) atomicAdd(&status[3], 1ull);
+  }
+}
+
+namespace {
+// Launch one stage with the kernel variant and brick chosen in the params.
+int launch_stage(const cosmos_params* p, const Tile& T, hipStream_t s, const double* U, const double* un, double* acc,
+                 double* out, size_t fs, const DevParams& P, double t, double ca, double cn, int mode,
+                 unsigned long long* status) {
+  const dim3 g(tile_blocks(T)), b(kBlock);
+  if (p->variant == 1) {
+    hipLaunchKernelGGL(k_bssn_stage, g, b, 0, s, U, un, acc, out, fs, P, T, t, ca, cn, mode, status);
+  } else if (T.bx == 16 && T.by == 4 && T.bz == 4) {
+    hipLaunchKernelGGL((k_bssn_stage_lds<16, 4, 4>), g, b, 0, s, U, un, acc, out, fs, P, T, t, ca, cn, mode, status);
+  } else if (T.bx == 16 && T.by == 8 && T.bz == 2) {
+    hipLaunchKernelGGL((k_bssn_stage_lds<16, 8, 2>), g, b, 0, s, U, un, acc, out, fs, P, T, t, ca, cn, mode, status);
+  } else if (T.bx == 8 && T.by == 8 && T.bz == 4) {
+    hipLaunchKernelGGL((k_bssn_stage_lds<8, 8, 4>), g, b, 0, s, U, un, acc, out, fs, P, T, t, ca, cn, mode, status);
+  } else if (T.bx == 8 && T.by == 4 && T.bz == 8) {
+    hipLaunchKernelGGL((k_bssn_stage_lds<8, 4, 8>), g, b, 0, s, U, un, acc, out, fs, P, T, t, ca, cn, mode, status);
+  } else {
+    return set_error(COSMOS_EINVAL, "LDS-staged variant has no %dx%dx%d brick (16x4x4, 16x8x2, 8x8x4, 8x4x8)", T.bx,
+                     T.by, T.bz);
+  }
+  return COSMOS_OK;
+}
+}  // namespace
 
 // ---------------------------------------------------------------- ABI
 extern "C" {
@@ -238,9 +309,12 @@ int cosmos_rhs(const cosmos_grid* grid, const cosmos_params* params, double t, c
   if (u == dudt) return set_error(COSMOS_EINVAL, "dudt must not alias u");
   if (!std::isfinite(t)) return set_error(COSMOS_EINVAL, "t is not finite");
   const DevParams P = dev_params(grid, params);
+  Tile T;
+  if ((rc = make_tile(grid, params, T))) return rc;
   auto* status = (unsigned long long*)ws;
-  hipLaunchKernelGGL(k_bssn_stage, dim3(nblocks(grid)), dim3(kBlock), 0, (hipStream_t)stream, u, nullptr, nullptr,
-                     dudt, npts(grid), P, t, 0.0, 0.0, 0, status);
+  if ((rc = launch_stage(params, T, (hipStream_t)stream, u, nullptr, nullptr, dudt, npts(grid), P, t, 0.0, 0.0, 0,
+                         status)))
+    return rc;
   HIP_TRY(hipGetLastError());
   return COSMOS_OK;
 }
@@ -257,13 +331,14 @@ int cosmos_rk4_step(const cosmos_grid* grid, const cosmos_params* params, double
   double* B = (double*)(w + L.B);
   auto* status = (unsigned long long*)(w + L.status);
   const DevParams P = dev_params(grid, params);
+  Tile T;
+  if ((rc = make_tile(grid, params, T))) return rc;
   const size_t fs = npts(grid);
-  const dim3 gdim(nblocks(grid)), bdim(kBlock);
   hipStream_t s = (hipStream_t)stream;
-  hipLaunchKernelGGL(k_bssn_stage, gdim, bdim, 0, s, u, u, acc, A, fs, P, t, dt / 6.0, dt / 2.0, 1, status);
-  hipLaunchKernelGGL(k_bssn_stage, gdim, bdim, 0, s, A, u, acc, B, fs, P, t + dt / 2.0, dt / 3.0, dt / 2.0, 2, status);
-  hipLaunchKernelGGL(k_bssn_stage, gdim, bdim, 0, s, B, u, acc, A, fs, P, t + dt / 2.0, dt / 3.0, dt, 2, status);
-  hipLaunchKernelGGL(k_bssn_stage, gdim, bdim, 0, s, A, nullptr, acc, u, fs, P, t + dt, dt / 6.0, 0.0, 3, status);
+  if ((rc = launch_stage(params, T, s, u, u, acc, A, fs, P, t, dt / 6.0, dt / 2.0, 1, status))) return rc;
+  launch_stage(params, T, s, A, u, acc, B, fs, P, t + dt / 2.0, dt / 3.0, dt / 2.0, 2, status);
+  launch_stage(params, T, s, B, u, acc, A, fs, P, t + dt / 2.0, dt / 3.0, dt, 2, status);
+  launch_stage(params, T, s, A, nullptr, acc, u, fs, P, t + dt, dt / 6.0, 0.0, 3, status);
   HIP_TRY(hipGetLastError());
   return COSMOS_OK;
 }

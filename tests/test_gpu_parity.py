@@ -42,10 +42,12 @@ def to_dev(u):
     return torch.from_numpy(np.ascontiguousarray(u)).cuda()
 
 
+@pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("n,L", [((8, 8, 8), (2.4, 2.4, 2.4)), ((12, 16, 10), (3.0, 3.5, 2.5)),
                                  ((32, 32, 32), (10.0, 10.0, 10.0))])
-def test_rhs_fuzz(P, orc, n, L):
+def test_rhs_fuzz(P, orc, n, L, variant):
     s, sol = mk(P, orc, n, L)
+    sol.params.variant = variant
     u = fuzz_state(n, seed=101)
     sol.set_state(to_dev(u))
     for t in (0.0, 0.37):
@@ -214,3 +216,30 @@ def test_bench_configuration_sampled(P, orc):
     r1 = orc.rk4_at_points(s, u0, pts[:8], 0.0, dt)
     scale = np.maximum(np.abs(r1).max(axis=0), 1e-3)
     assert (np.abs(g1 - r1).max(axis=0) / scale).max() < 1e-11
+
+
+def test_tile_invariance_bitwise(P, orc):
+    """Every brick and order of one kernel variant gives bitwise the same result (partial bricks
+    included); the two variants agree to round-off (the compiler contracts FMAs differently)."""
+    from paper_2606_02053_amd import autotune
+    n, L = (20, 12, 18), (4.0, 2.5, 3.5)
+    s, sol = mk(P, orc, n, L)
+    u = fuzz_state(n, seed=12)
+    sol.set_state(to_dev(u))
+    ref = sol.rhs(t=0.1)
+    r, _ = orc.rhs(s, u, t=0.1)
+    assert err_fields(ref.cpu().numpy(), r)[0] < 1e-11
+    dt = 0.25 * min(s.h)
+    first_rhs, first_step = {}, {}
+    for kv, tile, order in autotune.CANDIDATES:
+        p = autotune.with_tile(sol.params, kv, tile, order)
+        out = torch.empty_like(sol.u)
+        P.cosmos_rhs(sol.grid, p, 0.1, sol.u, out, sol.ws)
+        v = sol.u.clone()
+        P.cosmos_rk4_step(sol.grid, p, 0.1, dt, v, sol.ws)
+        if kv not in first_rhs:
+            first_rhs[kv], first_step[kv] = out, v
+            assert err_fields(out.cpu().numpy(), r)[0] < 1e-11, kv
+        assert torch.equal(out, first_rhs[kv]), (kv, tile, order)
+        assert torch.equal(v, first_step[kv]), (kv, tile, order)
+    assert err_fields(first_rhs[0].cpu().numpy(), first_rhs[1].cpu().numpy())[0] < 1e-13
