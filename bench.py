@@ -8,7 +8,12 @@ roofline of that kernel (algorithmic bytes per launch / average launch time,
 measured with HIP events on the launch stream) and the CPU oracle timed on a
 bounded sample of the same workload.
 
-Extra modes (for profiling runs of committed code):
+Extra modes:
+  --batched      the 64-run threshold-scan workload (grid sizes drawn from
+                 {48, 64, 80, 96}^3, mu in [0.3, 0.8], sigma in [0.8, 1.6], box 12/H0,
+                 300 RK4 steps per run): runs/s of the batched, hipGraph-replayed form
+                 against the same runs advanced one after another by the plain solver
+  --adjoint      the differentiation workload (see adjoint_bench)
   --copy-probe   only a plain device-to-device copy of known size (calibrates
                  rocprofv3 FETCH_SIZE / WRITE_SIZE counters)
   --no-cpu       skip the CPU baseline leg
@@ -43,6 +48,9 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-tune", action="store_true", help="use the default tile instead of the autotuned one")
+    ap.add_argument("--batched", action="store_true")
+    ap.add_argument("--batched-steps", type=int, default=30, help="timed steps (runs/s is scaled to 300 steps)")
+    ap.add_argument("--adjoint", action="store_true")
     return ap.parse_args()
 
 
@@ -84,6 +92,52 @@ def cpu_baseline(n_steps: int):
                       f"sigma = 2.0), OpenMP over z-planes, {el:.1f} s"}
 
 
+def batched_bench(a):
+    import paper_2606_02053_amd as P
+    from paper_2606_02053_amd.batch import Batch, draw_scan
+    runs = draw_scan(64, seed=2606)
+    total_steps = 300
+    b = Batch(runs)
+    b.init()
+    b.capture()
+    b.run(2)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    b.run(a.batched_steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / a.batched_steps
+    st = b.status()
+    if any(x["nonfinite"] for x in st):
+        raise RuntimeError("non-finite values in the batched run")
+    # the same runs, one after another, on the plain solver (same kernel and brick)
+    plain_ms = 0.0
+    for spec in runs:
+        s = P.Solver(spec.n, spec.L, P.make_params(tile=(16, 4, 4), tile_order=1))
+        s.init(mu=spec.mu, sigma=spec.sigma)
+        dt = 0.25 * spec.L / spec.n
+        s.step(dt)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(3):
+            s.step(dt)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        plain_ms += e0.elapsed_time(e1) / 3
+    pts = sum(r.n ** 3 for r in runs)
+    out = {"metric": "batched runs/sec (64-run threshold scan, 300 RK4 steps per run)",
+           "value": len(runs) / (ms_step * total_steps / 1e3), "unit": "runs/s",
+           "serial_plain_value": len(runs) / (plain_ms * total_steps / 1e3), "speedup_vs_serial": plain_ms / ms_step,
+           "ms_per_batched_step": ms_step, "ms_per_serial_step_sum": plain_ms, "points_per_step": pts,
+           "point_updates_per_s": pts / (ms_step / 1e3), "timed_steps": a.batched_steps,
+           "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "64 runs, n from {48,64,80,96} (numpy default_rng(2606)), mu U[0.3,0.8], "
+                                  "sigma U[0.8,1.6], L = 12/H0, CFL 0.25, hipGraph-replayed RK4 steps"}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -92,6 +146,9 @@ def main():
         sys.exit(2)
     if a.copy_probe:
         copy_probe()
+        return
+    if a.batched:
+        batched_bench(a)
         return
     import paper_2606_02053_amd as P
     from paper_2606_02053_amd import autotune

@@ -164,6 +164,37 @@ int cosmos_rk4_step(const cosmos_grid* grid, const cosmos_params* params, double
 int cosmos_constraints(const cosmos_grid* grid, const cosmos_params* params, const double* u,
                        double* norms_dev, double* H_out, double* M_out, void* ws, void* stream);
 
+/* Batched form: many independent runs advanced together, one persistent launch per RK4 stage
+ * for all of them (work items = (run, 16x4x4 brick)). Run r has a cubic periodic grid of n[r]^3
+ * points (n[r] divisible by 16) and box L[r]; its state (25 * n[r]^3 doubles, layout as above)
+ * starts at arena + state_off[r] (state_off[r] a multiple of 32). All runs share the params
+ * (tile fields are ignored). Host arrays, read during the call only. */
+typedef struct {
+  int32_t nruns;
+  const int32_t* n;
+  const double* L;
+  const int64_t* state_off;
+} cosmos_batch;
+
+/* Bytes of batch workspace: descriptor table, work list, per-run status counters and three
+ * stage buffers matching the arena layout. 0 for an invalid batch. */
+size_t cosmos_batch_workspace_bytes(const cosmos_batch* batch);
+
+/* Upload the per-run descriptor table and the interleaved (run, brick) work list into bws and
+ * zero the per-run status counters. Synchronises `stream`. Call once per batch (not inside a
+ * graph capture). */
+int cosmos_batch_setup(const cosmos_batch* batch, const cosmos_params* params, void* bws, void* stream);
+
+/* One classic RK4 step of every run: run r advances by dt_dev[r] from time t_dev[r]; t_dev is
+ * advanced on the device (t_dev, dt_dev: device arrays of nruns doubles). Enqueues 4 stage
+ * launches and one time update and nothing else, so it can be captured in a hipGraph and
+ * replayed; the results equal those of cosmos_rk4_step on each run with a 16x4x4 brick. */
+int cosmos_rk4_step_batched(const cosmos_batch* batch, const cosmos_params* params, double* arena,
+                            double* t_dev, const double* dt_dev, void* bws, void* stream);
+
+/* Synchronise and copy the per-run counters to host out[nruns][4] (as cosmos_status). */
+int cosmos_batch_status(const cosmos_batch* batch, void* bws, void* stream, int64_t* out);
+
 /* Human-readable reason for the last error on this thread ("" if none). */
 const char* cosmos_last_error(void);
 

@@ -70,6 +70,7 @@ def _load():
         "cosmos_batch_workspace_bytes": ([B], sz),
         "cosmos_batch_setup": ([B, Pr, P, P], i32),
         "cosmos_rk4_step_batched": ([B, Pr, P, P, P, P, P], i32),
+        "cosmos_batch_status": ([B, P, P, ctypes.POINTER(ctypes.c_int64)], i32),
         "cosmos_last_error": ([], ctypes.c_char_p),
         "cosmos_abi_version": ([], i32),
     }
@@ -200,3 +201,42 @@ def cosmos_adjoint_step(grid, params, t: float, dt: float, u_n, lam_np1, lam_n, 
 
 def cosmos_abi_version() -> int:
     return int(lib.cosmos_abi_version())
+
+
+# ---------------------------------------------------------------- batched form
+def make_batch(n_list, L_list, off_list):
+    """cosmos_batch plus the ctypes arrays it points to (kept alive on the struct)."""
+    k = len(n_list)
+    b = cosmos_batch()
+    b._n = (ctypes.c_int32 * k)(*[int(x) for x in n_list])
+    b._L = (ctypes.c_double * k)(*[float(x) for x in L_list])
+    b._off = (ctypes.c_int64 * k)(*[int(x) for x in off_list])
+    b.nruns = k
+    b.n = ctypes.cast(b._n, ctypes.POINTER(ctypes.c_int32))
+    b.L = ctypes.cast(b._L, ctypes.POINTER(ctypes.c_double))
+    b.state_off = ctypes.cast(b._off, ctypes.POINTER(ctypes.c_int64))
+    return b
+
+
+def cosmos_batch_workspace_bytes(batch) -> int:
+    return int(lib.cosmos_batch_workspace_bytes(ctypes.byref(batch)))
+
+
+def cosmos_batch_setup(batch, params, bws, stream=None):
+    _check(lib.cosmos_batch_setup(ctypes.byref(batch), ctypes.byref(params),
+                                  _dev(bws, "bws", cosmos_batch_workspace_bytes(batch), dtype=torch.uint8),
+                                  _stream(stream)))
+
+
+def cosmos_rk4_step_batched(batch, params, arena, t_dev, dt_dev, bws, stream=None):
+    _check(lib.cosmos_rk4_step_batched(ctypes.byref(batch), ctypes.byref(params), _dev(arena, "arena"),
+                                       _dev(t_dev, "t_dev", batch.nruns), _dev(dt_dev, "dt_dev", batch.nruns),
+                                       _dev(bws, "bws", cosmos_batch_workspace_bytes(batch), dtype=torch.uint8),
+                                       _stream(stream)))
+
+
+def cosmos_batch_status(batch, bws, stream=None):
+    out = (ctypes.c_int64 * (4 * batch.nruns))()
+    _check(lib.cosmos_batch_status(ctypes.byref(batch), _dev(bws, "bws", dtype=torch.uint8), _stream(stream), out))
+    return [{"nonfinite": out[4 * r], "prim_fail": out[4 * r + 1], "collapsed": out[4 * r + 2],
+             "steps": out[4 * r + 3]} for r in range(batch.nruns)]

@@ -87,18 +87,27 @@ __device__ __forceinline__ void lds_derivs(const double* c, const DevParams& P, 
   }
 }
 
-// Cooperative copy of one field's halo box: prefetch into registers, later commit to LDS.
+// Order in which the fields are staged (one per phase).
+constexpr int kStageOrder[NF] = {F_BET,    F_BET + 1, F_BET + 2, F_GT,     F_GT + 1, F_GT + 2, F_GT + 3,
+                                 F_GT + 4, F_GT + 5,  F_GAM,     F_GAM + 1, F_GAM + 2, F_CHI,   F_ALP,
+                                 F_K,      F_AT,      F_AT + 1,  F_AT + 2, F_AT + 3, F_AT + 4, F_AT + 5,
+                                 F_ET,     F_ST,      F_ST + 1,  F_ST + 2};
+constexpr int kPrefetch = 3;  // fields in flight ahead of the one being processed
+
+// Cooperative copy of the fields' halo boxes: a ring of kPrefetch register
+// sets (slot 0 = next field to commit to LDS), rotated with constant indices.
 template <class B>
 struct HaloCopy {
   int goff[B::NQ];  // linear grid index of this thread's halo-box points (wrapped)
-  double v[B::NQ];
+  double v[kPrefetch][B::NQ];
   __device__ __forceinline__ void init(int i0, int j0, int k0, const int n[3]) {
 #pragma unroll
     for (int q = 0; q < B::NQ; ++q) {
       const int e = threadIdx.x + 256 * q;
       const int ee = e < B::NH ? e : 0;
       const int hx = ee % B::HX, hy = (ee / B::HX) % B::HY, hz = ee / (B::HX * B::HY);
-      // |offset| <= 3 + brick size; wrap twice to be safe for bricks larger than the grid
+      // brick origins are inside the grid, so one period of wrap suffices except
+      // for grids smaller than the brick: reduce fully
       int x = i0 + hx - 3, y = j0 + hy - 3, z = k0 + hz - 3;
       x = ((x % n[0]) + n[0]) % n[0];
       y = ((y % n[1]) + n[1]) % n[1];
@@ -106,15 +115,20 @@ struct HaloCopy {
       goff[q] = x + n[0] * (y + n[1] * z);
     }
   }
+  template <int SLOT>
   __device__ __forceinline__ void fetch(const double* F) {
 #pragma unroll
     for (int q = 0; q < B::NQ; ++q)
-      if (threadIdx.x + 256 * q < B::NH) v[q] = ldq(F, goff[q]);
+      if (threadIdx.x + 256 * q < B::NH) v[SLOT][q] = ldq(F, goff[q]);
   }
-  __device__ __forceinline__ void commit(double* buf) const {
+  __device__ __forceinline__ void commit_and_rotate(double* buf) {
 #pragma unroll
     for (int q = 0; q < B::NQ; ++q)
-      if (threadIdx.x + 256 * q < B::NH) buf[threadIdx.x + 256 * q] = v[q];
+      if (threadIdx.x + 256 * q < B::NH) buf[threadIdx.x + 256 * q] = v[0][q];
+#pragma unroll
+    for (int d = 0; d + 1 < kPrefetch; ++d)
+#pragma unroll
+      for (int q = 0; q < B::NQ; ++q) v[d][q] = v[d + 1][q];
   }
 };
 
@@ -143,7 +157,9 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, size_t fs, const D
 #pragma unroll
   for (int q = 0; q < 3; ++q) beta[q] = ldq(U + (F_BET + q) * fs, cc);
 
-  hc.fetch(U + (F_BET + 0) * fs);
+  hc.template fetch<0>(U + kStageOrder[0] * fs);
+  hc.template fetch<1>(U + kStageOrder[1] * fs);
+  hc.template fetch<2>(U + kStageOrder[2] * fs);
   {
     double gi[6], St[3];
     inv_sym(gt, gi);
@@ -163,17 +179,19 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, size_t fs, const D
       R[R3_SG + q] = 0.0;
     }
   }
-  hc.commit(buf0);
+  hc.commit_and_rotate(buf0);
   __syncthreads();
 
-  // Field visiting order (one staged field per phase); the phase p field is in
-  // buffer p & 1 and the next one is fetched while p is processed.
+  // Phase p processes field kStageOrder[p] from LDS buffer p & 1. At its start
+  // the field p + kPrefetch is fetched into the last register slot; at its end
+  // the field p + 1 (slot 0) is committed to the other buffer.
   int phase = 0;
   auto cur = [&]() -> const double* { return ((phase & 1) ? buf1 : buf0) + cidx; };
-  auto advance = [&](int next_field) {
-    // called at the end of a phase: commit the prefetched next field, swap buffers
-    (void)next_field;
-    hc.commit((phase & 1) ? buf0 : buf1);
+  auto prefetch = [&]() {
+    if (phase + kPrefetch < NF) hc.template fetch<kPrefetch - 1>(U + kStageOrder[phase + kPrefetch] * fs);
+  };
+  auto advance = [&](int) {
+    if (phase + 1 < NF) hc.commit_and_rotate((phase & 1) ? buf0 : buf1);
     __syncthreads();
     ++phase;
   };
@@ -185,7 +203,7 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, size_t fs, const D
   // ---- shift
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    hc.fetch(U + (i < 2 ? F_BET + i + 1 : F_GT) * fs);
+    prefetch();
     if (active) {
       double gi[6];
 #pragma unroll
@@ -209,7 +227,7 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, size_t fs, const D
   // ---- conformal metric
 #pragma unroll
   for (int s = 0; s < 6; ++s) {
-    hc.fetch(U + (s < 5 ? F_GT + s + 1 : F_GAM) * fs);
+    prefetch();
     if (active) {
       double gi[6], db[3][3];
 #pragma unroll
@@ -259,7 +277,7 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, size_t fs, const D
   // ---- connection functions
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    hc.fetch(U + (k < 2 ? F_GAM + k + 1 : F_CHI) * fs);
+    prefetch();
     if (active) {
       FieldDerivs d;
       lds_derivs<B, false, true>(cur(), P, beta, d);
@@ -274,7 +292,7 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, size_t fs, const D
   }
 
   // ---- conformal factor
-  hc.fetch(U + F_ALP * fs);
+  prefetch();
   if (active) {
     double gi[6], Gu[3][6], Ric[6];
 #pragma unroll
@@ -297,7 +315,7 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, size_t fs, const D
   advance(0);
 
   // ---- lapse
-  hc.fetch(U + F_K * fs);
+  prefetch();
   if (active) {
     double gi[6], Gu[3][6], dchi[3];
 #pragma unroll
@@ -340,7 +358,7 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, size_t fs, const D
   advance(0);
 
   // ---- trace K, and the final Gt^i right-hand side
-  hc.fetch(U + F_AT * fs);
+  prefetch();
   if (active) {
     double gi[6], At[6];
 #pragma unroll
@@ -399,7 +417,7 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, size_t fs, const D
   // ---- traceless extrinsic curvature
 #pragma unroll
   for (int s = 0; s < 6; ++s) {
-    hc.fetch(U + (s < 5 ? F_AT + s + 1 : F_ET) * fs);
+    prefetch();
     if (active) {
       double gi[6], At[6], X[6], db[3][3];
 #pragma unroll
@@ -432,7 +450,7 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, size_t fs, const D
   const double nbeta[3] = {0.0, 0.0, 0.0};
   const double im32 = 1.0 / (chi * sqrt(chi));
   double div[4] = {0.0, 0.0, 0.0, 0.0};
-  hc.fetch(U + F_ST * fs);
+  prefetch();
   if (active) {
     Nbr nb;
     const int i = c % P.n[0], jk = c / P.n[0];
@@ -440,13 +458,10 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, size_t fs, const D
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       double Fm2[4], Fm1[4], Fp1[4], Fp2[4];
-      COSMOS_PHASE();
+      COSMOS_PHASE();  // the four neighbours of one axis are gathered together
       flux_at(U, fs, c + nb.d[a][1], a, P.w, Fm2);
-      COSMOS_PHASE();
       flux_at(U, fs, c + nb.d[a][2], a, P.w, Fm1);
-      COSMOS_PHASE();
       flux_at(U, fs, c + nb.d[a][4], a, P.w, Fp1);
-      COSMOS_PHASE();
       flux_at(U, fs, c + nb.d[a][5], a, P.w, Fp2);
 #pragma unroll
       for (int q = 0; q < 4; ++q) div[q] += ((Fm2[q] - Fp2[q]) + 8.0 * (Fp1[q] - Fm1[q])) * P.i12h[a];
@@ -466,7 +481,7 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, size_t fs, const D
   advance(0);
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    if (i < 2) hc.fetch(U + (F_ST + i + 1) * fs);
+    prefetch();
     if (active) {
       double sgt = 0.0;
 #pragma unroll

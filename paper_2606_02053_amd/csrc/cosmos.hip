@@ -9,6 +9,8 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
+#include <algorithm>
 
 #include "cosmos.h"
 #include "bssn_device.hpp"
@@ -363,3 +365,5 @@ int cosmos_constraints(const cosmos_grid* grid, const cosmos_params* params, con
 }
 
 }  // extern "C"
+
+#include "batch.hip.inc"
