@@ -13,7 +13,10 @@ Extra modes:
                  {48, 64, 80, 96}^3, mu in [0.3, 0.8], sigma in [0.8, 1.6], box 12/H0,
                  300 RK4 steps per run): runs/s of the batched, hipGraph-replayed form
                  against the same runs advanced one after another by the plain solver
-  --adjoint      the differentiation workload (see adjoint_bench)
+  --adjoint      the differentiation workload: 96^3, box 12/H0, mu = 0.55,
+                 sigma = 1.2, 200 RK4 steps, checkpoint every 20; gradient of the centre
+                 lapse in (mu, sigma) by the discrete adjoint, its cost relative to the
+                 plain forward run, and central finite differences (h = 1e-6)
   --copy-probe   only a plain device-to-device copy of known size (calibrates
                  rocprofv3 FETCH_SIZE / WRITE_SIZE counters)
   --no-cpu       skip the CPU baseline leg
@@ -138,6 +141,46 @@ def batched_bench(a):
     print(json.dumps(out), flush=True)
 
 
+def adjoint_bench(a):
+    from paper_2606_02053_amd.adjoint import RunConfig, central_lapse
+    import paper_2606_02053_amd as P
+    cfg = RunConfig(n=96, L=12.0, nsteps=200, checkpoint_every=20)
+    t64 = lambda x, g=False: torch.tensor(x, dtype=torch.float64, requires_grad=g)  # noqa: E731
+    # plain forward run (same steps, no checkpoints)
+    s = P.Solver(cfg.n, cfg.L, cfg.params)
+    s.init(mu=0.55, sigma=1.2)
+    s.step(cfg.dt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.init(mu=0.55, sigma=1.2)
+    for m in range(cfg.nsteps):
+        P.cosmos_rk4_step(s.grid, s.params, m * cfg.dt, cfg.dt, s.u, s.ws)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    mu, sigma = t64(0.55, True), t64(1.2, True)
+    t0 = time.perf_counter()
+    J = central_lapse(mu, sigma, cfg)
+    J.backward()
+    torch.cuda.synchronize()
+    t_grad = time.perf_counter() - t0
+    g = [mu.grad.item(), sigma.grad.item()]
+    h = 1e-6
+    fd = []
+    for dm, ds in ((h, 0.0), (0.0, h)):
+        jp = central_lapse(t64(0.55 + dm), t64(1.2 + ds), cfg).item()
+        jm = central_lapse(t64(0.55 - dm), t64(1.2 - ds), cfg).item()
+        fd.append((jp - jm) / (2 * h))
+    out = {"metric": "adjoint cost (forward + backward wall time / plain forward wall time)",
+           "value": t_grad / t_fwd, "unit": "x forward", "higher_is_better": False,
+           "forward_s": t_fwd, "forward_plus_adjoint_s": t_grad, "J": J.item(),
+           "dJ_dmu": g[0], "dJ_dsigma": g[1], "fd_dJ_dmu": fd[0], "fd_dJ_dsigma": fd[1],
+           "rel_diff_vs_fd": [abs(g[i] - fd[i]) / abs(fd[i]) for i in range(2)], "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "96^3 periodic, L = 12/H0, Gaussian zeta mu = 0.55 sigma = 1.2, 200 RK4 steps, "
+                                  "CFL 0.25, checkpoint every 20, J = centre lapse at the final time"}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -149,6 +192,9 @@ def main():
         return
     if a.batched:
         batched_bench(a)
+        return
+    if a.adjoint:
+        adjoint_bench(a)
         return
     import paper_2606_02053_amd as P
     from paper_2606_02053_amd import autotune

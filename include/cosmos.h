@@ -164,6 +164,25 @@ int cosmos_rk4_step(const cosmos_grid* grid, const cosmos_params* params, double
 int cosmos_constraints(const cosmos_grid* grid, const cosmos_params* params, const double* u,
                        double* norms_dev, double* H_out, double* M_out, void* ws, void* stream);
 
+/* Bytes of device workspace for cosmos_rhs_vjp / cosmos_adjoint_step: status counters, the
+ * recomputed stage states U2..U4 and the stage accumulator, two state-sized cotangent buffers and
+ * 136 * N3 doubles of per-point cotangent scratch. 0 for an invalid grid. */
+size_t cosmos_adjoint_workspace_bytes(const cosmos_grid* grid);
+
+/* Transposed Jacobian of the discrete right-hand side at state u and time t applied to kbar:
+ * ubar = (d rhs / d u)^T kbar (all three 25 * N3 values; ubar must not alias the others).
+ * The upwind branches are frozen at the forward choice (sign of beta^a at each point). */
+int cosmos_rhs_vjp(const cosmos_grid* grid, const cosmos_params* params, double t, const double* u,
+                   const double* kbar, double* ubar, void* ws, void* stream);
+
+/* Discrete adjoint of one RK4 step of cosmos_rk4_step: lam_n = (d u_{n+1} / d u_n)^T lam_np1 at
+ * state u_n, time t, step dt. The stage states are recomputed from u_n; then, with
+ * kb4 = dt/6 lam', ub_s = J_f(U_s)^T kb_s, kb3 = dt/3 lam' + dt ub4, kb2 = dt/3 lam' + dt/2 ub3,
+ * kb1 = dt/6 lam' + dt/2 ub2:  lam_n = lam' + ub1 + ub2 + ub3 + ub4. ws: at least
+ * cosmos_adjoint_workspace_bytes. lam_n must not alias u_n or lam_np1. */
+int cosmos_adjoint_step(const cosmos_grid* grid, const cosmos_params* params, double t, double dt,
+                        const double* u_n, const double* lam_np1, double* lam_n, void* ws, void* stream);
+
 /* Batched form: many independent runs advanced together, one persistent launch per RK4 stage
  * for all of them (work items = (run, 16x4x4 brick)). Run r has a cubic periodic grid of n[r]^3
  * points (n[r] divisible by 16) and box L[r]; its state (25 * n[r]^3 doubles, layout as above)

@@ -84,6 +84,7 @@ def lib():
             "oracle_splitmix64": [u64, u64],
             "oracle_stencil": [P, P, P, i32, i32, i32, i32, i32, i32, P, f64, P],
             "oracle_gamma_constraint": [P, P, P, P],
+            "oracle_point_rhs_vjp": [P, P, f64, P, f64, P, P, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -334,3 +335,16 @@ def gamma_constraint(s: Setup, u):
     out = np.empty(2)
     _check(lib().oracle_gamma_constraint(_p(n), _p(L), _p(u), _p(out)), "oracle_gamma_constraint")
     return float(out[0]), float(out[1])
+
+
+def point_rhs_vjp(s: Setup, d: dict, Et: float, St, rbar, t: float = 0.0):
+    """Reverse mode (tape) of the pointwise right-hand side: adjoints of the packed
+    inputs (GEOMIN_LAYOUT order) followed by those of Et and St."""
+    _, _, prm, iprm = s.arrays()
+    n = lib().oracle_geomin_size()
+    out = np.empty(n + 4)
+    St = np.ascontiguousarray(St, dtype=np.float64)
+    rbar = np.ascontiguousarray(rbar, dtype=np.float64)
+    _check(lib().oracle_point_rhs_vjp(_p(prm), _p(iprm), t, _p(pack_geomin(d)), Et, _p(St), _p(rbar), _p(out)),
+           "oracle_point_rhs_vjp")
+    return out

@@ -317,6 +317,66 @@ int oracle_point_rhs(const double* prm, const int* iprm, double t, const double*
   return fail ? 1 : 0;
 }
 
+// Reverse mode of the pointwise right-hand side (rhs_point) at one point:
+// given rbar[25], returns the adjoints of the packed GeomIn inputs (size
+// oracle_geomin_size()) followed by those of Et and St[3].
+int oracle_point_rhs_vjp(const double* prm, const int* iprm, double t, const double* packed, double Et,
+                         const double* St, const double* rbar, double* out) {
+  Params p;
+  p.w = prm[0];
+  p.H0 = prm[1];
+  p.eta = prm[2];
+  p.ko_eps = prm[3];
+  p.lapse_bg = iprm[0];
+  p.evolve_shift = iprm[1];
+  const int n = oracle_geomin_size();
+  g_tape.clear();
+  std::vector<Rev> x(n + 4);
+  for (int q = 0; q < n; ++q) x[q] = Rev::input(packed[q]);
+  x[n] = Rev::input(Et);
+  for (int c = 0; c < 3; ++c) x[n + 1 + c] = Rev::input(St[c]);
+  // unpack into a GeomIn<Rev> in the packed order
+  std::vector<double> tmp(n);
+  GeomIn<Rev> in;
+  {
+    const Rev* q = x.data();
+    in.chi = *q++;
+    for (int s = 0; s < 6; ++s) in.gt[s] = *q++;
+    in.K = *q++;
+    for (int s = 0; s < 6; ++s) in.At[s] = *q++;
+    for (int s = 0; s < 3; ++s) in.Gam[s] = *q++;
+    in.alpha = *q++;
+    for (int s = 0; s < 3; ++s) in.beta[s] = *q++;
+    for (int s = 0; s < 3; ++s) in.dchi[s] = *q++;
+    for (int s = 0; s < 6; ++s) in.d2chi[s] = *q++;
+    for (int s = 0; s < 6; ++s)
+      for (int a = 0; a < 3; ++a) in.dgt[s][a] = *q++;
+    for (int s = 0; s < 6; ++s)
+      for (int c = 0; c < 6; ++c) in.d2gt[s][c] = *q++;
+    for (int s = 0; s < 3; ++s)
+      for (int c = 0; c < 3; ++c) in.dGam[s][c] = *q++;
+    for (int s = 0; s < 3; ++s) in.dalpha[s] = *q++;
+    for (int s = 0; s < 6; ++s) in.d2alpha[s] = *q++;
+    for (int s = 0; s < 3; ++s)
+      for (int c = 0; c < 3; ++c) in.dbeta[s][c] = *q++;
+    for (int s = 0; s < 3; ++s)
+      for (int c = 0; c < 6; ++c) in.d2beta[s][c] = *q++;
+    for (int s = 0; s < 3; ++s) in.dK[s] = *q++;
+    for (int s = 0; s < 6; ++s)
+      for (int c = 0; c < 3; ++c) in.dAt[s][c] = *q++;
+  }
+  Rev r[NF];
+  Rev St3[3] = {x[n + 1], x[n + 2], x[n + 3]};
+  rhs_point(p, t, in, x[n], St3, r);
+  g_tape.adj.assign((size_t)g_tape.size(), 0.0);
+  for (int f = 0; f < NF; ++f)
+    if (r[f].id >= 0) g_tape.adj[(size_t)r[f].id] += rbar[f];
+  g_tape.sweep();
+  for (int q = 0; q < n + 4; ++q) out[q] = g_tape.adj[(size_t)x[q].id];
+  g_tape.clear();
+  return 0;
+}
+
 // Primitive recovery at one point. out: E, S[3], S2, P, invX, Sup[3], Strace
 int oracle_matter_point(double w, double chi, const double* gt, double Et, const double* St, double* out) {
   Params p;

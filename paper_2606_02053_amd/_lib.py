@@ -67,6 +67,7 @@ def _load():
         "cosmos_constraints": ([G, Pr, P, P, P, P, P, P], i32),
         "cosmos_adjoint_step": ([G, Pr, f64, f64, P, P, P, P, P], i32),
         "cosmos_adjoint_workspace_bytes": ([G], sz),
+        "cosmos_rhs_vjp": ([G, Pr, f64, P, P, P, P, P], i32),
         "cosmos_batch_workspace_bytes": ([B], sz),
         "cosmos_batch_setup": ([B, Pr, P, P], i32),
         "cosmos_rk4_step_batched": ([B, Pr, P, P, P, P, P], i32),
@@ -197,6 +198,14 @@ def cosmos_adjoint_step(grid, params, t: float, dt: float, u_n, lam_np1, lam_n, 
                                    _dev(lam_np1, "lam_np1", N), _dev(lam_n, "lam_n", N),
                                    _dev(ws, "ws", cosmos_adjoint_workspace_bytes(grid), dtype=torch.uint8),
                                    _stream(stream)))
+
+
+def cosmos_rhs_vjp(grid, params, t: float, u, kbar, ubar, ws, stream=None):
+    N = NFIELDS * npts(grid)
+    _check(lib.cosmos_rhs_vjp(ctypes.byref(grid), ctypes.byref(params), float(t), _dev(u, "u", N),
+                              _dev(kbar, "kbar", N), _dev(ubar, "ubar", N),
+                              _dev(ws, "ws", cosmos_adjoint_workspace_bytes(grid), dtype=torch.uint8),
+                              _stream(stream)))
 
 
 def cosmos_abi_version() -> int:

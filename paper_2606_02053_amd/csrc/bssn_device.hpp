@@ -210,7 +210,7 @@ __device__ __forceinline__ double field_advko(const double* F, const Nbr& nb0, c
 }
 
 // Contraction g^{ab} X_{ab} of two symmetric tensors in 6-component storage.
-__device__ __forceinline__ double contract_sym(const double gi[6], const double X[6]) {
+__host__ __device__ __forceinline__ double contract_sym(const double gi[6], const double X[6]) {
   return (gi[0] * X[0] + gi[3] * X[3] + gi[5] * X[5]) + 2.0 * (gi[1] * X[1] + gi[2] * X[2] + gi[4] * X[4]);
 }
 

@@ -17,6 +17,7 @@
 #include "init_device.hpp"
 #include "constraints_device.hpp"
 #include "bssn_lds.hpp"
+#include "adjoint_point.hpp"
 
 using namespace cosmos;
 
@@ -367,3 +368,4 @@ int cosmos_constraints(const cosmos_grid* grid, const cosmos_params* params, con
 }  // extern "C"
 
 #include "batch.hip.inc"
+#include "adjoint.hip.inc"
