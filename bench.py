@@ -20,10 +20,16 @@ Extra modes:
   --copy-probe   only a plain device-to-device copy of known size (calibrates
                  rocprofv3 FETCH_SIZE / WRITE_SIZE counters)
   --no-cpu       skip the CPU baseline leg
+  --config K     fixed configuration (lds|direct:BXxBYxBZ:xcd|linear) instead of the autotuner
+
+roofline.traffic is the HBM bytes per stage launch from committed rocprofv3 counters
+(profiles/k_bssn_stage_lds_256cubed_traffic.txt), reported only while the stage-kernel
+sources, the configuration and the grid are the ones those counters were taken on.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -39,6 +45,10 @@ FP64_PEAK_TFLOPS = 78.6
 #  stage 4 reads U4, acc and writes u): 16 * 25 * 8
 BYTES_PER_POINT_STEP = 3200.0
 LAUNCHES_PER_STEP = 4
+HERE = os.path.dirname(os.path.abspath(__file__))
+# sources that define the stage kernel; the committed counters apply only while they are unchanged
+STAGE_SOURCES = ["bssn_device.hpp", "bssn_lds.hpp", "cosmos.hip"]
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "k_bssn_stage_lds_256cubed_traffic.txt")
 
 
 def parse():
@@ -54,7 +64,46 @@ def parse():
     ap.add_argument("--batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=30, help="timed steps (runs/s is scaled to 300 steps)")
     ap.add_argument("--adjoint", action="store_true")
+    ap.add_argument("--config", default=None,
+                    help="fixed kernel configuration instead of autotuning, e.g. lds:16x4x4:linear or direct:32x4x2:xcd")
+    ap.add_argument("--source-hash", action="store_true", help="print the stage-kernel source hash and exit")
     return ap.parse_args()
+
+
+def parse_config(text):
+    kind, tile, order = text.split(":")
+    kv = {"lds": 0, "direct": 1}[kind]
+    return kv, tuple(int(x) for x in tile.split("x")), {"xcd": 0, "linear": 1}[order]
+
+
+def config_name(kv, tile, order):
+    return f"{'lds' if kv == 0 else 'direct'}:{'x'.join(map(str, tile))}:{'xcd' if order == 0 else 'linear'}"
+
+
+def stage_source_hash():
+    h = hashlib.sha256()
+    for name in STAGE_SOURCES:
+        with open(os.path.join(HERE, "paper_2606_02053_amd", "csrc", name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(cfg, npts):
+    """HBM bytes per stage launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    counters (KiB per dispatch, averaged over the four RK4 stages), each scaled by
+    what the same counter reads for a plain device copy of known size. None when the
+    counters were taken on other kernel sources, another configuration or grid."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith(("#", " ", "|")))
+        kv = {k.strip(): v.strip() for k, v in kv.items()}
+        if kv["source_hash"] != stage_source_hash() or kv["config"] != cfg or int(kv["points"]) != npts:
+            return None
+        fetch = float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_scale"])
+        write = float(kv["write_kib_per_dispatch"]) * float(kv["write_scale"])
+        return round((fetch + write) * 1024.0)
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def copy_probe():
@@ -187,6 +236,9 @@ def main():
         print(f"bench.py runs on exactly one GPU (this build has no multi-GPU path); got --gpus {a.gpus}",
               file=sys.stderr)
         sys.exit(2)
+    if a.source_hash:
+        print(stage_source_hash())
+        return
     if a.copy_probe:
         copy_probe()
         return
@@ -203,7 +255,9 @@ def main():
     sol.init(mu=0.6, sigma=2.0)
     dt = sol.default_dt()
     kv, tile, order = 0, (16, 4, 4), 0
-    if not a.no_tune:  # untimed: picks kernel variant and brick (cached per arch and grid)
+    if a.config:
+        kv, tile, order = parse_config(a.config)
+    elif not a.no_tune:  # untimed: picks kernel variant and brick (cached per arch and grid)
         (kv, tile, order), _ = autotune.tune(sol.grid, sol.params, sol.u, dt)
     sol.params = autotune.with_tile(sol.params, kv, tile, order)
     for _ in range(a.warmup):
@@ -228,8 +282,10 @@ def main():
     achieved = bytes_launch / launch_s / 1e9
     fl = flops_per_point_step()
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "k_bssn_stage", "avg_launch_ms": round(launch_s * 1e3, 4),
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(config_name(kv, tile, order), npts),
+            "traffic_unit": "bytes per launch", "algorithmic_bytes_per_launch": round(bytes_launch),
+            "kernel": f"k_bssn_stage_lds<{tile[0]},{tile[1]},{tile[2]}>" if kv == 0 else "k_bssn_stage",
+            "avg_launch_ms": round(launch_s * 1e3, 4),
             "fp64_tflops_algorithmic": round(fl * npts * a.steps / (ms / 1e3) / 1e12, 2),
             "fp64_frac": round(fl * npts * a.steps / (ms / 1e3) / 1e12 / FP64_PEAK_TFLOPS, 4)}
     out = {"metric": METRIC, "value": value, "unit": "point-updates/s", "n_gpus": 1, "steps": a.steps,
@@ -239,6 +295,7 @@ def main():
                                   f"Gaussian zeta mu = 0.6 sigma = 2.0, CFL 0.25, KO eps 0.1",
                       "grid": n, "dt": dt, "kernel_variant": "lds-staged" if kv == 0 else "direct",
                       "tile": list(tile), "tile_order": "xcd" if order == 0 else "linear",
+                      "kernel_config": config_name(kv, tile, order),
                       "parallelism": "single GPU"},
            "roofline": roof}
     if not a.no_cpu:

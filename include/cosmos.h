@@ -68,7 +68,8 @@ enum cosmos_field {
   COSMOS_ALPHA = 17, COSMOS_BETA = 18, COSMOS_ET = 21, COSMOS_ST = 22
 };
 
-/* Periodic box: n[a] points and length L[a] along axis a (x, y, z). */
+/* Periodic box: n[a] points and length L[a] along axis a (x, y, z); 8 <= n[a] <= 2048 and
+ * n[0] n[1] n[2] < 2^29 (the kernels address a field with 32-bit byte offsets). */
 typedef struct {
   int32_t n[3];
   double L[3];
@@ -111,9 +112,10 @@ typedef struct {
   int32_t profile, density_mode;
 } cosmos_init;
 
-/* Bytes of device workspace needed by cosmos_rhs / cosmos_rk4_step / cosmos_constraints /
- * cosmos_adjoint_step on this grid (3 state-sized stage buffers, the status counters and the
- * reduction and adjoint scratch). Returns 0 for an invalid grid. */
+/* Bytes of device workspace needed by cosmos_rhs / cosmos_rk4_step / cosmos_constraints on this
+ * grid: the status counters, the reduction partials, 3 state-sized RK4 buffers and 12 * N3
+ * doubles for the fluid fluxes that every stage forms in a pointwise pre-pass. Returns 0 for an
+ * invalid grid. */
 size_t cosmos_workspace_bytes(const cosmos_grid* grid);
 
 /* Zero the status counters held in the workspace (asynchronous). */

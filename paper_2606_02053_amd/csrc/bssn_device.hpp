@@ -47,6 +47,7 @@ struct DevParams {
   double i12h2[3];  // 1 / (12 h_a^2)
   double i144[3];   // 1 / (144 h_a h_b) for pairs (0,1), (0,2), (1,2)
   double iko[3];    // ko_eps / (64 h_a)
+  double i24h[3];   // 1 / (24 h_a)
 };
 
 // Brick decomposition of the grid for the stage kernel: a workgroup of
@@ -110,14 +111,37 @@ __device__ __forceinline__ double op_d1(const double v[7], double i12h) {
 __device__ __forceinline__ double op_d2(const double v[7], double i12h2) {
   return ((16.0 * (v[2] + v[4]) - (v[1] + v[5])) - 30.0 * v[3]) * i12h2;
 }
-// beta * (one-sided derivative chosen by the sign of beta)
-__device__ __forceinline__ double op_adv(const double v[7], double beta, double i12h) {
-  double d = (beta > 0.0) ? (((v[6] - 3.0 * v[2]) - 10.0 * v[3]) + (18.0 * v[4] - 6.0 * v[5]))
-                          : (((3.0 * v[4] - v[0]) + 10.0 * v[3]) + (6.0 * v[1] - 18.0 * v[2]));
-  return beta * (d * i12h);
-}
 __device__ __forceinline__ double op_ko(const double v[7], double iko) {
   return (((v[0] + v[6]) - 6.0 * (v[1] + v[5])) + (15.0 * (v[2] + v[4]) - 20.0 * v[3])) * iko;
+}
+
+// Every operator of one stencil line v[o] = f(x + (o - 3) h) in one pass, branch
+// free. With t_k = f_k - f_-k and s_k = f_k + f_-k:
+//   D1 = (8 t1 - t2) / 12h,   D2 = (16 s1 - s2 - 30 f0) / 12h^2,
+// and the lopsided derivatives of the advection term split into a centred odd part
+// and a multiple of the 6th difference D6 that the KO operator also uses,
+//   U+ (beta > 0), U- (beta <= 0) = (t3 - 6 t2 + 21 t1) / 24h +/- D6 / 24h,
+//   D6 = s3 - 6 s2 + 15 s1 - 20 f0,
+// so beta U + KO = beta (t3 - 6 t2 + 21 t1) / 24h + (|beta| / 24h + eps / 64h) D6
+// (equal to the textbook branch form up to rounding, also at beta = 0).
+template <bool SECOND, bool ADV, bool KO>
+__device__ __forceinline__ void op_line(const double v[7], double beta, double i12h, double i12h2, double i24h,
+                                        double iko, double& d1, double& d2, double& advko) {
+  const double t1 = v[4] - v[2], t2 = v[5] - v[1];
+  d1 = (8.0 * t1 - t2) * i12h;
+  const double s1 = v[4] + v[2], s2 = v[5] + v[1];
+  if (SECOND) d2 = ((16.0 * s1 - s2) - 30.0 * v[3]) * i12h2;
+  if (ADV || KO) {
+    const double d6 = ((v[6] + v[0]) - 6.0 * s2) + (15.0 * s1 - 20.0 * v[3]);
+    double cd6 = 0.0;
+    if (ADV) {
+      const double odd = ((v[6] - v[0]) - 6.0 * t2) + 21.0 * t1;
+      advko += (beta * i24h) * odd;
+      cd6 = fabs(beta) * i24h;
+    }
+    if (KO) cd6 += iko;
+    advko += cd6 * d6;
+  }
 }
 
 // Load f at linear index q: uniform base pointer + zero-extended 32-bit byte offset
@@ -179,10 +203,9 @@ __device__ __forceinline__ void field_derivs(const double* F, const Nbr& nb0, co
   for (int a = 0; a < 3; ++a) {
     double v[7];
     load_line(F, nb, a, v);
-    r.d1[a] = op_d1(v, P.i12h[a]);
-    if (SECOND) r.d2[S(a, a)] = op_d2(v, P.i12h2[a]);
-    if (ADV) acc += op_adv(v, beta[a], P.i12h[a]);
-    if (KO) acc += op_ko(v, P.iko[a]);
+    double d2 = 0.0;
+    op_line<SECOND, ADV, KO>(v, beta[a], P.i12h[a], P.i12h2[a], P.i24h[a], P.iko[a], r.d1[a], d2, acc);
+    if (SECOND) r.d2[S(a, a)] = d2;
   }
   r.advko = acc;
   if (SECOND) {
@@ -202,9 +225,8 @@ __device__ __forceinline__ double field_advko(const double* F, const Nbr& nb0, c
   for (int a = 0; a < 3; ++a) {
     double v[7];
     load_line(F, nb, a, v);
-    d1[a] = op_d1(v, P.i12h[a]);
-    if (ADV) acc += op_adv(v, beta[a], P.i12h[a]);
-    acc += op_ko(v, P.iko[a]);
+    double d2 = 0.0;
+    op_line<false, ADV, true>(v, beta[a], P.i12h[a], P.i12h2[a], P.i24h[a], P.iko[a], d1[a], d2, acc);
   }
   return acc;
 }
@@ -264,26 +286,67 @@ __device__ __forceinline__ bool recover(double w, double chi, const double gi[6]
   return fail;
 }
 
-// Flux of (Et, St_x, St_y, St_z) along axis a at a grid point given by linear index q:
+// Fluxes of (Et, St_x, St_y, St_z) along the three axes at grid point c, stored
+// field-major as F[(4 a + q) fs + c] (12 arrays of fs doubles):
 //   F^a_E = chi^(-3/2) (alpha S^a - beta^a E),
 //   F^a_i = chi^(-3/2) (alpha (S^a S_i / X + P delta^a_i) - beta^a S_i).
-__device__ __forceinline__ void flux_at(const double* U, size_t fs, int q, int a, double w, double Fo[4]) {
-  const double chi = ldq(U + F_CHI * fs, q);
+// Formed once per point per stage (a pointwise pre-pass), so the stage kernel
+// takes the divergence from 4 loads per flux component instead of recovering
+// the primitives at all 12 axis neighbours.
+__device__ __forceinline__ void fluid_flux_point(const double* U, size_t fs, int c, double w, double* F) {
+  const double chi = ldq(U + F_CHI * fs, c);
   double g[6], gi[6], St[3];
 #pragma unroll
-  for (int s = 0; s < 6; ++s) g[s] = ldq(U + (F_GT + s) * fs, q);
+  for (int s = 0; s < 6; ++s) g[s] = ldq(U + (F_GT + s) * fs, c);
 #pragma unroll
-  for (int i = 0; i < 3; ++i) St[i] = ldq(U + (F_ST + i) * fs, q);
+  for (int i = 0; i < 3; ++i) St[i] = ldq(U + (F_ST + i) * fs, c);
   inv_sym(g, gi);
   Fluid fl;
-  recover(w, chi, gi, ldq(U + F_ET * fs, q), St, fl);
-  const double alpha = ldq(U + F_ALP * fs, q);
-  const double ba = ldq(U + (F_BET + a) * fs, q);
+  recover(w, chi, gi, ldq(U + F_ET * fs, c), St, fl);
+  const double alpha = ldq(U + F_ALP * fs, c);
   const double im32 = 1.0 / (chi * sqrt(chi));
-  Fo[0] = im32 * (alpha * fl.Sup[a] - ba * fl.E);
-  const double t = alpha * fl.Sup[a] * fl.invX;
 #pragma unroll
-  for (int i = 0; i < 3; ++i) Fo[1 + i] = im32 * ((t * fl.S[i] + (i == a ? alpha * fl.P : 0.0)) - ba * fl.S[i]);
+  for (int a = 0; a < 3; ++a) {
+    const double ba = ldq(U + (F_BET + a) * fs, c);
+    stq(F + (4 * a) * fs, c, im32 * (alpha * fl.Sup[a] - ba * fl.E));
+    const double t = alpha * fl.Sup[a] * fl.invX;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      stq(F + (4 * a + 1 + i) * fs, c, im32 * ((t * fl.S[i] + (i == a ? alpha * fl.P : 0.0)) - ba * fl.S[i]));
+  }
+}
+
+// Divergence of the fluxes at point c, div[q] = sum_a D1_a F^a_q (4th-order centred),
+// in two steps per axis so that callers can issue the loads early:
+// flux_axis_load fetches F^a_q at the four axis neighbours, flux_axis_add
+// accumulates their centred difference.
+__device__ __forceinline__ void flux_axis_load(const double* F, size_t fs, int c, const Nbr& nb, int a,
+                                               double v[4][4]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const double* Fa = F + (4 * a + q) * fs;
+    v[q][0] = ldq(Fa, c + nb.d[a][1]);
+    v[q][1] = ldq(Fa, c + nb.d[a][2]);
+    v[q][2] = ldq(Fa, c + nb.d[a][4]);
+    v[q][3] = ldq(Fa, c + nb.d[a][5]);
+  }
+}
+
+__device__ __forceinline__ void flux_axis_add(const double v[4][4], double i12h, double div[4]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) div[q] += ((v[q][0] - v[q][3]) + 8.0 * (v[q][2] - v[q][1])) * i12h;
+}
+
+__device__ __forceinline__ void flux_divergence(const double* F, size_t fs, int c, const Nbr& nb, const DevParams& P,
+                                                double div[4]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) div[q] = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double v[4][4];
+    flux_axis_load(F, fs, c, nb, a, v);
+    flux_axis_add(v, P.i12h[a], div);
+  }
 }
 
 // Conformal Christoffels from d gt: Gt_kij = 1/2 (d_i gt_kj + d_j gt_ki - d_k gt_ij)
@@ -383,9 +446,11 @@ __device__ __forceinline__ double rec_Sjk(const Rec& R, double chi, int s) {
 }
 
 // Sink interface: put(f, value) receives the final right-hand side of field f at this point.
+// F holds the fluid fluxes of U (fluid_flux_point) at every grid point.
 template <class Sink>
-__device__ __forceinline__ void bssn_rhs_stream(const double* U, size_t fs, const Nbr& nb, const DevParams& P,
-                                                double t, const Rec& R, Sink& sink, bool& prim_fail) {
+__device__ __forceinline__ void bssn_rhs_stream(const double* U, const double* F, size_t fs, const Nbr& nb,
+                                                const DevParams& P, double t, const Rec& R, Sink& sink,
+                                                bool& prim_fail) {
   const int c = nb.base;
   // centre values kept in registers for the whole evaluation
   const double chi = ldq(U + F_CHI * fs, c);
@@ -652,21 +717,9 @@ __device__ __forceinline__ void bssn_rhs_stream(const double* U, size_t fs, cons
   }
 
   // ---- fluid: flux divergence, geometric sources, dissipation
-  double div[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    double Fm2[4], Fm1[4], Fp1[4], Fp2[4];
-    COSMOS_PHASE();
-    flux_at(U, fs, c + nb.d[a][1], a, P.w, Fm2);
-    COSMOS_PHASE();
-    flux_at(U, fs, c + nb.d[a][2], a, P.w, Fm1);
-    COSMOS_PHASE();
-    flux_at(U, fs, c + nb.d[a][4], a, P.w, Fp1);
-    COSMOS_PHASE();
-    flux_at(U, fs, c + nb.d[a][5], a, P.w, Fp2);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) div[q] += ((Fm2[q] - Fp2[q]) + 8.0 * (Fp1[q] - Fm1[q])) * P.i12h[a];
-  }
+  double div[4];
+  COSMOS_PHASE();
+  flux_divergence(F, fs, c, nb, P, div);
   const double nbeta[3] = {0.0, 0.0, 0.0};
   const double im32 = 1.0 / (chi * sqrt(chi));
   COSMOS_PHASE();

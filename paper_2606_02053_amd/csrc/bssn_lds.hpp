@@ -7,12 +7,17 @@
 // compile-time-offset reads. The copy of the next field is issued before the
 // current field's arithmetic and written to the second LDS buffer after it, so
 // its latency hides behind the FP64 work. Long-lived per-point intermediates
-// live in a per-thread LDS record (R3_* slots).
+// (R3_* slots) stay in registers: one wave per SIMD is resident anyway (the
+// fused point evaluation needs ~300 registers), so the VGPR + AGPR file holds
+// them, and LDS only carries the two halo buffers. The fluid fluxes come from a
+// pointwise pre-pass (fluid_flux_point) and are differentiated from global loads.
 //
 // The arithmetic is that of bssn_rhs_stream in bssn_device.hpp (same
 // operations in the same order); only where the operands come from differs, so
-// the two variants agree up to the compiler's FMA-contraction choices.
+// the two variants agree to rounding.
 #pragma once
+#include <type_traits>
+
 #include "bssn_device.hpp"
 
 namespace cosmos {
@@ -39,8 +44,9 @@ struct Brick {
   static constexpr int HX = BX + 6, HY = BY + 6, HZ = BZ + 6;
   static constexpr int NH = HX * HY * HZ;       // halo-box points
   static constexpr int NQ = (NH + 255) / 256;   // loads per thread per field
+  static constexpr int NP = NQ * 256;            // padded LDS buffer: every thread copies NQ points
   static constexpr int SY = HX, SZ = HX * HY;   // LDS strides
-  static constexpr int LDS_DOUBLES = R3_COUNT * 256 + 2 * NH;
+  static constexpr int LDS_DOUBLES = 2 * NP;       // two halo buffers
   static_assert(BX * BY * BZ == 256, "one point per thread");
   static_assert(LDS_DOUBLES * 8 <= 160 * 1024, "LDS budget");
 };
@@ -74,10 +80,9 @@ __device__ __forceinline__ void lds_derivs(const double* c, const DevParams& P, 
   for (int a = 0; a < 3; ++a) {
     double v[7];
     lds_line<B>(c, a, v);
-    r.d1[a] = op_d1(v, P.i12h[a]);
-    if (SECOND) r.d2[S(a, a)] = op_d2(v, P.i12h2[a]);
-    if (ADV) acc += op_adv(v, beta[a], P.i12h[a]);
-    if (KO) acc += op_ko(v, P.iko[a]);
+    double d2 = 0.0;
+    op_line<SECOND, ADV, KO>(v, beta[a], P.i12h[a], P.i12h2[a], P.i24h[a], P.iko[a], r.d1[a], d2, acc);
+    if (SECOND) r.d2[S(a, a)] = d2;
   }
   r.advko = acc;
   if (SECOND) {
@@ -93,6 +98,17 @@ constexpr int kStageOrder[NF] = {F_BET,    F_BET + 1, F_BET + 2, F_GT,     F_GT 
                                  F_K,      F_AT,      F_AT + 1,  F_AT + 2, F_AT + 3, F_AT + 4, F_AT + 5,
                                  F_ET,     F_ST,      F_ST + 1,  F_ST + 2};
 constexpr int kPrefetch = 3;  // fields in flight ahead of the one being processed
+
+// Fields whose right-hand side becomes final in each phase, in the order they are
+// handed to the sink (the Gt^i right-hand sides complete in the trace-K phase).
+constexpr int kPutCount[NF] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 0, 0, 0, 1, 1, 4, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1};
+constexpr int kPutField[NF][4] = {
+    {F_BET}, {F_BET + 1}, {F_BET + 2}, {F_GT}, {F_GT + 1}, {F_GT + 2}, {F_GT + 3}, {F_GT + 4}, {F_GT + 5},
+    {}, {}, {}, {F_CHI}, {F_ALP}, {F_K, F_GAM, F_GAM + 1, F_GAM + 2},
+    {F_AT}, {F_AT + 1}, {F_AT + 2}, {F_AT + 3}, {F_AT + 4}, {F_AT + 5}, {F_ET}, {F_ST}, {F_ST + 1}, {F_ST + 2}};
+// The RK4 epilogue operands of phase p's outputs (u_n and/or acc at the point) are
+// loaded kEpiAhead phases earlier: they come from HBM, whose latency exceeds one phase.
+constexpr int kEpiAhead = 3;
 
 // Cooperative copy of the fields' halo boxes: a ring of kPrefetch register
 // sets (slot 0 = next field to commit to LDS), rotated with constant indices.
@@ -119,12 +135,12 @@ struct HaloCopy {
   __device__ __forceinline__ void fetch(const double* F) {
 #pragma unroll
     for (int q = 0; q < B::NQ; ++q)
-      if (threadIdx.x + 256 * q < B::NH) v[SLOT][q] = ldq(F, goff[q]);
+      v[SLOT][q] = ldq(F, goff[q]);
   }
   __device__ __forceinline__ void commit_and_rotate(double* buf) {
 #pragma unroll
     for (int q = 0; q < B::NQ; ++q)
-      if (threadIdx.x + 256 * q < B::NH) buf[threadIdx.x + 256 * q] = v[0][q];
+      buf[threadIdx.x + 256 * q] = v[0][q];
 #pragma unroll
     for (int d = 0; d + 1 < kPrefetch; ++d)
 #pragma unroll
@@ -136,10 +152,13 @@ struct HaloCopy {
 // of the workgroup must call it (it contains barriers); `active` marks threads
 // whose point lies inside the grid.
 template <class B, class Sink>
-__device__ __forceinline__ void bssn_rhs_lds(const double* U, size_t fs, const DevParams& P, double t, int i0, int j0,
-                                             int k0, int c, bool active, double* rec_base, double* buf0, double* buf1,
-                                             Sink& sink, bool& prim_fail) {
-  const Rec R{rec_base + threadIdx.x, 256};
+__device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, size_t fs, const DevParams& P, double t,
+                                             int i0, int j0, int k0, int c, bool active,
+                                             double* buf0, double* buf1, Sink& sink, bool& prim_fail) {
+  struct {  // the per-point record, indexed by compile-time constants only (kept in registers)
+    double v[R3_COUNT];
+    __device__ __forceinline__ double& operator[](int k) { return v[k]; }
+  } R;
   const int lx = threadIdx.x % (B::HX - 6), ly = (threadIdx.x / (B::HX - 6)) % (B::HY - 6),
             lz = threadIdx.x / ((B::HX - 6) * (B::HY - 6));
   const int cidx = (lx + 3) + B::SY * ((ly + 3) + B::HY * (lz + 3));
@@ -151,11 +170,28 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, size_t fs, const D
   const double chi = ldq(U + F_CHI * fs, cc);
   const double K = ldq(U + F_K * fs, cc);
   const double alpha = ldq(U + F_ALP * fs, cc);
-  double gt[6], beta[3];
+  double gt[6], beta[3], At[6], Gam[3];
 #pragma unroll
   for (int s = 0; s < 6; ++s) gt[s] = ldq(U + (F_GT + s) * fs, cc);
 #pragma unroll
   for (int q = 0; q < 3; ++q) beta[q] = ldq(U + (F_BET + q) * fs, cc);
+#pragma unroll
+  for (int s = 0; s < 6; ++s) At[s] = ldq(U + (F_AT + s) * fs, cc);
+#pragma unroll
+  for (int q = 0; q < 3; ++q) Gam[q] = ldq(U + (F_GAM + q) * fs, cc);
+
+  // ring of epilogue operands: slot d holds those of phase `phase + d`
+  typename Sink::Pre ep[kEpiAhead + 1][4];
+  auto epi_load = [&](int ph, auto slot) {
+    if (ph < NF) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (k < kPutCount[ph]) ep[decltype(slot)::value][k] = sink.preload(kPutField[ph][k]);
+    }
+  };
+  epi_load(0, std::integral_constant<int, 0>());
+  epi_load(1, std::integral_constant<int, 1>());
+  epi_load(2, std::integral_constant<int, 2>());
 
   hc.template fetch<0>(U + kStageOrder[0] * fs);
   hc.template fetch<1>(U + kStageOrder[1] * fs);
@@ -189,8 +225,13 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, size_t fs, const D
   auto cur = [&]() -> const double* { return ((phase & 1) ? buf1 : buf0) + cidx; };
   auto prefetch = [&]() {
     if (phase + kPrefetch < NF) hc.template fetch<kPrefetch - 1>(U + kStageOrder[phase + kPrefetch] * fs);
+    epi_load(phase + kEpiAhead, std::integral_constant<int, kEpiAhead>());
   };
   auto advance = [&](int) {
+#pragma unroll
+    for (int d = 0; d < kEpiAhead; ++d)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) ep[d][k] = ep[d + 1][k];
     if (phase + 1 < NF) hc.commit_and_rotate((phase & 1) ? buf0 : buf1);
     __syncthreads();
     ++phase;
@@ -218,8 +259,8 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, size_t fs, const D
         R[R3_RG + l] +=
             (gi[S(l, 0)] * d.d2[S(0, i)] + gi[S(l, 1)] * d.d2[S(1, i)] + gi[S(l, 2)] * d.d2[S(2, i)]) * (1.0 / 3.0);
       double r = 0.0;
-      if (P.evolve_shift) r = d.advko + (0.75 * ldq(U + (F_GAM + i) * fs, c) - P.eta * beta[i]);
-      sink.put(F_BET + i, r);
+      if (P.evolve_shift) r = d.advko + (0.75 * Gam[i] - P.eta * beta[i]);
+      sink.put(F_BET + i, r, ep[0][0]);
     }
     advance(0);
   }
@@ -250,8 +291,8 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, size_t fs, const D
 #pragma unroll
       for (int k = 0; k < 3; ++k) r += gt[S(i, k)] * db[k][j] + gt[S(j, k)] * db[k][i];
       r -= (2.0 / 3.0) * gt[s] * divb;
-      r -= 2.0 * alpha * ldq(U + (F_AT + s) * fs, c);
-      sink.put(F_GT + s, r);
+      r -= 2.0 * alpha * At[s];
+      sink.put(F_GT + s, r, ep[0][0]);
     }
     if (s == 5 && active) {  // connection and the quadratic Ricci terms (pure algebra)
       COSMOS_PHASE();
@@ -310,7 +351,7 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, size_t fs, const D
 #pragma unroll
     for (int a = 0; a < 3; ++a) R[R3_DCHI + a] = d.d1[a];
     const double divb = R[R3_DB + 0] + R[R3_DB + 4] + R[R3_DB + 8];
-    sink.put(F_CHI, d.advko + (2.0 / 3.0) * chi * (alpha * K - divb));
+    sink.put(F_CHI, d.advko + (2.0 / 3.0) * chi * (alpha * K - divb), ep[0][0]);
   }
   advance(0);
 
@@ -344,7 +385,7 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, size_t fs, const D
     }
     R[R3_D2A] = chi * contract_sym(gi, DDa);
     const double Kbg = P.lapse_bg ? -3.0 * P.H0 / (1.0 + 2.0 * P.H0 * t) : 0.0;
-    sink.put(F_ALP, d.advko - 2.0 * alpha * (K - Kbg));
+    sink.put(F_ALP, d.advko - 2.0 * alpha * (K - Kbg), ep[0][0]);
     const double ichi = 1.0 / chi;
     const double ix = R[R3_IX], pr = R[R3_P];
 #pragma unroll
@@ -360,12 +401,9 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, size_t fs, const D
   // ---- trace K, and the final Gt^i right-hand side
   prefetch();
   if (active) {
-    double gi[6], At[6];
+    double gi[6];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) {
-      gi[q] = R[R3_GI + q];
-      At[q] = ldq(U + (F_AT + q) * fs, c);
-    }
+    for (int q = 0; q < 6; ++q) gi[q] = R[R3_GI + q];
     FieldDerivs d;
     lds_derivs<B, false, true>(cur(), P, beta, d);
     double Amix[3][3];
@@ -384,7 +422,8 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, size_t fs, const D
 #pragma unroll
     for (int q = 0; q < 3; ++q) Sup[q] = S_up(q);
     const double Str = (Sup[0] * R[R3_S + 0] + Sup[1] * R[R3_S + 1] + Sup[2] * R[R3_S + 2]) * R[R3_IX] + 3.0 * R[R3_P];
-    sink.put(F_K, d.advko + (-R[R3_D2A] + alpha * (AA + K * K * (1.0 / 3.0)) + 4.0 * PI_D * alpha * (R[R3_E] + Str)));
+    sink.put(F_K, d.advko + (-R[R3_D2A] + alpha * (AA + K * K * (1.0 / 3.0)) + 4.0 * PI_D * alpha * (R[R3_E] + Str)),
+             ep[0][0]);
     // Gt^i: every remaining term
     const double divb = R[R3_DB + 0] + R[R3_DB + 4] + R[R3_DB + 8];
 #pragma unroll
@@ -409,21 +448,29 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, size_t fs, const D
       inner -= (1.5 / chi) * (Aup[S(i, 0)] * R[R3_DCHI + 0] + Aup[S(i, 1)] * R[R3_DCHI + 1] + Aup[S(i, 2)] * R[R3_DCHI + 2]);
       r += 2.0 * alpha * inner;
       r -= 16.0 * PI_D * alpha * (gi[S(i, 0)] * R[R3_S + 0] + gi[S(i, 1)] * R[R3_S + 1] + gi[S(i, 2)] * R[R3_S + 2]);
-      sink.put(F_GAM + i, r);
+      sink.put(F_GAM + i, r, ep[0][1 + i]);
     }
   }
   advance(0);
 
-  // ---- traceless extrinsic curvature
+  // ---- traceless extrinsic curvature. The flux-divergence loads of axis a are issued
+  // in At phase 3 + a and consumed one phase later, so their latency overlaps the algebra.
+  double div[4] = {0.0, 0.0, 0.0, 0.0}, fv[4][4];
+  Nbr fnb;
+  if (active) {
+    const int i = c % P.n[0], jk = c / P.n[0];
+    make_nbr(fnb, i, jk % P.n[1], jk / P.n[1], P.n);
+  }
 #pragma unroll
   for (int s = 0; s < 6; ++s) {
     prefetch();
     if (active) {
-      double gi[6], At[6], X[6], db[3][3];
+      if (s >= 4) flux_axis_add(fv, P.i12h[s - 4], div);
+      if (s >= 3) flux_axis_load(F, fs, c, fnb, s - 3, fv);
+      double gi[6], X[6], db[3][3];
 #pragma unroll
       for (int q = 0; q < 6; ++q) {
         gi[q] = R[R3_GI + q];
-        At[q] = ldq(U + (F_AT + q) * fs, c);
         X[q] = R[R3_RX + q];
       }
 #pragma unroll
@@ -441,42 +488,27 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, size_t fs, const D
       for (int k = 0; k < 3; ++k)
         AAij += At[S(i, k)] * (gi[S(k, 0)] * At[S(0, j)] + gi[S(k, 1)] * At[S(1, j)] + gi[S(k, 2)] * At[S(2, j)]);
       r += alpha * (K * At[s] - 2.0 * AAij);
-      sink.put(F_AT + s, r);
+      sink.put(F_AT + s, r, ep[0][0]);
     }
     advance(0);
   }
 
-  // ---- fluid: flux divergence (fluxes formed at the axis neighbours), sources, dissipation
+  // ---- fluid: flux divergence (fluxes from the pointwise pre-pass), sources, dissipation
   const double nbeta[3] = {0.0, 0.0, 0.0};
   const double im32 = 1.0 / (chi * sqrt(chi));
-  double div[4] = {0.0, 0.0, 0.0, 0.0};
   prefetch();
   if (active) {
-    Nbr nb;
-    const int i = c % P.n[0], jk = c / P.n[0];
-    make_nbr(nb, i, jk % P.n[1], jk / P.n[1], P.n);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      double Fm2[4], Fm1[4], Fp1[4], Fp2[4];
-      COSMOS_PHASE();  // the four neighbours of one axis are gathered together
-      flux_at(U, fs, c + nb.d[a][1], a, P.w, Fm2);
-      flux_at(U, fs, c + nb.d[a][2], a, P.w, Fm1);
-      flux_at(U, fs, c + nb.d[a][4], a, P.w, Fp1);
-      flux_at(U, fs, c + nb.d[a][5], a, P.w, Fp2);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) div[q] += ((Fm2[q] - Fp2[q]) + 8.0 * (Fp1[q] - Fm1[q])) * P.i12h[a];
-    }
-    COSMOS_PHASE();
+    flux_axis_add(fv, P.i12h[2], div);
     double KS = 0.0;
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
-      const double Kij = (ldq(U + (F_AT + s) * fs, c) + gt[s] * K * (1.0 / 3.0)) / chi;
+      const double Kij = (At[s] + gt[s] * K * (1.0 / 3.0)) / chi;
       KS += (s == 0 || s == 3 || s == 5 ? 1.0 : 2.0) * Kij * Sjk_at(s);
     }
     FieldDerivs d;
     lds_derivs<B, false, false>(cur(), P, nbeta, d);
     const double Sda = S_up(0) * R[R3_DAL + 0] + S_up(1) * R[R3_DAL + 1] + S_up(2) * R[R3_DAL + 2];
-    sink.put(F_ET, d.advko + (im32 * (alpha * KS - Sda) - div[0]));
+    sink.put(F_ET, d.advko + (im32 * (alpha * KS - Sda) - div[0]), ep[0][0]);
   }
   advance(0);
 #pragma unroll
@@ -492,7 +524,7 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, size_t fs, const D
                    (R[R3_S + 0] * R[R3_DB + 0 + i] + R[R3_S + 1] * R[R3_DB + 3 + i] + R[R3_S + 2] * R[R3_DB + 6 + i]);
       const double ichi = 1.0 / chi;
       src += 0.5 * alpha * (R[R3_SG + i] * ichi - sgt * R[R3_DCHI + i] * (ichi * ichi));
-      sink.put(F_ST + i, d.advko + (im32 * src - div[1 + i]));
+      sink.put(F_ST + i, d.advko + (im32 * src - div[1 + i]), ep[0][0]);
     }
     if (i < 2) advance(0);
   }

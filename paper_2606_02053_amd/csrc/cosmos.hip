@@ -41,21 +41,24 @@ static int set_error(int code, const char* fmt, ...) {
   } while (0)
 
 // ---------------------------------------------------------------- workspace layout
-// [status: 8 x int64 | reduction partials | acc | stage A | stage B]
+// [status: 8 x int64 | reduction partials | acc | stage A | stage B | fluid fluxes (12 fields)]
 namespace {
 constexpr size_t kAlign = 256;
 constexpr int kBlock = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t status, partials, acc, A, B, total;
+  size_t status, partials, acc, A, B, F, total;
 };
+constexpr int kFluxFields = 12;  // F^a_q, a = axis, q = (Et, St_x, St_y, St_z)
 
 bool grid_ok(const cosmos_grid* g) {
   if (!g) return false;
   for (int a = 0; a < 3; ++a)
     if (g->n[a] < 8 || g->n[a] > 2048 || !(g->L[a] > 0.0) || !std::isfinite(g->L[a])) return false;
-  return (int64_t)g->n[0] * g->n[1] * g->n[2] < (int64_t)1 << 31;
+  // per-field byte offsets are 32-bit in the kernels (8 * n0 n1 n2 < 2^32); 4 RK4 states of
+  // that size are 430 GB, beyond one GPU's HBM anyway
+  return (int64_t)g->n[0] * g->n[1] * g->n[2] < (int64_t)1 << 29;
 }
 
 size_t npts(const cosmos_grid* g) { return (size_t)g->n[0] * g->n[1] * g->n[2]; }
@@ -69,14 +72,15 @@ Layout layout(const cosmos_grid* g) {
   L.acc = align_up(L.partials + nblocks(g) * kRedRecord * sizeof(double));
   L.A = align_up(L.acc + state);
   L.B = align_up(L.A + state);
-  L.total = align_up(L.B + state);
+  L.F = align_up(L.B + state);
+  L.total = align_up(L.F + (size_t)kFluxFields * npts(g) * sizeof(double));
   return L;
 }
 
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
 int check_common(const cosmos_grid* g, const cosmos_params* p) {
-  if (!grid_ok(g)) return set_error(COSMOS_EINVAL, "invalid grid (need 8 <= n <= 2048, L > 0, n0*n1*n2 < 2^31)");
+  if (!grid_ok(g)) return set_error(COSMOS_EINVAL, "invalid grid (need 8 <= n <= 2048, L > 0, n0*n1*n2 < 2^29)");
   if (!p) return set_error(COSMOS_EINVAL, "params is NULL");
   if (!std::isfinite(p->w) || !std::isfinite(p->H0) || !std::isfinite(p->eta) || !std::isfinite(p->ko_eps) ||
       !(p->w > 0.0))
@@ -133,6 +137,7 @@ DevParams dev_params(const cosmos_grid* g, const cosmos_params* p) {
     d.i12h[a] = 1.0 / (12.0 * h[a]);
     d.i12h2[a] = 1.0 / (12.0 * h[a] * h[a]);
     d.iko[a] = p->ko_eps / (64.0 * h[a]);
+    d.i24h[a] = 1.0 / (24.0 * h[a]);
   }
   d.i144[0] = 1.0 / (144.0 * h[0] * h[1]);
   d.i144[1] = 1.0 / (144.0 * h[0] * h[2]);
@@ -142,43 +147,64 @@ DevParams dev_params(const cosmos_grid* g, const cosmos_params* p) {
 }  // namespace
 
 // ---------------------------------------------------------------- stage kernel
-// One kernel for every use of the right-hand side; `mode` (uniform) selects the epilogue:
+// One kernel for every use of the right-hand side; MODE (a template parameter, so
+// the epilogue has no run-time branches) selects what is done with f(U):
 // 0: dudt = f(U)
 // 1: first RK4 stage   acc = U + ca k,  out = U + cn k          (U = u_n)
 // 2: middle stages     acc += ca k,     out = u_n + cn k
 // 3: last stage        out = acc + ca k (out = u_n's buffer), non-finite / collapse counts
+template <int MODE>
 struct StageSink {
   const double* un;
   double* acc;
   double* out;
   size_t fs;
-  int c, mode;
+  int c;
   double ca, cn, acol;
   bool bad = false, coll = false;
-  __device__ __forceinline__ void put(int f, double r) {
+  // Epilogue operands of field f at this point (u_n and/or acc by mode), loaded
+  // ahead of the point's arithmetic so that their latency overlaps it.
+  struct Pre {
+    double u0, a0;
+  };
+  __device__ __forceinline__ Pre preload(int f) const {
     const size_t fo = (size_t)f * fs;  // uniform: field base offsets live in SGPRs
-    if (mode == 0) {
+    Pre p{0.0, 0.0};
+    if constexpr (MODE == 1 || MODE == 2) p.u0 = ldq(un + fo, c);
+    if constexpr (MODE >= 2) p.a0 = ldq(acc + fo, c);
+    return p;
+  }
+  __device__ __forceinline__ void put(int f, double r, const Pre& p) {
+    const size_t fo = (size_t)f * fs;
+    if constexpr (MODE == 0) {
       stq(out + fo, c, r);
-    } else if (mode == 1) {
-      const double u0 = ldq(un + fo, c);
-      stq(acc + fo, c, u0 + ca * r);
-      stq(out + fo, c, u0 + cn * r);
-    } else if (mode == 2) {
-      const double u0 = ldq(un + fo, c);
-      stq(acc + fo, c, ldq(acc + fo, c) + ca * r);
-      stq(out + fo, c, u0 + cn * r);
+    } else if constexpr (MODE == 1) {
+      stq(acc + fo, c, p.u0 + ca * r);
+      stq(out + fo, c, p.u0 + cn * r);
+    } else if constexpr (MODE == 2) {
+      stq(acc + fo, c, p.a0 + ca * r);
+      stq(out + fo, c, p.u0 + cn * r);
     } else {
-      const double v = ldq(acc + fo, c) + ca * r;
+      const double v = p.a0 + ca * r;
       stq(out + fo, c, v);
       bad = bad || !isfinite(v);
       if (f == F_ALP) coll = v < acol;
     }
   }
+  __device__ __forceinline__ void put(int f, double r) { put(f, r, preload(f)); }
 };
 
-__global__ __launch_bounds__(kBlock) void k_bssn_stage(const double* U, const double* un, double* acc, double* out,
-                                                        size_t fs, DevParams P, Tile T, double t, double ca, double cn,
-                                                        int mode, unsigned long long* status) {
+// Pointwise pre-pass of every stage: the fluid fluxes of U at all points.
+__global__ __launch_bounds__(kBlock) void k_fluid_flux(const double* U, size_t fs, double w, double* F) {
+  const size_t c = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (c >= fs) return;
+  fluid_flux_point(U, fs, (int)c, w, F);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_bssn_stage(const double* U, const double* F, const double* un, double* acc,
+                                                        double* out, size_t fs, DevParams P, Tile T, double t,
+                                                        double ca, double cn, unsigned long long* status) {
   int i, j, k;
   if (!tile_point(T, P.n, i, j, k)) return;
   const int p = i + P.n[0] * (j + P.n[1] * k);
@@ -186,21 +212,22 @@ __global__ __launch_bounds__(kBlock) void k_bssn_stage(const double* U, const do
   make_nbr(nb, i, j, k, P.n);
   __shared__ double lds_rec[R_COUNT * kBlock];
   const Rec rec{lds_rec + threadIdx.x, kBlock};
-  StageSink sink{un, acc, out, fs, p, mode, ca, cn, P.alpha_collapse};
+  StageSink<MODE> sink{un, acc, out, fs, p, ca, cn, P.alpha_collapse};
   bool fail = false;
-  bssn_rhs_stream(U, fs, nb, P, t, rec, sink, fail);
+  bssn_rhs_stream(U, F, fs, nb, P, t, rec, sink, fail);
   if (fail) atomicAdd(&status[1], 1ull);
-  if (mode == 3) {
+  if constexpr (MODE == 3) {
     if (sink.bad) atomicAdd(&status[0], 1ull);
     if (sink.coll) atomicAdd(&status[2], 1ull);
     if (p == 0) atomicAdd(&status[3], 1ull);
   }
 }
 
-template <int BX, int BY, int BZ>
-__global__ __launch_bounds__(kBlock) void k_bssn_stage_lds(const double* U, const double* un, double* acc, double* out,
-                                                            size_t fs, DevParams P, Tile T, double t, double ca,
-                                                            double cn, int mode, unsigned long long* status) {
+template <int BX, int BY, int BZ, int MODE>
+__global__ __launch_bounds__(kBlock) void k_bssn_stage_lds(const double* U, const double* F, const double* un,
+                                                            double* acc, double* out, size_t fs, DevParams P, Tile T,
+                                                            double t, double ca, double cn,
+                                                            unsigned long long* status) {
   using B = Brick<BX, BY, BZ>;
   __shared__ double smem[B::LDS_DOUBLES];
   int brick = blockIdx.x;
@@ -211,13 +238,13 @@ __global__ __launch_bounds__(kBlock) void k_bssn_stage_lds(const double* U, cons
   const int i = i0 + threadIdx.x % BX, j = j0 + (threadIdx.x / BX) % BY, k = k0 + threadIdx.x / (BX * BY);
   const bool active = i < P.n[0] && j < P.n[1] && k < P.n[2];
   const int c = active ? i + P.n[0] * (j + P.n[1] * k) : 0;
-  StageSink sink{un, acc, out, fs, c, mode, ca, cn, P.alpha_collapse};
+  StageSink<MODE> sink{un, acc, out, fs, c, ca, cn, P.alpha_collapse};
   bool fail = false;
-  bssn_rhs_lds<B>(U, fs, P, t, i0, j0, k0, c, active, smem, smem + R3_COUNT * 256, smem + R3_COUNT * 256 + B::NH,
-                  sink, fail);
+  bssn_rhs_lds<B>(U, F, fs, P, t, i0, j0, k0, c, active, smem,
+                  smem + B::NP, sink, fail);
   if (!active) return;
   if (fail) atomicAdd(&status[1], 1ull);
-  if (mode == 3) {
+  if constexpr (MODE == 3) {
     if (sink.bad) atomicAdd(&status[0], 1ull);
     if (sink.coll) atomicAdd(&status[2], 1ull);
     if (c == 0) atomicAdd(&status[3], 1ull);
@@ -225,24 +252,40 @@ __global__ __launch_bounds__(kBlock) void k_bssn_stage_lds(const double* U, cons
 }
 
 namespace {
-// Launch one stage with the kernel variant and brick chosen in the params.
-int launch_stage(const cosmos_params* p, const Tile& T, hipStream_t s, const double* U, const double* un, double* acc,
-                 double* out, size_t fs, const DevParams& P, double t, double ca, double cn, int mode,
+template <int M>
+void launch_mode(bool lds, const Tile& T, hipStream_t s, const double* U, const double* F, const double* un,
+                 double* acc, double* out, size_t fs, const DevParams& P, double t, double ca, double cn,
                  unsigned long long* status) {
   const dim3 g(tile_blocks(T)), b(kBlock);
-  if (p->variant == 1) {
-    hipLaunchKernelGGL(k_bssn_stage, g, b, 0, s, U, un, acc, out, fs, P, T, t, ca, cn, mode, status);
-  } else if (T.bx == 16 && T.by == 4 && T.bz == 4) {
-    hipLaunchKernelGGL((k_bssn_stage_lds<16, 4, 4>), g, b, 0, s, U, un, acc, out, fs, P, T, t, ca, cn, mode, status);
-  } else if (T.bx == 16 && T.by == 8 && T.bz == 2) {
-    hipLaunchKernelGGL((k_bssn_stage_lds<16, 8, 2>), g, b, 0, s, U, un, acc, out, fs, P, T, t, ca, cn, mode, status);
-  } else if (T.bx == 8 && T.by == 8 && T.bz == 4) {
-    hipLaunchKernelGGL((k_bssn_stage_lds<8, 8, 4>), g, b, 0, s, U, un, acc, out, fs, P, T, t, ca, cn, mode, status);
-  } else if (T.bx == 8 && T.by == 4 && T.bz == 8) {
-    hipLaunchKernelGGL((k_bssn_stage_lds<8, 4, 8>), g, b, 0, s, U, un, acc, out, fs, P, T, t, ca, cn, mode, status);
+  if (!lds) {
+    hipLaunchKernelGGL(k_bssn_stage<M>, g, b, 0, s, U, F, un, acc, out, fs, P, T, t, ca, cn, status);
+  } else if (T.bx == 16 && T.by == 4) {
+    hipLaunchKernelGGL((k_bssn_stage_lds<16, 4, 4, M>), g, b, 0, s, U, F, un, acc, out, fs, P, T, t, ca, cn, status);
+  } else if (T.bx == 16) {
+    hipLaunchKernelGGL((k_bssn_stage_lds<16, 8, 2, M>), g, b, 0, s, U, F, un, acc, out, fs, P, T, t, ca, cn, status);
+  } else if (T.by == 8) {
+    hipLaunchKernelGGL((k_bssn_stage_lds<8, 8, 4, M>), g, b, 0, s, U, F, un, acc, out, fs, P, T, t, ca, cn, status);
   } else {
+    hipLaunchKernelGGL((k_bssn_stage_lds<8, 4, 8, M>), g, b, 0, s, U, F, un, acc, out, fs, P, T, t, ca, cn, status);
+  }
+}
+
+// Launch one stage: the flux pre-pass into F (kFluxFields x fs doubles), then the
+// stage kernel with the variant and brick chosen in the params.
+int launch_stage(const cosmos_params* p, const Tile& T, hipStream_t s, const double* U, double* F, const double* un,
+                 double* acc, double* out, size_t fs, const DevParams& P, double t, double ca, double cn, int mode,
+                 unsigned long long* status) {
+  const bool lds = p->variant == 0;
+  if (lds && !((T.bx == 16 && T.by == 4 && T.bz == 4) || (T.bx == 16 && T.by == 8 && T.bz == 2) ||
+               (T.bx == 8 && T.by == 8 && T.bz == 4) || (T.bx == 8 && T.by == 4 && T.bz == 8)))
     return set_error(COSMOS_EINVAL, "LDS-staged variant has no %dx%dx%d brick (16x4x4, 16x8x2, 8x8x4, 8x4x8)", T.bx,
                      T.by, T.bz);
+  hipLaunchKernelGGL(k_fluid_flux, dim3((unsigned)((fs + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, U, fs, P.w, F);
+  switch (mode) {
+    case 0: launch_mode<0>(lds, T, s, U, F, un, acc, out, fs, P, t, ca, cn, status); break;
+    case 1: launch_mode<1>(lds, T, s, U, F, un, acc, out, fs, P, t, ca, cn, status); break;
+    case 2: launch_mode<2>(lds, T, s, U, F, un, acc, out, fs, P, t, ca, cn, status); break;
+    default: launch_mode<3>(lds, T, s, U, F, un, acc, out, fs, P, t, ca, cn, status); break;
   }
   return COSMOS_OK;
 }
@@ -315,7 +358,8 @@ int cosmos_rhs(const cosmos_grid* grid, const cosmos_params* params, double t, c
   Tile T;
   if ((rc = make_tile(grid, params, T))) return rc;
   auto* status = (unsigned long long*)ws;
-  if ((rc = launch_stage(params, T, (hipStream_t)stream, u, nullptr, nullptr, dudt, npts(grid), P, t, 0.0, 0.0, 0,
+  double* F = (double*)((char*)ws + layout(grid).F);
+  if ((rc = launch_stage(params, T, (hipStream_t)stream, u, F, nullptr, nullptr, dudt, npts(grid), P, t, 0.0, 0.0, 0,
                          status)))
     return rc;
   HIP_TRY(hipGetLastError());
@@ -332,16 +376,17 @@ int cosmos_rk4_step(const cosmos_grid* grid, const cosmos_params* params, double
   double* acc = (double*)(w + L.acc);
   double* A = (double*)(w + L.A);
   double* B = (double*)(w + L.B);
+  double* F = (double*)(w + L.F);
   auto* status = (unsigned long long*)(w + L.status);
   const DevParams P = dev_params(grid, params);
   Tile T;
   if ((rc = make_tile(grid, params, T))) return rc;
   const size_t fs = npts(grid);
   hipStream_t s = (hipStream_t)stream;
-  if ((rc = launch_stage(params, T, s, u, u, acc, A, fs, P, t, dt / 6.0, dt / 2.0, 1, status))) return rc;
-  launch_stage(params, T, s, A, u, acc, B, fs, P, t + dt / 2.0, dt / 3.0, dt / 2.0, 2, status);
-  launch_stage(params, T, s, B, u, acc, A, fs, P, t + dt / 2.0, dt / 3.0, dt, 2, status);
-  launch_stage(params, T, s, A, nullptr, acc, u, fs, P, t + dt, dt / 6.0, 0.0, 3, status);
+  if ((rc = launch_stage(params, T, s, u, F, u, acc, A, fs, P, t, dt / 6.0, dt / 2.0, 1, status))) return rc;
+  launch_stage(params, T, s, A, F, u, acc, B, fs, P, t + dt / 2.0, dt / 3.0, dt / 2.0, 2, status);
+  launch_stage(params, T, s, B, F, u, acc, A, fs, P, t + dt / 2.0, dt / 3.0, dt, 2, status);
+  launch_stage(params, T, s, A, F, nullptr, acc, u, fs, P, t + dt, dt / 6.0, 0.0, 3, status);
   HIP_TRY(hipGetLastError());
   return COSMOS_OK;
 }
