@@ -59,7 +59,7 @@ def parse():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-tune", action="store_true", help="use the default tile instead of the autotuned one")
     ap.add_argument("--batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=30, help="timed steps (runs/s is scaled to 300 steps)")

@@ -154,6 +154,37 @@ __device__ __forceinline__ void stq(double* F, int q, double v) {
   *(double*)((char*)F + (uint32_t)q * 8u) = v;
 }
 
+// One field array as a raw buffer: the uniform base address sits in a buffer
+// descriptor in SGPRs and each lane supplies only a 32-bit byte offset, so a load
+// or store costs no vector address arithmetic (a plain pointer load makes the
+// compiler form a 64-bit VGPR address per access). Descriptor word 3 = 0x00020000
+// is the gfx9 raw-buffer format (32-bit data, no swizzle, no index stride). The
+// record size bounds the access; grids keep 8 * points < 2^32 bytes per field.
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t field_rsrc(const double* base, uint32_t nbytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), (short)0, (int)nbytes, 0x00020000);
+}
+__device__ __forceinline__ double bld(const double* base, uint32_t nbytes, uint32_t off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(field_rsrc(base, nbytes), off, 0, 0));
+}
+__device__ __forceinline__ void bst(double* base, uint32_t nbytes, uint32_t off, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), field_rsrc(base, nbytes), off, 0, 0);
+}
+
+// Base of field f of a field-major array. The field offset passes through an empty
+// asm statement so the compiler recomputes it (two scalar ops) at each use instead
+// of keeping one base per field live for the whole kernel, which would overflow the
+// scalar registers and spill them.
+__device__ __forceinline__ size_t field_off(int f, size_t fs) {
+  size_t off = (size_t)f * fs;
+  asm volatile("" : "+s"(off));
+  return off;
+}
+template <class T>
+__device__ __forceinline__ T* field_ptr(T* U, int f, size_t fs) {
+  return U + field_off(f, fs);
+}
+
 // A per-phase copy of the neighbour offsets that the compiler cannot prove equal
 // to the other phases' copies, so the address arithmetic is redone per field
 // instead of being kept live across the whole point evaluation.
@@ -322,19 +353,45 @@ __device__ __forceinline__ void fluid_flux_point(const double* U, size_t fs, int
 // accumulates their centred difference.
 __device__ __forceinline__ void flux_axis_load(const double* F, size_t fs, int c, const Nbr& nb, int a,
                                                double v[4][4]) {
+  const uint32_t nbytes = (uint32_t)(fs * 8);
+  const uint32_t o0 = (uint32_t)(c + nb.d[a][1]) * 8u, o1 = (uint32_t)(c + nb.d[a][2]) * 8u;
+  const uint32_t o2 = (uint32_t)(c + nb.d[a][4]) * 8u, o3 = (uint32_t)(c + nb.d[a][5]) * 8u;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const double* Fa = F + (4 * a + q) * fs;
-    v[q][0] = ldq(Fa, c + nb.d[a][1]);
-    v[q][1] = ldq(Fa, c + nb.d[a][2]);
-    v[q][2] = ldq(Fa, c + nb.d[a][4]);
-    v[q][3] = ldq(Fa, c + nb.d[a][5]);
+    const double* Fa = field_ptr(F, 4 * a + q, fs);
+    v[q][0] = bld(Fa, nbytes, o0);
+    v[q][1] = bld(Fa, nbytes, o1);
+    v[q][2] = bld(Fa, nbytes, o2);
+    v[q][3] = bld(Fa, nbytes, o3);
   }
 }
 
 __device__ __forceinline__ void flux_axis_add(const double v[4][4], double i12h, double div[4]) {
 #pragma unroll
   for (int q = 0; q < 4; ++q) div[q] += ((v[q][0] - v[q][3]) + 8.0 * (v[q][2] - v[q][1])) * i12h;
+}
+
+// The same divergence for one conserved variable q: flux_var_load fetches F^a_q at
+// the four neighbours along each axis a, flux_var_div sums the centred differences
+// over a = 0, 1, 2 (the order flux_divergence uses).
+__device__ __forceinline__ void flux_var_load(const double* F, size_t fs, int c, const Nbr& nb, int q,
+                                              double v[3][4]) {
+  const uint32_t nbytes = (uint32_t)(fs * 8);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double* Fa = field_ptr(F, 4 * a + q, fs);
+    v[a][0] = bld(Fa, nbytes, (uint32_t)(c + nb.d[a][1]) * 8u);
+    v[a][1] = bld(Fa, nbytes, (uint32_t)(c + nb.d[a][2]) * 8u);
+    v[a][2] = bld(Fa, nbytes, (uint32_t)(c + nb.d[a][4]) * 8u);
+    v[a][3] = bld(Fa, nbytes, (uint32_t)(c + nb.d[a][5]) * 8u);
+  }
+}
+
+__device__ __forceinline__ double flux_var_div(const double v[3][4], const DevParams& P) {
+  double div = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) div += ((v[a][0] - v[a][3]) + 8.0 * (v[a][2] - v[a][1])) * P.i12h[a];
+  return div;
 }
 
 __device__ __forceinline__ void flux_divergence(const double* F, size_t fs, int c, const Nbr& nb, const DevParams& P,
@@ -369,6 +426,17 @@ __device__ __forceinline__ void connection_and_quadratic_ricci(const double dgt[
     for (int s = 0; s < 6; ++s) Gu[k][s] = gi[S(k, 0)] * Gl[0][s] + gi[S(k, 1)] * Gl[1][s] + gi[S(k, 2)] * Gl[2][s];
 #pragma unroll
   for (int k = 0; k < 3; ++k) Gd[k] = contract_sym(gi, Gu[k]);
+  // With Q[j][k][l] = gt^lm Gt_jkm (last index raised; 27 values), every gt^lm
+  // contraction of the quadratic terms becomes a single sum over k, l:
+  //   gt^lm Gt^k_li Gt_jkm = Gt^k_li Q[j][k][l],  gt^lm Gt^k_im Gt_klj = Gt^k_im Q[k][j][m].
+  double Q[3][3][3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int l = 0; l < 3; ++l)
+        Q[j][k][l] = gi[S(l, 0)] * Gl[j][S(k, 0)] + gi[S(l, 1)] * Gl[j][S(k, 1)] + gi[S(l, 2)] * Gl[j][S(k, 2)];
 #pragma unroll
   for (int s = 0; s < 6; ++s) {
     const int i = SI(s), j = SJ(s);
@@ -376,14 +444,10 @@ __device__ __forceinline__ void connection_and_quadratic_ricci(const double dgt[
 #pragma unroll
     for (int k = 0; k < 3; ++k) r += 0.5 * Gd[k] * (Gl[i][S(j, k)] + Gl[j][S(i, k)]);
 #pragma unroll
-    for (int l = 0; l < 3; ++l)
+    for (int k = 0; k < 3; ++k)
 #pragma unroll
-      for (int m = 0; m < 3; ++m) {
-        const double g = gi[S(l, m)];
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-          r += g * ((Gu[k][S(l, i)] * Gl[j][S(k, m)] + Gu[k][S(l, j)] * Gl[i][S(k, m)]) + Gu[k][S(i, m)] * Gl[k][S(l, j)]);
-      }
+      for (int l = 0; l < 3; ++l)
+        r += (Gu[k][S(l, i)] * Q[j][k][l] + Gu[k][S(l, j)] * Q[i][k][l]) + Gu[k][S(i, l)] * Q[k][j][l];
     Ric[s] += r;
   }
 }

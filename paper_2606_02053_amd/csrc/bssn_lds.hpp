@@ -97,7 +97,7 @@ constexpr int kStageOrder[NF] = {F_BET,    F_BET + 1, F_BET + 2, F_GT,     F_GT 
                                  F_GT + 4, F_GT + 5,  F_GAM,     F_GAM + 1, F_GAM + 2, F_CHI,   F_ALP,
                                  F_K,      F_AT,      F_AT + 1,  F_AT + 2, F_AT + 3, F_AT + 4, F_AT + 5,
                                  F_ET,     F_ST,      F_ST + 1,  F_ST + 2};
-constexpr int kPrefetch = 3;  // fields in flight ahead of the one being processed
+constexpr int kPrefetch = 2;  // fields in flight ahead of the one being processed
 
 // Fields whose right-hand side becomes final in each phase, in the order they are
 // handed to the sink (the Gt^i right-hand sides complete in the trace-K phase).
@@ -110,11 +110,17 @@ constexpr int kPutField[NF][4] = {
 // loaded kEpiAhead phases earlier: they come from HBM, whose latency exceeds one phase.
 constexpr int kEpiAhead = 3;
 
+__device__ __forceinline__ int wrap_halo(int x, int n) {
+  x = x < 0 ? x + n : x;
+  x = x >= n ? x - n : x;
+  return x >= n ? x - n : x;
+}
+
 // Cooperative copy of the fields' halo boxes: a ring of kPrefetch register
 // sets (slot 0 = next field to commit to LDS), rotated with constant indices.
 template <class B>
 struct HaloCopy {
-  int goff[B::NQ];  // linear grid index of this thread's halo-box points (wrapped)
+  uint32_t goffb[B::NQ];  // byte offset of this thread's halo-box points in a field (wrapped)
   double v[kPrefetch][B::NQ];
   __device__ __forceinline__ void init(int i0, int j0, int k0, const int n[3]) {
 #pragma unroll
@@ -122,20 +128,19 @@ struct HaloCopy {
       const int e = threadIdx.x + 256 * q;
       const int ee = e < B::NH ? e : 0;
       const int hx = ee % B::HX, hy = (ee / B::HX) % B::HY, hz = ee / (B::HX * B::HY);
-      // brick origins are inside the grid, so one period of wrap suffices except
-      // for grids smaller than the brick: reduce fully
-      int x = i0 + hx - 3, y = j0 + hy - 3, z = k0 + hz - 3;
-      x = ((x % n[0]) + n[0]) % n[0];
-      y = ((y % n[1]) + n[1]) % n[1];
-      z = ((z % n[2]) + n[2]) % n[2];
-      goff[q] = x + n[0] * (y + n[1] * z);
+      // Brick origins lie inside the grid and n >= 8, so a halo coordinate lies in
+      // [-3, 3n): one conditional add and two conditional subtracts wrap it (cheaper
+      // than an integer remainder by a run-time n).
+      goffb[q] = 8u * (uint32_t)(wrap_halo(i0 + hx - 3, n[0]) +
+                                 n[0] * (wrap_halo(j0 + hy - 3, n[1]) + n[1] * wrap_halo(k0 + hz - 3, n[2])));
     }
   }
   template <int SLOT>
-  __device__ __forceinline__ void fetch(const double* F) {
+  __device__ __forceinline__ void fetch(const double* F, uint32_t nbytes) {
+    static_assert(SLOT < kPrefetch, "ring slot");
 #pragma unroll
     for (int q = 0; q < B::NQ; ++q)
-      v[SLOT][q] = ldq(F, goff[q]);
+      v[SLOT][q] = bld(F, nbytes, goffb[q]);
   }
   __device__ __forceinline__ void commit_and_rotate(double* buf) {
 #pragma unroll
@@ -167,18 +172,20 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
 
   // centre values (registers); inactive threads read a valid point and never store
   const int cc = active ? c : 0;
-  const double chi = ldq(U + F_CHI * fs, cc);
-  const double K = ldq(U + F_K * fs, cc);
-  const double alpha = ldq(U + F_ALP * fs, cc);
+  const uint32_t nbytes = (uint32_t)(fs * 8), cb = (uint32_t)cc * 8u;
+  auto centre = [&](int f) { return bld(field_ptr(U, f, fs), nbytes, cb); };
+  const double chi = centre(F_CHI);
+  const double K = centre(F_K);
+  const double alpha = centre(F_ALP);
   double gt[6], beta[3], At[6], Gam[3];
 #pragma unroll
-  for (int s = 0; s < 6; ++s) gt[s] = ldq(U + (F_GT + s) * fs, cc);
+  for (int s = 0; s < 6; ++s) gt[s] = centre(F_GT + s);
 #pragma unroll
-  for (int q = 0; q < 3; ++q) beta[q] = ldq(U + (F_BET + q) * fs, cc);
+  for (int q = 0; q < 3; ++q) beta[q] = centre(F_BET + q);
 #pragma unroll
-  for (int s = 0; s < 6; ++s) At[s] = ldq(U + (F_AT + s) * fs, cc);
+  for (int s = 0; s < 6; ++s) At[s] = centre(F_AT + s);
 #pragma unroll
-  for (int q = 0; q < 3; ++q) Gam[q] = ldq(U + (F_GAM + q) * fs, cc);
+  for (int q = 0; q < 3; ++q) Gam[q] = centre(F_GAM + q);
 
   // ring of epilogue operands: slot d holds those of phase `phase + d`
   typename Sink::Pre ep[kEpiAhead + 1][4];
@@ -193,16 +200,18 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
   epi_load(1, std::integral_constant<int, 1>());
   epi_load(2, std::integral_constant<int, 2>());
 
-  hc.template fetch<0>(U + kStageOrder[0] * fs);
-  hc.template fetch<1>(U + kStageOrder[1] * fs);
-  hc.template fetch<2>(U + kStageOrder[2] * fs);
+  // fill the ring: slot d holds field d
+  static_assert(kPrefetch >= 1 && kPrefetch <= 3, "ring depth");
+  hc.template fetch<0>(field_ptr(U, kStageOrder[0], fs), nbytes);
+  if constexpr (kPrefetch > 1) hc.template fetch<(kPrefetch > 1 ? 1 : 0)>(field_ptr(U, kStageOrder[1], fs), nbytes);
+  if constexpr (kPrefetch > 2) hc.template fetch<(kPrefetch > 2 ? 2 : 0)>(field_ptr(U, kStageOrder[2], fs), nbytes);
   {
     double gi[6], St[3];
     inv_sym(gt, gi);
 #pragma unroll
-    for (int q = 0; q < 3; ++q) St[q] = ldq(U + (F_ST + q) * fs, cc);
+    for (int q = 0; q < 3; ++q) St[q] = centre(F_ST + q);
     Fluid fl;
-    prim_fail = active && recover(P.w, chi, gi, ldq(U + F_ET * fs, cc), St, fl);
+    prim_fail = active && recover(P.w, chi, gi, centre(F_ET), St, fl);
 #pragma unroll
     for (int s = 0; s < 6; ++s) R[R3_GI + s] = gi[s];
     R[R3_E] = fl.E;
@@ -224,7 +233,7 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
   int phase = 0;
   auto cur = [&]() -> const double* { return ((phase & 1) ? buf1 : buf0) + cidx; };
   auto prefetch = [&]() {
-    if (phase + kPrefetch < NF) hc.template fetch<kPrefetch - 1>(U + kStageOrder[phase + kPrefetch] * fs);
+    if (phase + kPrefetch < NF) hc.template fetch<kPrefetch - 1>(field_ptr(U, kStageOrder[phase + kPrefetch], fs), nbytes);
     epi_load(phase + kEpiAhead, std::integral_constant<int, kEpiAhead>());
   };
   auto advance = [&](int) {
@@ -453,9 +462,11 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
   }
   advance(0);
 
-  // ---- traceless extrinsic curvature. The flux-divergence loads of axis a are issued
-  // in At phase 3 + a and consumed one phase later, so their latency overlaps the algebra.
-  double div[4] = {0.0, 0.0, 0.0, 0.0}, fv[4][4];
+  // ---- traceless extrinsic curvature. The flux-divergence loads of conserved
+  // variable q (all three axes) are issued two phases before the phase that
+  // completes its right-hand side (q = 0 in At phase 4, 1 in At phase 5, 2 in the
+  // Et phase, 3 in the first St phase), so their latency overlaps the algebra.
+  double fa[3][4], fb[3][4];
   Nbr fnb;
   if (active) {
     const int i = c % P.n[0], jk = c / P.n[0];
@@ -465,8 +476,8 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
   for (int s = 0; s < 6; ++s) {
     prefetch();
     if (active) {
-      if (s >= 4) flux_axis_add(fv, P.i12h[s - 4], div);
-      if (s >= 3) flux_axis_load(F, fs, c, fnb, s - 3, fv);
+      if (s == 4) flux_var_load(F, fs, c, fnb, 0, fa);
+      if (s == 5) flux_var_load(F, fs, c, fnb, 1, fb);
       double gi[6], X[6], db[3][3];
 #pragma unroll
       for (int q = 0; q < 6; ++q) {
@@ -498,7 +509,8 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
   const double im32 = 1.0 / (chi * sqrt(chi));
   prefetch();
   if (active) {
-    flux_axis_add(fv, P.i12h[2], div);
+    const double div0 = flux_var_div(fa, P);
+    flux_var_load(F, fs, c, fnb, 2, fa);
     double KS = 0.0;
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
@@ -508,13 +520,21 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
     FieldDerivs d;
     lds_derivs<B, false, false>(cur(), P, nbeta, d);
     const double Sda = S_up(0) * R[R3_DAL + 0] + S_up(1) * R[R3_DAL + 1] + S_up(2) * R[R3_DAL + 2];
-    sink.put(F_ET, d.advko + (im32 * (alpha * KS - Sda) - div[0]), ep[0][0]);
+    sink.put(F_ET, d.advko + (im32 * (alpha * KS - Sda) - div0), ep[0][0]);
   }
   advance(0);
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     prefetch();
     if (active) {
+      // St_0: q = 1 (loaded in At phase 5), then issue q = 3; St_1: q = 2; St_2: q = 3
+      double divi;
+      if (i == 0) {
+        divi = flux_var_div(fb, P);
+        flux_var_load(F, fs, c, fnb, 3, fb);
+      } else {
+        divi = flux_var_div(i == 1 ? fa : fb, P);
+      }
       double sgt = 0.0;
 #pragma unroll
       for (int s = 0; s < 6; ++s) sgt += (s == 0 || s == 3 || s == 5 ? 1.0 : 2.0) * Sjk_at(s) * gt[s];
@@ -524,7 +544,7 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
                    (R[R3_S + 0] * R[R3_DB + 0 + i] + R[R3_S + 1] * R[R3_DB + 3 + i] + R[R3_S + 2] * R[R3_DB + 6 + i]);
       const double ichi = 1.0 / chi;
       src += 0.5 * alpha * (R[R3_SG + i] * ichi - sgt * R[R3_DCHI + i] * (ichi * ichi));
-      sink.put(F_ST + i, d.advko + (im32 * src - div[1 + i]), ep[0][0]);
+      sink.put(F_ST + i, d.advko + (im32 * src - divi), ep[0][0]);
     }
     if (i < 2) advance(0);
   }

@@ -168,25 +168,27 @@ struct StageSink {
     double u0, a0;
   };
   __device__ __forceinline__ Pre preload(int f) const {
-    const size_t fo = (size_t)f * fs;  // uniform: field base offsets live in SGPRs
+    const uint32_t nb = (uint32_t)(fs * 8), cb = (uint32_t)c * 8u;
+    const size_t o = field_off(f, fs);
     Pre p{0.0, 0.0};
-    if constexpr (MODE == 1 || MODE == 2) p.u0 = ldq(un + fo, c);
-    if constexpr (MODE >= 2) p.a0 = ldq(acc + fo, c);
+    if constexpr (MODE == 1 || MODE == 2) p.u0 = bld(un + o, nb, cb);
+    if constexpr (MODE >= 2) p.a0 = bld(acc + o, nb, cb);
     return p;
   }
   __device__ __forceinline__ void put(int f, double r, const Pre& p) {
-    const size_t fo = (size_t)f * fs;
+    const uint32_t nb = (uint32_t)(fs * 8), cb = (uint32_t)c * 8u;
+    const size_t o = field_off(f, fs);
     if constexpr (MODE == 0) {
-      stq(out + fo, c, r);
+      bst(out + o, nb, cb, r);
     } else if constexpr (MODE == 1) {
-      stq(acc + fo, c, p.u0 + ca * r);
-      stq(out + fo, c, p.u0 + cn * r);
+      bst(acc + o, nb, cb, p.u0 + ca * r);
+      bst(out + o, nb, cb, p.u0 + cn * r);
     } else if constexpr (MODE == 2) {
-      stq(acc + fo, c, p.a0 + ca * r);
-      stq(out + fo, c, p.u0 + cn * r);
+      bst(acc + o, nb, cb, p.a0 + ca * r);
+      bst(out + o, nb, cb, p.u0 + cn * r);
     } else {
       const double v = p.a0 + ca * r;
-      stq(out + fo, c, v);
+      bst(out + o, nb, cb, v);
       bad = bad || !isfinite(v);
       if (f == F_ALP) coll = v < acol;
     }
