@@ -6,7 +6,9 @@
 // then forms that field's derivatives at its point from LDS with
 // compile-time-offset reads. The copy of the next field is issued before the
 // current field's arithmetic and written to the second LDS buffer after it, so
-// its latency hides behind the FP64 work. Long-lived per-point intermediates
+// its latency hides behind the FP64 work. A workgroup walks several bricks and
+// loads the next brick's first fields, epilogue operands and point values during
+// the last phases of the current one. Long-lived per-point intermediates
 // (R3_* slots) stay in registers: one wave per SIMD is resident anyway (the
 // fused point evaluation needs ~300 registers), so the VGPR + AGPR file holds
 // them, and LDS only carries the two halo buffers. The fluid fluxes come from a
@@ -122,7 +124,8 @@ template <class B>
 struct HaloCopy {
   uint32_t goffb[B::NQ];  // byte offset of this thread's halo-box points in a field (wrapped)
   double v[kPrefetch][B::NQ];
-  __device__ __forceinline__ void init(int i0, int j0, int k0, const int n[3]) {
+  __device__ __forceinline__ void init(int i0, int j0, int k0, const int n[3]) { offsets(i0, j0, k0, n, goffb); }
+  static __device__ __forceinline__ void offsets(int i0, int j0, int k0, const int n[3], uint32_t goffb[B::NQ]) {
 #pragma unroll
     for (int q = 0; q < B::NQ; ++q) {
       const int e = threadIdx.x + 256 * q;
@@ -137,10 +140,14 @@ struct HaloCopy {
   }
   template <int SLOT>
   __device__ __forceinline__ void fetch(const double* F, uint32_t nbytes) {
+    fetch_at<SLOT>(F, nbytes, goffb);
+  }
+  template <int SLOT>
+  __device__ __forceinline__ void fetch_at(const double* F, uint32_t nbytes, const uint32_t off[B::NQ]) {
     static_assert(SLOT < kPrefetch, "ring slot");
 #pragma unroll
     for (int q = 0; q < B::NQ; ++q)
-      v[SLOT][q] = bld(F, nbytes, goffb[q]);
+      v[SLOT][q] = bld(F, nbytes, off[q]);
   }
   __device__ __forceinline__ void commit_and_rotate(double* buf) {
 #pragma unroll
@@ -153,12 +160,53 @@ struct HaloCopy {
   }
 };
 
+// State carried from one brick to the next by a workgroup that walks several
+// bricks: the halo ring (the next fields to commit), the epilogue-operand ring
+// (slot d = phase + d) and the 25 values of the thread's point.
+template <class B, class Pre>
+struct LdsCarry {
+  HaloCopy<B> hc;
+  Pre ep[kEpiAhead + 1][4];
+  double cen[NF];
+};
+
+// The brick a workgroup processes next (valid is uniform): its halo offsets and
+// this thread's point in it (0 for a thread outside the grid).
+template <class B>
+struct NextBrick {
+  bool valid;
+  int c;
+  uint32_t goffb[B::NQ];
+};
+
+// Loads of the first brick of a workgroup (later bricks are prefetched during the
+// previous one): fields 0 .. kPrefetch-1 into the ring, the epilogue operands of
+// phases 0 .. kEpiAhead-1 and the point's values.
+template <class B, class Sink, class Pre>
+__device__ __forceinline__ void lds_carry_fill(LdsCarry<B, Pre>& cy, const double* U, size_t fs, const Sink& sink,
+                                               int c) {
+  static_assert(kPrefetch >= 1 && kPrefetch <= 3, "ring depth");
+  const uint32_t nbytes = (uint32_t)(fs * 8);
+  cy.hc.template fetch<0>(field_ptr(U, kStageOrder[0], fs), nbytes);
+  if constexpr (kPrefetch > 1) cy.hc.template fetch<(kPrefetch > 1 ? 1 : 0)>(field_ptr(U, kStageOrder[1], fs), nbytes);
+  if constexpr (kPrefetch > 2) cy.hc.template fetch<(kPrefetch > 2 ? 2 : 0)>(field_ptr(U, kStageOrder[2], fs), nbytes);
+#pragma unroll
+  for (int d = 0; d < kEpiAhead; ++d)
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (k < kPutCount[d]) cy.ep[d][k] = sink.preload_at(kPutField[d][k], c);
+#pragma unroll
+  for (int f = 0; f < NF; ++f) cy.cen[f] = bld(field_ptr(U, f, fs), nbytes, (uint32_t)c * 8u);
+}
+
 // The whole right-hand side of one point with LDS-staged stencils. All threads
 // of the workgroup must call it (it contains barriers); `active` marks threads
-// whose point lies inside the grid.
-template <class B, class Sink>
+// whose point lies inside the grid. On entry `cy` holds this brick's ring,
+// epilogue operands and point values; if nx.valid, on return it holds those of
+// the next brick (loaded during the last phases of this one).
+template <class B, class Sink, class Pre>
 __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, size_t fs, const DevParams& P, double t,
-                                             int i0, int j0, int k0, int c, bool active,
+                                             int c, bool active, LdsCarry<B, Pre>& cy, const NextBrick<B>& nx,
                                              double* buf0, double* buf1, Sink& sink, bool& prim_fail) {
   struct {  // the per-point record, indexed by compile-time constants only (kept in registers)
     double v[R3_COUNT];
@@ -167,51 +215,43 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
   const int lx = threadIdx.x % (B::HX - 6), ly = (threadIdx.x / (B::HX - 6)) % (B::HY - 6),
             lz = threadIdx.x / ((B::HX - 6) * (B::HY - 6));
   const int cidx = (lx + 3) + B::SY * ((ly + 3) + B::HY * (lz + 3));
-  HaloCopy<B> hc;
-  hc.init(i0, j0, k0, P.n);
+  HaloCopy<B>& hc = cy.hc;
+  auto& ep = cy.ep;
+  const uint32_t nbytes = (uint32_t)(fs * 8);
 
-  // centre values (registers); inactive threads read a valid point and never store
-  const int cc = active ? c : 0;
-  const uint32_t nbytes = (uint32_t)(fs * 8), cb = (uint32_t)cc * 8u;
-  auto centre = [&](int f) { return bld(field_ptr(U, f, fs), nbytes, cb); };
-  const double chi = centre(F_CHI);
-  const double K = centre(F_K);
-  const double alpha = centre(F_ALP);
+  // centre values (registers); inactive threads hold a valid point's values and never store
+  const double chi = cy.cen[F_CHI];
+  const double K = cy.cen[F_K];
+  const double alpha = cy.cen[F_ALP];
   double gt[6], beta[3], At[6], Gam[3];
 #pragma unroll
-  for (int s = 0; s < 6; ++s) gt[s] = centre(F_GT + s);
+  for (int s = 0; s < 6; ++s) gt[s] = cy.cen[F_GT + s];
 #pragma unroll
-  for (int q = 0; q < 3; ++q) beta[q] = centre(F_BET + q);
+  for (int q = 0; q < 3; ++q) beta[q] = cy.cen[F_BET + q];
 #pragma unroll
-  for (int s = 0; s < 6; ++s) At[s] = centre(F_AT + s);
+  for (int s = 0; s < 6; ++s) At[s] = cy.cen[F_AT + s];
 #pragma unroll
-  for (int q = 0; q < 3; ++q) Gam[q] = centre(F_GAM + q);
+  for (int q = 0; q < 3; ++q) Gam[q] = cy.cen[F_GAM + q];
 
-  // ring of epilogue operands: slot d holds those of phase `phase + d`
-  typename Sink::Pre ep[kEpiAhead + 1][4];
+  // epilogue operands of phase ph (of this brick, or of the next one when ph >= NF)
   auto epi_load = [&](int ph, auto slot) {
     if (ph < NF) {
 #pragma unroll
       for (int k = 0; k < 4; ++k)
         if (k < kPutCount[ph]) ep[decltype(slot)::value][k] = sink.preload(kPutField[ph][k]);
+    } else if (nx.valid) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (k < kPutCount[ph - NF]) ep[decltype(slot)::value][k] = sink.preload_at(kPutField[ph - NF][k], nx.c);
     }
   };
-  epi_load(0, std::integral_constant<int, 0>());
-  epi_load(1, std::integral_constant<int, 1>());
-  epi_load(2, std::integral_constant<int, 2>());
-
-  // fill the ring: slot d holds field d
-  static_assert(kPrefetch >= 1 && kPrefetch <= 3, "ring depth");
-  hc.template fetch<0>(field_ptr(U, kStageOrder[0], fs), nbytes);
-  if constexpr (kPrefetch > 1) hc.template fetch<(kPrefetch > 1 ? 1 : 0)>(field_ptr(U, kStageOrder[1], fs), nbytes);
-  if constexpr (kPrefetch > 2) hc.template fetch<(kPrefetch > 2 ? 2 : 0)>(field_ptr(U, kStageOrder[2], fs), nbytes);
   {
     double gi[6], St[3];
     inv_sym(gt, gi);
 #pragma unroll
-    for (int q = 0; q < 3; ++q) St[q] = centre(F_ST + q);
+    for (int q = 0; q < 3; ++q) St[q] = cy.cen[F_ST + q];
     Fluid fl;
-    prim_fail = active && recover(P.w, chi, gi, centre(F_ET), St, fl);
+    prim_fail = active && recover(P.w, chi, gi, cy.cen[F_ET], St, fl);
 #pragma unroll
     for (int s = 0; s < 6; ++s) R[R3_GI + s] = gi[s];
     R[R3_E] = fl.E;
@@ -233,7 +273,10 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
   int phase = 0;
   auto cur = [&]() -> const double* { return ((phase & 1) ? buf1 : buf0) + cidx; };
   auto prefetch = [&]() {
-    if (phase + kPrefetch < NF) hc.template fetch<kPrefetch - 1>(field_ptr(U, kStageOrder[phase + kPrefetch], fs), nbytes);
+    if (phase + kPrefetch < NF)
+      hc.template fetch<kPrefetch - 1>(field_ptr(U, kStageOrder[phase + kPrefetch], fs), nbytes);
+    else if (nx.valid)
+      hc.template fetch_at<kPrefetch - 1>(field_ptr(U, kStageOrder[phase + kPrefetch - NF], fs), nbytes, nx.goffb);
     epi_load(phase + kEpiAhead, std::integral_constant<int, kEpiAhead>());
   };
   auto advance = [&](int) {
@@ -523,9 +566,14 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
     sink.put(F_ET, d.advko + (im32 * (alpha * KS - Sda) - div0), ep[0][0]);
   }
   advance(0);
+  double cnext[NF];  // the next brick's point values, loaded during the St phases
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     prefetch();
+    if (i == 0 && nx.valid) {
+#pragma unroll
+      for (int f = 0; f < NF; ++f) cnext[f] = bld(field_ptr(U, f, fs), nbytes, (uint32_t)nx.c * 8u);
+    }
     if (active) {
       // St_0: q = 1 (loaded in At phase 5), then issue q = 3; St_1: q = 2; St_2: q = 3
       double divi;
@@ -547,6 +595,16 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
       sink.put(F_ST + i, d.advko + (im32 * src - divi), ep[0][0]);
     }
     if (i < 2) advance(0);
+  }
+  if (nx.valid) {  // hand over to the next brick: the halo ring already holds its first fields
+#pragma unroll
+    for (int f = 0; f < NF; ++f) cy.cen[f] = cnext[f];
+#pragma unroll
+    for (int q = 0; q < B::NQ; ++q) hc.goffb[q] = nx.goffb[q];
+#pragma unroll
+    for (int d = 0; d < kEpiAhead; ++d)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) ep[d][k] = ep[d + 1][k];
   }
 }
 

@@ -167,8 +167,9 @@ struct StageSink {
   struct Pre {
     double u0, a0;
   };
-  __device__ __forceinline__ Pre preload(int f) const {
-    const uint32_t nb = (uint32_t)(fs * 8), cb = (uint32_t)c * 8u;
+  __device__ __forceinline__ Pre preload(int f) const { return preload_at(f, c); }
+  __device__ __forceinline__ Pre preload_at(int f, int cp) const {
+    const uint32_t nb = (uint32_t)(fs * 8), cb = (uint32_t)cp * 8u;
     const size_t o = field_off(f, fs);
     Pre p{0.0, 0.0};
     if constexpr (MODE == 1 || MODE == 2) p.u0 = bld(un + o, nb, cb);
@@ -225,50 +226,121 @@ __global__ __launch_bounds__(kBlock) void k_bssn_stage(const double* U, const do
   }
 }
 
+// LDS-staged stage kernel: a persistent workgroup walks bricks v = blockIdx.x +
+// it * gridDim.x (gridDim.x a multiple of 8, so with the XCD-aware order every
+// brick of a workgroup lies in its XCD's slab), prefetching each next brick
+// during the last phases of the current one.
 template <int BX, int BY, int BZ, int MODE>
 __global__ __launch_bounds__(kBlock) void k_bssn_stage_lds(const double* U, const double* F, const double* un,
                                                             double* acc, double* out, size_t fs, DevParams P, Tile T,
                                                             double t, double ca, double cn,
                                                             unsigned long long* status) {
   using B = Brick<BX, BY, BZ>;
+  using Sink = StageSink<MODE>;
   __shared__ double smem[B::LDS_DOUBLES];
-  int brick = blockIdx.x;
-  if (T.xcd_order) brick = (blockIdx.x & 7) * T.per + (blockIdx.x >> 3);
-  if (brick >= T.nbricks) return;  // uniform over the workgroup
-  const int bxi = brick % T.nbx, byz = brick / T.nbx;
-  const int i0 = bxi * BX, j0 = (byz % T.nby) * BY, k0 = (byz / T.nby) * BZ;
-  const int i = i0 + threadIdx.x % BX, j = j0 + (threadIdx.x / BX) % BY, k = k0 + threadIdx.x / (BX * BY);
-  const bool active = i < P.n[0] && j < P.n[1] && k < P.n[2];
-  const int c = active ? i + P.n[0] * (j + P.n[1] * k) : 0;
-  StageSink<MODE> sink{un, acc, out, fs, c, ca, cn, P.alpha_collapse};
-  bool fail = false;
-  bssn_rhs_lds<B>(U, F, fs, P, t, i0, j0, k0, c, active, smem,
-                  smem + B::NP, sink, fail);
-  if (!active) return;
-  if (fail) atomicAdd(&status[1], 1ull);
+  // brick number `it` of this workgroup: origin, and this thread's point (c = 0 outside the grid)
+  auto locate = [&](int it, int& i0, int& j0, int& k0, int& c, bool& act) -> bool {
+    const int v = blockIdx.x + it * gridDim.x;
+    int brick = v;
+    if (T.xcd_order) {
+      if ((v >> 3) >= T.per) return false;
+      brick = (v & 7) * T.per + (v >> 3);
+    }
+    if (brick >= T.nbricks) return false;  // bricks increase with `it`: none after this one
+    const int bxi = brick % T.nbx, byz = brick / T.nbx;
+    i0 = bxi * BX, j0 = (byz % T.nby) * BY, k0 = (byz / T.nby) * BZ;
+    const int i = i0 + threadIdx.x % BX, j = j0 + (threadIdx.x / BX) % BY, k = k0 + threadIdx.x / (BX * BY);
+    act = i < P.n[0] && j < P.n[1] && k < P.n[2];
+    c = act ? i + P.n[0] * (j + P.n[1] * k) : 0;
+    return true;
+  };
+  int i0, j0, k0, c;
+  bool active;
+  if (!locate(0, i0, j0, k0, c, active)) return;  // uniform over the workgroup
+  LdsCarry<B, typename Sink::Pre> cy;
+  cy.hc.init(i0, j0, k0, P.n);
+  {
+    const Sink s0{un, acc, out, fs, c, ca, cn, P.alpha_collapse};
+    lds_carry_fill(cy, U, fs, s0, c);
+  }
+  unsigned long long nfail = 0, nbad = 0, ncoll = 0, nstep = 0;
+  for (int it = 0;; ++it) {
+    NextBrick<B> nx;
+    int ni0, nj0, nk0;
+    bool nact = false;
+    nx.valid = locate(it + 1, ni0, nj0, nk0, nx.c, nact);
+    if (nx.valid) HaloCopy<B>::offsets(ni0, nj0, nk0, P.n, nx.goffb);
+    Sink sink{un, acc, out, fs, c, ca, cn, P.alpha_collapse};
+    bool fail = false;
+    bssn_rhs_lds<B>(U, F, fs, P, t, c, active, cy, nx, smem, smem + B::NP, sink, fail);
+    if (active) {
+      nfail += fail;
+      if constexpr (MODE == 3) {
+        nbad += sink.bad;
+        ncoll += sink.coll;
+        nstep += c == 0;
+      }
+    }
+    if (!nx.valid) break;
+    __syncthreads();  // the halo buffers are reused by the next brick
+    c = nx.c;
+    active = nact;
+  }
+  if (nfail) atomicAdd(&status[1], nfail);
   if constexpr (MODE == 3) {
-    if (sink.bad) atomicAdd(&status[0], 1ull);
-    if (sink.coll) atomicAdd(&status[2], 1ull);
-    if (c == 0) atomicAdd(&status[3], 1ull);
+    if (nbad) atomicAdd(&status[0], nbad);
+    if (ncoll) atomicAdd(&status[2], ncoll);
+    if (nstep) atomicAdd(&status[3], nstep);
   }
 }
 
 namespace {
+// Workgroups of `kernel` resident on the whole device at once, rounded down to a
+// multiple of 8 (one slot per XCD per round), cached per device and kernel.
+template <class K>
+unsigned resident_groups(K kernel) {
+  struct Entry {
+    const void* k;
+    int dev;
+    unsigned n;
+  };
+  static Entry cache[64];
+  static int used = 0;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 8;
+  for (int e = 0; e < used; ++e)
+    if (cache[e].k == (const void*)kernel && cache[e].dev == dev) return cache[e].n;
+  int ncu = 0, per = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) ncu = 8;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kBlock, 0) != hipSuccess || per < 1) per = 1;
+  const unsigned n = std::max(8u, (unsigned)(ncu * per) / 8u * 8u);
+  if (used < 64) cache[used++] = Entry{(const void*)kernel, dev, n};
+  return n;
+}
+
+template <class K>
+void launch_persistent(K kernel, const Tile& T, hipStream_t s, const double* U, const double* F, const double* un,
+                       double* acc, double* out, size_t fs, const DevParams& P, double t, double ca, double cn,
+                       unsigned long long* status) {
+  const dim3 g(std::min(tile_blocks(T), resident_groups(kernel))), b(kBlock);
+  hipLaunchKernelGGL(kernel, g, b, 0, s, U, F, un, acc, out, fs, P, T, t, ca, cn, status);
+}
+
 template <int M>
 void launch_mode(bool lds, const Tile& T, hipStream_t s, const double* U, const double* F, const double* un,
                  double* acc, double* out, size_t fs, const DevParams& P, double t, double ca, double cn,
                  unsigned long long* status) {
-  const dim3 g(tile_blocks(T)), b(kBlock);
   if (!lds) {
+    const dim3 g(tile_blocks(T)), b(kBlock);
     hipLaunchKernelGGL(k_bssn_stage<M>, g, b, 0, s, U, F, un, acc, out, fs, P, T, t, ca, cn, status);
   } else if (T.bx == 16 && T.by == 4) {
-    hipLaunchKernelGGL((k_bssn_stage_lds<16, 4, 4, M>), g, b, 0, s, U, F, un, acc, out, fs, P, T, t, ca, cn, status);
+    launch_persistent(k_bssn_stage_lds<16, 4, 4, M>, T, s, U, F, un, acc, out, fs, P, t, ca, cn, status);
   } else if (T.bx == 16) {
-    hipLaunchKernelGGL((k_bssn_stage_lds<16, 8, 2, M>), g, b, 0, s, U, F, un, acc, out, fs, P, T, t, ca, cn, status);
+    launch_persistent(k_bssn_stage_lds<16, 8, 2, M>, T, s, U, F, un, acc, out, fs, P, t, ca, cn, status);
   } else if (T.by == 8) {
-    hipLaunchKernelGGL((k_bssn_stage_lds<8, 8, 4, M>), g, b, 0, s, U, F, un, acc, out, fs, P, T, t, ca, cn, status);
+    launch_persistent(k_bssn_stage_lds<8, 8, 4, M>, T, s, U, F, un, acc, out, fs, P, t, ca, cn, status);
   } else {
-    hipLaunchKernelGGL((k_bssn_stage_lds<8, 4, 8, M>), g, b, 0, s, U, F, un, acc, out, fs, P, T, t, ca, cn, status);
+    launch_persistent(k_bssn_stage_lds<8, 4, 8, M>, T, s, U, F, un, acc, out, fs, P, t, ca, cn, status);
   }
 }
 
