@@ -20,7 +20,7 @@ Extra modes:
   --copy-probe   only a plain device-to-device copy of known size (calibrates
                  rocprofv3 FETCH_SIZE / WRITE_SIZE counters)
   --no-cpu       skip the CPU baseline leg
-  --config K     fixed configuration (lds|direct:BXxBYxBZ:xcd|linear) instead of the autotuner
+  --config K     fixed configuration (lds|direct:BXxBYxBZ:xcd|linear|blocked) instead of the autotuner
 
 roofline.traffic is the HBM bytes per stage launch from committed rocprofv3 counters
 (profiles/k_bssn_stage_lds_256cubed_traffic.txt), reported only while the stage-kernel
@@ -65,7 +65,7 @@ def parse():
     ap.add_argument("--batched-steps", type=int, default=30, help="timed steps (runs/s is scaled to 300 steps)")
     ap.add_argument("--adjoint", action="store_true")
     ap.add_argument("--config", default=None,
-                    help="fixed kernel configuration instead of autotuning, e.g. lds:16x4x4:linear or direct:32x4x2:xcd")
+                    help="fixed kernel configuration instead of autotuning, e.g. lds:16x4x4:blocked or direct:32x4x2:xcd")
     ap.add_argument("--source-hash", action="store_true", help="print the stage-kernel source hash and exit")
     return ap.parse_args()
 
@@ -73,11 +73,11 @@ def parse():
 def parse_config(text):
     kind, tile, order = text.split(":")
     kv = {"lds": 0, "direct": 1}[kind]
-    return kv, tuple(int(x) for x in tile.split("x")), {"xcd": 0, "linear": 1}[order]
+    return kv, tuple(int(x) for x in tile.split("x")), {"xcd": 0, "linear": 1, "blocked": 2}[order]
 
 
 def config_name(kv, tile, order):
-    return f"{'lds' if kv == 0 else 'direct'}:{'x'.join(map(str, tile))}:{'xcd' if order == 0 else 'linear'}"
+    return f"{'lds' if kv == 0 else 'direct'}:{'x'.join(map(str, tile))}:{('xcd', 'linear', 'blocked')[order]}"
 
 
 def stage_source_hash():
@@ -294,7 +294,7 @@ def main():
            "config": {"workload": f"BSSN + radiation fluid (P = rho/3) classic RK4, {n}^3 periodic grid, L = 16/H0, "
                                   f"Gaussian zeta mu = 0.6 sigma = 2.0, CFL 0.25, KO eps 0.1",
                       "grid": n, "dt": dt, "kernel_variant": "lds-staged" if kv == 0 else "direct",
-                      "tile": list(tile), "tile_order": "xcd" if order == 0 else "linear",
+                      "tile": list(tile), "tile_order": ("xcd", "linear", "blocked")[order],
                       "kernel_config": config_name(kv, tile, order),
                       "parallelism": "single GPU"},
            "roofline": roof}

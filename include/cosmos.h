@@ -90,7 +90,10 @@ typedef struct {
  *   tile_x, tile_y, tile_z  brick owned by one 256-thread workgroup of the stage kernel
  *            (tile_x * tile_y * tile_z must be 256; all 0 = default 16 x 4 x 4); results do not
  *            depend on the tile (bitwise), only the speed does
- *   tile_order 0: XCD-aware brick order (each of the 8 XCDs walks one contiguous slab); 1: linear */
+ *   tile_order brick order: 0 = XCD slabs (each of the 8 XCDs walks one contiguous slab of bricks),
+ *            1 = linear, 2 = XCD-blocked (LDS-staged variant: each XCD owns a slab of brick layers and
+ *            its resident workgroups process one compact block of bricks at a time, so shared halos
+ *            are read into that XCD's L2 once; the direct variant treats 2 as linear) */
 typedef struct {
   double w, H0, eta, ko_eps;
   int32_t lapse_bg, evolve_shift, fluid_scheme, variant;

@@ -2,7 +2,7 @@
 
 Searches the kernel variant (LDS-staged bricks, or direct loads through the
 caches), the brick owned by one 256-thread workgroup (tile_x x tile_y x
-tile_z, x fastest) and the brick order (XCD-aware slabs or linear), times
+tile_z, x fastest) and the brick order (XCD slabs, linear, or XCD-blocked), times
 full RK4 steps of each candidate with HIP events on the launch stream, and
 keeps the fastest. A candidate is eligible only if its right-hand side is
 bitwise identical to its variant's default brick on the same state (the brick
@@ -22,9 +22,9 @@ from . import _lib as C
 
 LDS_BRICKS = [(16, 4, 4), (16, 8, 2), (8, 8, 4), (8, 4, 8)]
 DIRECT_TILES = [(256, 1, 1), (64, 4, 1), (32, 8, 1), (32, 4, 2), (16, 16, 1), (16, 4, 4), (8, 8, 4)]
-ORDERS = (0, 1)
+ORDERS = (0, 1, 2)  # XCD slabs, linear, XCD-blocked (the last only for the LDS-staged variant)
 # (variant, tile, order): variant 0 = LDS-staged bricks, 1 = direct loads
-CANDIDATES = [(0, t, o) for t in LDS_BRICKS for o in ORDERS] + [(1, t, o) for t in DIRECT_TILES for o in ORDERS]
+CANDIDATES = [(0, t, o) for t in LDS_BRICKS for o in ORDERS] + [(1, t, o) for t in DIRECT_TILES for o in ORDERS[:2]]
 
 
 def _cache_path() -> str:

@@ -61,6 +61,11 @@ struct Tile {
   int bx, by, bz;
   int nbx, nby, nbz;
   int nbricks, per, xcd_order;
+  // brick order of the persistent LDS kernel: 0 XCD slabs, 1 linear, 2 XCD-blocked
+  // (each XCD owns a slab of zr brick layers and its W = gx gy gz resident
+  // workgroups process one gx x gy x gz block of bricks at a time, so that the
+  // halos they share are read from that XCD's L2 once)
+  int order, gx, gy, gz, zr, ngx, ngy, ngroups;
 };
 
 // Maps (blockIdx, threadIdx) to a grid point; false for padding workgroups

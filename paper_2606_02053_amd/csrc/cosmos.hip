@@ -107,10 +107,13 @@ int make_tile(const cosmos_grid* g, const cosmos_params* p, Tile& T) {
   T.bx = p->tile_x ? p->tile_x : 16;
   T.by = p->tile_y ? p->tile_y : 4;
   T.bz = p->tile_z ? p->tile_z : 4;
-  T.xcd_order = p->tile_order == 0 ? 1 : (p->tile_order == 1 ? 0 : -1);
-  if (T.bx < 1 || T.by < 1 || T.bz < 1 || T.bx * T.by * T.bz != kBlock || T.xcd_order < 0)
-    return set_error(COSMOS_EINVAL, "tile %dx%dx%d (order %d) invalid: need tile_x*tile_y*tile_z == %d, order 0 or 1",
-                     T.bx, T.by, T.bz, p->tile_order, kBlock);
+  T.order = p->tile_order;
+  T.xcd_order = p->tile_order == 0 ? 1 : 0;  // the direct variant treats order 2 as linear
+  if (T.bx < 1 || T.by < 1 || T.bz < 1 || T.bx * T.by * T.bz != kBlock || T.order < 0 || T.order > 2)
+    return set_error(COSMOS_EINVAL,
+                     "tile %dx%dx%d (order %d) invalid: need tile_x*tile_y*tile_z == %d, order 0, 1 or 2", T.bx, T.by,
+                     T.bz, p->tile_order, kBlock);
+  T.gx = T.gy = T.gz = T.zr = T.ngx = T.ngy = T.ngroups = 0;  // set at launch for order 2
   T.nbx = (g->n[0] + T.bx - 1) / T.bx;
   T.nby = (g->n[1] + T.by - 1) / T.by;
   T.nbz = (g->n[2] + T.bz - 1) / T.bz;
@@ -238,25 +241,47 @@ __global__ __launch_bounds__(kBlock) void k_bssn_stage_lds(const double* U, cons
   using B = Brick<BX, BY, BZ>;
   using Sink = StageSink<MODE>;
   __shared__ double smem[B::LDS_DOUBLES];
-  // brick number `it` of this workgroup: origin, and this thread's point (c = 0 outside the grid)
-  auto locate = [&](int it, int& i0, int& j0, int& k0, int& c, bool& act) -> bool {
-    const int v = blockIdx.x + it * gridDim.x;
-    int brick = v;
-    if (T.xcd_order) {
-      if ((v >> 3) >= T.per) return false;
-      brick = (v & 7) * T.per + (v >> 3);
+  // brick number `it` of this workgroup (all uniform): 1 = a brick (origin, and this
+  // thread's point, c = 0 outside the grid), 0 = none in this round, -1 = no more
+  auto locate = [&](int it, int& i0, int& j0, int& k0, int& c, bool& act) -> int {
+    int bxi, byi, bzi;
+    if (T.order == 2) {
+      if (it >= T.ngroups) return -1;
+      const int l = blockIdx.x >> 3, gxy = T.ngx * T.ngy;
+      bxi = (it % T.ngx) * T.gx + l % T.gx;
+      byi = ((it / T.ngx) % T.ngy) * T.gy + (l / T.gx) % T.gy;
+      const int bzl = (it / gxy) * T.gz + l / (T.gx * T.gy);
+      bzi = (blockIdx.x & 7) * T.zr + bzl;
+      if (bxi >= T.nbx || byi >= T.nby || bzl >= T.zr || bzi >= T.nbz) return 0;
+    } else {
+      const int v = blockIdx.x + it * gridDim.x;
+      int brick = v;
+      if (T.order == 0) {
+        if ((v >> 3) >= T.per) return -1;
+        brick = (v & 7) * T.per + (v >> 3);
+      }
+      if (brick >= T.nbricks) return -1;  // bricks increase with `it`: none after this one
+      bxi = brick % T.nbx;
+      byi = (brick / T.nbx) % T.nby;
+      bzi = brick / (T.nbx * T.nby);
     }
-    if (brick >= T.nbricks) return false;  // bricks increase with `it`: none after this one
-    const int bxi = brick % T.nbx, byz = brick / T.nbx;
-    i0 = bxi * BX, j0 = (byz % T.nby) * BY, k0 = (byz / T.nby) * BZ;
+    i0 = bxi * BX, j0 = byi * BY, k0 = bzi * BZ;
     const int i = i0 + threadIdx.x % BX, j = j0 + (threadIdx.x / BX) % BY, k = k0 + threadIdx.x / (BX * BY);
     act = i < P.n[0] && j < P.n[1] && k < P.n[2];
     c = act ? i + P.n[0] * (j + P.n[1] * k) : 0;
-    return true;
+    return 1;
+  };
+  // the first brick at or after round `it`; -1 when there is none
+  auto next_brick = [&](int it, int& i0, int& j0, int& k0, int& c, bool& act) -> int {
+    for (;; ++it) {
+      const int r = locate(it, i0, j0, k0, c, act);
+      if (r != 0) return r > 0 ? it : -1;
+    }
   };
   int i0, j0, k0, c;
   bool active;
-  if (!locate(0, i0, j0, k0, c, active)) return;  // uniform over the workgroup
+  int it = next_brick(0, i0, j0, k0, c, active);
+  if (it < 0) return;  // uniform over the workgroup
   LdsCarry<B, typename Sink::Pre> cy;
   cy.hc.init(i0, j0, k0, P.n);
   {
@@ -264,11 +289,12 @@ __global__ __launch_bounds__(kBlock) void k_bssn_stage_lds(const double* U, cons
     lds_carry_fill(cy, U, fs, s0, c);
   }
   unsigned long long nfail = 0, nbad = 0, ncoll = 0, nstep = 0;
-  for (int it = 0;; ++it) {
+  for (;;) {
     NextBrick<B> nx;
     int ni0, nj0, nk0;
     bool nact = false;
-    nx.valid = locate(it + 1, ni0, nj0, nk0, nx.c, nact);
+    const int nit = next_brick(it + 1, ni0, nj0, nk0, nx.c, nact);
+    nx.valid = nit >= 0;
     if (nx.valid) HaloCopy<B>::offsets(ni0, nj0, nk0, P.n, nx.goffb);
     Sink sink{un, acc, out, fs, c, ca, cn, P.alpha_collapse};
     bool fail = false;
@@ -285,6 +311,7 @@ __global__ __launch_bounds__(kBlock) void k_bssn_stage_lds(const double* U, cons
     __syncthreads();  // the halo buffers are reused by the next brick
     c = nx.c;
     active = nact;
+    it = nit;
   }
   if (nfail) atomicAdd(&status[1], nfail);
   if constexpr (MODE == 3) {
@@ -318,12 +345,43 @@ unsigned resident_groups(K kernel) {
   return n;
 }
 
+// Block of bricks processed together by the W resident workgroups of one XCD in the
+// XCD-blocked order: gx gy gz = W, the smallest halo-to-interior ratio of the block
+// among the divisor triples that fit the XCD's slab of the brick grid.
+bool blocked_order(Tile& T, unsigned W) {
+  T.zr = (T.nbz + 7) / 8;
+  double best = 1e300;
+  for (int gx = 1; gx <= (int)W; ++gx) {
+    if (W % gx || gx > T.nbx) continue;
+    for (int gy = 1; gy <= (int)W / gx; ++gy) {
+      if ((W / gx) % gy || gy > T.nby) continue;
+      const int gz = (int)W / (gx * gy);
+      if (gz > T.zr) continue;
+      const double ex = gx * T.bx + 6.0, ey = gy * T.by + 6.0, ez = gz * T.bz + 6.0;
+      const double ratio = ex * ey * ez / (double(W) * kBlock);
+      if (ratio < best) best = ratio, T.gx = gx, T.gy = gy, T.gz = gz;
+    }
+  }
+  if (!(best < 1e300)) return false;
+  T.ngx = (T.nbx + T.gx - 1) / T.gx;
+  T.ngy = (T.nby + T.gy - 1) / T.gy;
+  T.ngroups = T.ngx * T.ngy * ((T.zr + T.gz - 1) / T.gz);
+  return true;
+}
+
 template <class K>
-void launch_persistent(K kernel, const Tile& T, hipStream_t s, const double* U, const double* F, const double* un,
+void launch_persistent(K kernel, const Tile& T0, hipStream_t s, const double* U, const double* F, const double* un,
                        double* acc, double* out, size_t fs, const DevParams& P, double t, double ca, double cn,
                        unsigned long long* status) {
-  const dim3 g(std::min(tile_blocks(T), resident_groups(kernel))), b(kBlock);
-  hipLaunchKernelGGL(kernel, g, b, 0, s, U, F, un, acc, out, fs, P, T, t, ca, cn, status);
+  Tile T = T0;
+  const unsigned G = resident_groups(kernel);
+  unsigned grid = std::min(tile_blocks(T), G);
+  if (T.order == 2) {
+    // needs every XCD busy with whole blocks; small grids fall back to the linear order
+    if (T.nbricks >= (int)G && blocked_order(T, G / 8)) grid = G;
+    else T.order = 1;
+  }
+  hipLaunchKernelGGL(kernel, dim3(grid), dim3(kBlock), 0, s, U, F, un, acc, out, fs, P, T, t, ca, cn, status);
 }
 
 template <int M>
