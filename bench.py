@@ -2,11 +2,11 @@
 fluid hot path on one MI355X, on the 256^3 periodic configuration (box 16/H0,
 Gaussian curvature perturbation mu = 0.6, sigma = 2.0, CFL 0.25).
 
-One step = one classic RK4 step = 4 launches of the stage kernel
-(k_bssn_stage), inputs resident in HBM. Prints one JSON line with the
-roofline of that kernel (algorithmic bytes per launch / average launch time,
-measured with HIP events on the launch stream) and the CPU oracle timed on a
-bounded sample of the same workload.
+One step = one classic RK4 step = 4 stages, each a pointwise flux pre-pass
+(k_fluid_flux) plus the stage kernel (k_bssn_stage_lds), inputs resident in HBM.
+Prints one JSON line with the roofline of a stage (algorithmic bytes per stage /
+average stage time, measured with HIP events on the launch stream around the
+timed steps) and the CPU oracle timed on a bounded sample of the same workload.
 
 Extra modes:
   --batched      the 64-run threshold-scan workload (grid sizes drawn from
@@ -284,7 +284,8 @@ def main():
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(config_name(kv, tile, order), npts),
             "traffic_unit": "bytes per launch", "algorithmic_bytes_per_launch": round(bytes_launch),
-            "kernel": f"k_bssn_stage_lds<{tile[0]},{tile[1]},{tile[2]}>" if kv == 0 else "k_bssn_stage",
+            "kernel": (f"k_bssn_stage_lds<{tile[0]},{tile[1]},{tile[2]}>" if kv == 0 else "k_bssn_stage") +
+                      " + k_fluid_flux pre-pass (one RK4 stage)",
             "avg_launch_ms": round(launch_s * 1e3, 4),
             "fp64_tflops_algorithmic": round(fl * npts * a.steps / (ms / 1e3) / 1e12, 2),
             "fp64_frac": round(fl * npts * a.steps / (ms / 1e3) / 1e12 / FP64_PEAK_TFLOPS, 4)}
