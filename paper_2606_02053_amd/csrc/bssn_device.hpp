@@ -460,7 +460,7 @@ __device__ __forceinline__ void connection_and_quadratic_ricci(const double dgt[
 // Conformal-factor part of the Ricci tensor added to Ric:
 //   (1/2chi)(DDchi_ij + gt_ij gt^lm DDchi_lm) - (1/4chi^2)(d_i chi d_j chi + 3 gt_ij gt^lm d_l chi d_m chi),
 // DDchi_ij = d_i d_j chi - Gt^k_ij d_k chi.
-__device__ __forceinline__ void ricci_conformal_factor(double chi, const double dchi[3], const double d2chi[6],
+__device__ __forceinline__ void ricci_conformal_factor(double ichi, const double dchi[3], const double d2chi[6],
                                                        const double gt[6], const double gi[6], const double Gu[3][6],
                                                        double Ric[6]) {
   double DD[6];
@@ -472,7 +472,7 @@ __device__ __forceinline__ void ricci_conformal_factor(double chi, const double 
   for (int l = 0; l < 3; ++l)
 #pragma unroll
     for (int m = 0; m < 3; ++m) dc2 += gi[S(l, m)] * dchi[l] * dchi[m];
-  const double ih = 0.5 / chi, iq = 0.25 / (chi * chi);
+  const double ih = 0.5 * ichi, iq = 0.25 * (ichi * ichi);  // ichi = 1 / chi
 #pragma unroll
   for (int s = 0; s < 6; ++s) Ric[s] += ih * (DD[s] + gt[s] * trDD) - iq * (dchi[SI(s)] * dchi[SJ(s)] + 3.0 * gt[s] * dc2);
 }
@@ -651,7 +651,7 @@ __device__ __forceinline__ void bssn_rhs_stream(const double* U, const double* F
     }
     FieldDerivs d;
     field_derivs<true, true>(U + F_CHI * fs, nb, P, beta, d);
-    ricci_conformal_factor(chi, d.d1, d.d2, gt, gi, Gu, Ric);
+    ricci_conformal_factor(1.0 / chi, d.d1, d.d2, gt, gi, Gu, Ric);
 #pragma unroll
     for (int q = 0; q < 6; ++q) R[R_RIC + q] = Ric[q];
 #pragma unroll

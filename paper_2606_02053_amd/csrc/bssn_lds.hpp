@@ -221,6 +221,7 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
 
   // centre values (registers); inactive threads hold a valid point's values and never store
   const double chi = cy.cen[F_CHI];
+  const double ichi = 1.0 / chi;
   const double K = cy.cen[F_K];
   const double alpha = cy.cen[F_ALP];
   double gt[6], beta[3], At[6], Gam[3];
@@ -288,10 +289,11 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
     __syncthreads();
     ++phase;
   };
-  auto S_up = [&](int j) {  // S^j = chi gt^jk S_k
-    return chi * (R[R3_GI + S(j, 0)] * R[R3_S + 0] + R[R3_GI + S(j, 1)] * R[R3_S + 1] + R[R3_GI + S(j, 2)] * R[R3_S + 2]);
-  };
-  auto Sjk_at = [&](int s) { return S_up(SI(s)) * S_up(SJ(s)) * R[R3_IX] + R[R3_P] * chi * R[R3_GI + s]; };
+  double Sup[3];  // S^j = chi gt^jk S_k
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+    Sup[j] = chi * (R[R3_GI + S(j, 0)] * R[R3_S + 0] + R[R3_GI + S(j, 1)] * R[R3_S + 1] + R[R3_GI + S(j, 2)] * R[R3_S + 2]);
+  auto Sjk_at = [&](int s) { return Sup[SI(s)] * Sup[SJ(s)] * R[R3_IX] + R[R3_P] * chi * R[R3_GI + s]; };
 
   // ---- shift
 #pragma unroll
@@ -397,7 +399,7 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
     }
     FieldDerivs d;
     lds_derivs<B, true, true>(cur(), P, beta, d);
-    ricci_conformal_factor(chi, d.d1, d.d2, gt, gi, Gu, Ric);
+    ricci_conformal_factor(ichi, d.d1, d.d2, gt, gi, Gu, Ric);
 #pragma unroll
     for (int q = 0; q < 6; ++q) R[R3_RX + q] = Ric[q];
 #pragma unroll
@@ -427,7 +429,7 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
     for (int k = 0; k < 3; ++k)
 #pragma unroll
       for (int l = 0; l < 3; ++l) cda += gi[S(k, l)] * dchi[k] * dal[l];
-    const double ih = 0.5 / chi;
+    const double ih = 0.5 * ichi;
     double DDa[6];
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
@@ -438,7 +440,6 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
     R[R3_D2A] = chi * contract_sym(gi, DDa);
     const double Kbg = P.lapse_bg ? -3.0 * P.H0 / (1.0 + 2.0 * P.H0 * t) : 0.0;
     sink.put(F_ALP, d.advko - 2.0 * alpha * (K - Kbg), ep[0][0]);
-    const double ichi = 1.0 / chi;
     const double ix = R[R3_IX], pr = R[R3_P];
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
@@ -450,7 +451,9 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
   }
   advance(0);
 
-  // ---- trace K, and the final Gt^i right-hand side
+  // ---- trace K, and the final Gt^i right-hand side. Amix = gt^kl At_lj and one third of
+  // the trace gt^ij X_ij are kept for the At phases.
+  double Amix[3][3], trX3 = 0.0;
   prefetch();
   if (active) {
     double gi[6];
@@ -458,7 +461,12 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
     for (int q = 0; q < 6; ++q) gi[q] = R[R3_GI + q];
     FieldDerivs d;
     lds_derivs<B, false, true>(cur(), P, beta, d);
-    double Amix[3][3];
+    {
+      double X[6];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) X[q] = R[R3_RX + q];
+      trX3 = contract_sym(gi, X) * (1.0 / 3.0);
+    }
 #pragma unroll
     for (int k = 0; k < 3; ++k)
 #pragma unroll
@@ -470,9 +478,6 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
       Aup[s] = Amix[i][0] * gi[S(0, j)] + Amix[i][1] * gi[S(1, j)] + Amix[i][2] * gi[S(2, j)];
     }
     const double AA = contract_sym(At, Aup);
-    double Sup[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) Sup[q] = S_up(q);
     const double Str = (Sup[0] * R[R3_S + 0] + Sup[1] * R[R3_S + 1] + Sup[2] * R[R3_S + 2]) * R[R3_IX] + 3.0 * R[R3_P];
     sink.put(F_K, d.advko + (-R[R3_D2A] + alpha * (AA + K * K * (1.0 / 3.0)) + 4.0 * PI_D * alpha * (R[R3_E] + Str)),
              ep[0][0]);
@@ -497,7 +502,7 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
       r += (2.0 / 3.0) * Gd[i] * divb;
       r -= 2.0 * (Aup[S(i, 0)] * R[R3_DAL + 0] + Aup[S(i, 1)] * R[R3_DAL + 1] + Aup[S(i, 2)] * R[R3_DAL + 2]);
       double inner = contract_sym(Gu, Aup);
-      inner -= (1.5 / chi) * (Aup[S(i, 0)] * R[R3_DCHI + 0] + Aup[S(i, 1)] * R[R3_DCHI + 1] + Aup[S(i, 2)] * R[R3_DCHI + 2]);
+      inner -= (1.5 * ichi) * (Aup[S(i, 0)] * R[R3_DCHI + 0] + Aup[S(i, 1)] * R[R3_DCHI + 1] + Aup[S(i, 2)] * R[R3_DCHI + 2]);
       r += 2.0 * alpha * inner;
       r -= 16.0 * PI_D * alpha * (gi[S(i, 0)] * R[R3_S + 0] + gi[S(i, 1)] * R[R3_S + 1] + gi[S(i, 2)] * R[R3_S + 2]);
       sink.put(F_GAM + i, r, ep[0][1 + i]);
@@ -521,12 +526,7 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
     if (active) {
       if (s == 4) flux_var_load(F, fs, c, fnb, 0, fa);
       if (s == 5) flux_var_load(F, fs, c, fnb, 1, fb);
-      double gi[6], X[6], db[3][3];
-#pragma unroll
-      for (int q = 0; q < 6; ++q) {
-        gi[q] = R[R3_GI + q];
-        X[q] = R[R3_RX + q];
-      }
+      double db[3][3];
 #pragma unroll
       for (int q = 0; q < 9; ++q) db[q / 3][q % 3] = R[R3_DB + q];
       const int i = SI(s), j = SJ(s);
@@ -536,11 +536,10 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
 #pragma unroll
       for (int k = 0; k < 3; ++k) r += At[S(i, k)] * db[k][j] + At[S(j, k)] * db[k][i];
       r -= (2.0 / 3.0) * At[s] * (db[0][0] + db[1][1] + db[2][2]);
-      r += chi * (X[s] - gt[s] * contract_sym(gi, X) * (1.0 / 3.0));
-      double AAij = 0.0;
+      r += chi * (R[R3_RX + s] - gt[s] * trX3);
+      double AAij = 0.0;  // At_ik gt^kl At_lj
 #pragma unroll
-      for (int k = 0; k < 3; ++k)
-        AAij += At[S(i, k)] * (gi[S(k, 0)] * At[S(0, j)] + gi[S(k, 1)] * At[S(1, j)] + gi[S(k, 2)] * At[S(2, j)]);
+      for (int k = 0; k < 3; ++k) AAij += At[S(i, k)] * Amix[k][j];
       r += alpha * (K * At[s] - 2.0 * AAij);
       sink.put(F_AT + s, r, ep[0][0]);
     }
@@ -550,6 +549,7 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
   // ---- fluid: flux divergence (fluxes from the pointwise pre-pass), sources, dissipation
   const double nbeta[3] = {0.0, 0.0, 0.0};
   const double im32 = 1.0 / (chi * sqrt(chi));
+  double sgt = 0.0;  // S^jk gt_jk (formed in the Et phase, used by the St phases)
   prefetch();
   if (active) {
     const double div0 = flux_var_div(fa, P);
@@ -557,12 +557,13 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
     double KS = 0.0;
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
-      const double Kij = (At[s] + gt[s] * K * (1.0 / 3.0)) / chi;
-      KS += (s == 0 || s == 3 || s == 5 ? 1.0 : 2.0) * Kij * Sjk_at(s);
+      const double Sjk = Sjk_at(s), wS = (s == 0 || s == 3 || s == 5 ? 1.0 : 2.0) * Sjk;
+      KS += wS * ((At[s] + gt[s] * K * (1.0 / 3.0)) * ichi);
+      sgt += wS * gt[s];
     }
     FieldDerivs d;
     lds_derivs<B, false, false>(cur(), P, nbeta, d);
-    const double Sda = S_up(0) * R[R3_DAL + 0] + S_up(1) * R[R3_DAL + 1] + S_up(2) * R[R3_DAL + 2];
+    const double Sda = Sup[0] * R[R3_DAL + 0] + Sup[1] * R[R3_DAL + 1] + Sup[2] * R[R3_DAL + 2];
     sink.put(F_ET, d.advko + (im32 * (alpha * KS - Sda) - div0), ep[0][0]);
   }
   advance(0);
@@ -583,14 +584,10 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
       } else {
         divi = flux_var_div(i == 1 ? fa : fb, P);
       }
-      double sgt = 0.0;
-#pragma unroll
-      for (int s = 0; s < 6; ++s) sgt += (s == 0 || s == 3 || s == 5 ? 1.0 : 2.0) * Sjk_at(s) * gt[s];
       FieldDerivs d;
       lds_derivs<B, false, false>(cur(), P, nbeta, d);
       double src = -R[R3_E] * R[R3_DAL + i] +
                    (R[R3_S + 0] * R[R3_DB + 0 + i] + R[R3_S + 1] * R[R3_DB + 3 + i] + R[R3_S + 2] * R[R3_DB + 6 + i]);
-      const double ichi = 1.0 / chi;
       src += 0.5 * alpha * (R[R3_SG + i] * ichi - sgt * R[R3_DCHI + i] * (ichi * ichi));
       sink.put(F_ST + i, d.advko + (im32 * src - divi), ep[0][0]);
     }

@@ -64,7 +64,7 @@ __device__ __forceinline__ void constraint_point(const double* __restrict__ U, s
     field_derivs<true, false, false>(U + F_CHI * fs, nb, P, nob, d);
 #pragma unroll
     for (int a = 0; a < 3; ++a) dchi[a] = d.d1[a];
-    ricci_conformal_factor(chi, dchi, d.d2, gt, gi, Gu, Ric);
+    ricci_conformal_factor(1.0 / chi, dchi, d.d2, gt, gi, Gu, Ric);
   }
   const double R = chi * contract_sym(gi, Ric);
 
