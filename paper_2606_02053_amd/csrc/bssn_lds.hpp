@@ -170,13 +170,18 @@ struct LdsCarry {
   double cen[NF];
 };
 
-// The brick a workgroup processes next (valid is uniform): its halo offsets and
-// this thread's point in it (0 for a thread outside the grid).
+// The brick a workgroup processes next (valid is uniform): its halo offsets, this
+// thread's point in it (0 for a thread outside the grid), and the arrays and field
+// size of its grid (another run's in the batched form; the current ones otherwise).
 template <class B>
 struct NextBrick {
   bool valid;
   int c;
   uint32_t goffb[B::NQ];
+  const double* U;   // stage input
+  const double* un;  // RK4 epilogue operands
+  const double* acc;
+  size_t fs;
 };
 
 // Loads of the first brick of a workgroup (later bricks are prefetched during the
@@ -243,7 +248,8 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
     } else if (nx.valid) {
 #pragma unroll
       for (int k = 0; k < 4; ++k)
-        if (k < kPutCount[ph - NF]) ep[decltype(slot)::value][k] = sink.preload_at(kPutField[ph - NF][k], nx.c);
+        if (k < kPutCount[ph - NF])
+          ep[decltype(slot)::value][k] = sink.preload_from(kPutField[ph - NF][k], nx.c, nx.un, nx.acc, nx.fs);
     }
   };
   {
@@ -277,7 +283,8 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
     if (phase + kPrefetch < NF)
       hc.template fetch<kPrefetch - 1>(field_ptr(U, kStageOrder[phase + kPrefetch], fs), nbytes);
     else if (nx.valid)
-      hc.template fetch_at<kPrefetch - 1>(field_ptr(U, kStageOrder[phase + kPrefetch - NF], fs), nbytes, nx.goffb);
+      hc.template fetch_at<kPrefetch - 1>(field_ptr(nx.U, kStageOrder[phase + kPrefetch - NF], nx.fs),
+                                          (uint32_t)(nx.fs * 8), nx.goffb);
     epi_load(phase + kEpiAhead, std::integral_constant<int, kEpiAhead>());
   };
   auto advance = [&](int) {
@@ -573,7 +580,7 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
     prefetch();
     if (i == 0 && nx.valid) {
 #pragma unroll
-      for (int f = 0; f < NF; ++f) cnext[f] = bld(field_ptr(U, f, fs), nbytes, (uint32_t)nx.c * 8u);
+      for (int f = 0; f < NF; ++f) cnext[f] = bld(field_ptr(nx.U, f, nx.fs), (uint32_t)(nx.fs * 8), (uint32_t)nx.c * 8u);
     }
     if (active) {
       // St_0: q = 1 (loaded in At phase 5), then issue q = 3; St_1: q = 2; St_2: q = 3

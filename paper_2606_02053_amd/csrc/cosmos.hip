@@ -171,12 +171,15 @@ struct StageSink {
     double u0, a0;
   };
   __device__ __forceinline__ Pre preload(int f) const { return preload_at(f, c); }
-  __device__ __forceinline__ Pre preload_at(int f, int cp) const {
-    const uint32_t nb = (uint32_t)(fs * 8), cb = (uint32_t)cp * 8u;
-    const size_t o = field_off(f, fs);
+  __device__ __forceinline__ Pre preload_at(int f, int cp) const { return preload_from(f, cp, un, acc, fs); }
+  // the same for point cp of another grid (arrays un_, acc_ with field size fs_)
+  __device__ __forceinline__ Pre preload_from(int f, int cp, const double* un_, const double* acc_,
+                                              size_t fs_) const {
+    const uint32_t nb = (uint32_t)(fs_ * 8), cb = (uint32_t)cp * 8u;
+    const size_t o = field_off(f, fs_);
     Pre p{0.0, 0.0};
-    if constexpr (MODE == 1 || MODE == 2) p.u0 = bld(un + o, nb, cb);
-    if constexpr (MODE >= 2) p.a0 = bld(acc + o, nb, cb);
+    if constexpr (MODE == 1 || MODE == 2) p.u0 = bld(un_ + o, nb, cb);
+    if constexpr (MODE >= 2) p.a0 = bld(acc_ + o, nb, cb);
     return p;
   }
   __device__ __forceinline__ void put(int f, double r, const Pre& p) {
@@ -295,6 +298,7 @@ __global__ __launch_bounds__(kBlock) void k_bssn_stage_lds(const double* U, cons
     bool nact = false;
     const int nit = next_brick(it + 1, ni0, nj0, nk0, nx.c, nact);
     nx.valid = nit >= 0;
+    nx.U = U, nx.un = un, nx.acc = acc, nx.fs = fs;
     if (nx.valid) HaloCopy<B>::offsets(ni0, nj0, nk0, P.n, nx.goffb);
     Sink sink{un, acc, out, fs, c, ca, cn, P.alpha_collapse};
     bool fail = false;
