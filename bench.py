@@ -258,7 +258,7 @@ def main():
     sol = P.Solver(n, L)
     sol.init(mu=0.6, sigma=2.0)
     dt = sol.default_dt()
-    kv, tile, order = 0, (16, 4, 4), 0
+    kv, tile, order = 0, (16, 4, 4), 2
     if a.config:
         kv, tile, order = parse_config(a.config)
     elif not a.no_tune:  # untimed: picks kernel variant and brick (cached per arch and grid)

@@ -126,7 +126,9 @@ def make_grid(n, L) -> cosmos_grid:
 
 
 def make_params(w=1.0 / 3.0, H0=1.0, eta=1.0, ko_eps=0.1, lapse_bg=1, evolve_shift=1, fluid_scheme=0,
-                alpha_collapse=0.0, tile=(0, 0, 0), tile_order=0, variant=0) -> cosmos_params:
+                alpha_collapse=0.0, tile=(0, 0, 0), tile_order=2, variant=0) -> cosmos_params:
+    """Defaults: radiation (w = 1/3), H0 = 1, Gamma-driver eta = 1, KO eps = 0.1, background-
+    subtracted 1+log lapse, evolved shift; LDS-staged kernel, 16x4x4 bricks, XCD-blocked order."""
     return cosmos_params(w, H0, eta, ko_eps, lapse_bg, evolve_shift, fluid_scheme, variant, alpha_collapse,
                          int(tile[0]), int(tile[1]), int(tile[2]), int(tile_order))
 

@@ -193,11 +193,14 @@ def test_status_counts_match_oracle(P, orc):
     assert norms[5] == rn[5]
 
 
-def test_bench_configuration_sampled(P, orc):
-    """256^3, L = 16, Gaussian zeta mu = 0.6, sigma = 2: initial data, one RHS and one RK4 step
-    in the launch configuration the benchmark times, checked at sampled points."""
-    n, L = (256, 256, 256), (16.0, 16.0, 16.0)
+@pytest.mark.parametrize("nn", [256, 384])
+def test_bench_configuration_sampled(P, orc, nn):
+    """256^3 and 384^3, L = 16, Gaussian zeta mu = 0.6, sigma = 2: initial data, one RHS and one
+    RK4 step in the launch configuration the benchmark times (LDS-staged 16x4x4 bricks, XCD-blocked
+    order, persistent workgroups), checked at sampled points."""
+    n, L = (nn, nn, nn), (16.0, 16.0, 16.0)
     s, sol = mk(P, orc, n, L)
+    assert (sol.params.variant, sol.params.tile_order) == (0, 2)
     ini = dict(mu=0.6, sigma=2.0)
     sol.init(**ini)
     pts = sample_points(n, 24, seed=1)
