@@ -143,22 +143,31 @@ __device__ __forceinline__ void red_store(double* p, const Red& r) {
 }
 __device__ __forceinline__ Red red_load(const double* p) { return {p[0], p[1], p[2], p[3], p[4], p[5], p[6], p[7]}; }
 
-// Fixed-shape tree over the 256 entries of a block (entry t combines with t + stride).
+// Wavefront reduction, then one step across the block's four waves: lane l combines
+// with lane l ^ m for m = 32, 16, ..., 1 (cross-lane moves, no LDS round trips), lane 0
+// of each wave parks its wave's result in LDS, and thread 0 combines the four in a
+// fixed order. The order never depends on timing, so the result is bitwise reproducible.
+__device__ __forceinline__ Red red_shfl_xor(const Red& a, int m) {
+  return {__shfl_xor(a.sH2, m), __shfl_xor(a.sM2, m),  __shfl_xor(a.sHn2, m), __shfl_xor(a.mH, m),
+          __shfl_xor(a.mM, m),  __shfl_xor(a.nbad, m), __shfl_xor(a.minA, m), __shfl_xor(a.arg, m)};
+}
+
 __device__ __forceinline__ Red block_tree(Red mine, Red* sh) {
-  const int t = threadIdx.x;
-  sh[t] = mine;
-  __syncthreads();
-  for (int stride = 128; stride > 0; stride >>= 1) {
-    if (t < stride) sh[t] = red_combine(sh[t], sh[t + stride]);
-    __syncthreads();
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) {
+    const Red o = red_shfl_xor(mine, m);
+    // the lower lane of each pair keeps the left operand, so both lanes hold the same value
+    mine = ((threadIdx.x & m) == 0) ? red_combine(mine, o) : red_combine(o, mine);
   }
-  return sh[0];
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = mine;
+  __syncthreads();
+  return red_combine(red_combine(sh[0], sh[1]), red_combine(sh[2], sh[3]));
 }
 
 __global__ __launch_bounds__(256) void k_constraints(const double* __restrict__ U, size_t fs, DevParams P,
                                                       double* __restrict__ Hout, double* __restrict__ Mout,
                                                       double* __restrict__ part) {
-  __shared__ Red sh[256];
+  __shared__ Red sh[4];  // one entry per wave
   const int p = blockIdx.x * 256 + threadIdx.x;
   Red mine = red_neutral();
   if (p < (int)fs) {
@@ -194,7 +203,7 @@ __global__ __launch_bounds__(256) void k_constraints(const double* __restrict__ 
 
 __global__ __launch_bounds__(256) void k_reduce_partials(const double* __restrict__ part, int nblocks, size_t N3,
                                                           double* __restrict__ norms) {
-  __shared__ Red sh[256];
+  __shared__ Red sh[4];  // one entry per wave
   Red acc = red_neutral();
   for (int b = threadIdx.x; b < nblocks; b += 256) acc = red_combine(acc, red_load(part + (size_t)b * kRedRecord));
   const Red r = block_tree(acc, sh);
