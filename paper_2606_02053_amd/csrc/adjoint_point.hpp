@@ -1,17 +1,17 @@
 // Hand-written reverse mode of the pointwise part of the right-hand side (and
 // of the fluid fluxes), for the discrete adjoint of the RK4 step.
 //
-// pt_forward evaluates the pointwise algebra of one point -- everything except
-// the advection, dissipation and flux-divergence stencils -- from the point
-// values and the finite-difference derivatives (the same equations as the
-// stage kernel: conformal connection and Ricci tensor, second covariant
-// derivative of the lapse, perfect-fluid recovery and projections, the BSSN
-// and fluid source terms), keeping its intermediates. pt_reverse then walks the
-// same statements backwards: given the cotangent rbar of the 25 outputs it
-// accumulates the cotangents of every input (dy = a dx  =>  xbar += a ybar).
-// flux_forward / flux_reverse do the same for the fluxes of the densitised
-// fluid variables along one axis. Branches (recovery clamps) are taken exactly
-// as in the forward evaluation, so this is the derivative of the discrete map.
+// pt_vjp forms the cotangents of every input of the pointwise algebra at one
+// point -- point values, first and second finite differences -- from the
+// cotangents of the 25 outputs: the same equations as the stage kernel
+// (conformal connection and Ricci tensor, second covariant derivative of the
+// lapse, perfect-fluid recovery and projections, the BSSN and fluid source
+// terms) without the advection, dissipation and flux-divergence stencils.
+// flux_forward / flux_reverse do the same for the fluxes of the densitised fluid
+// variables along one axis. The building blocks (inverse metric, fluid recovery)
+// come as forward/reverse pairs: dy = a dx gives xbar += a ybar. Branches
+// (recovery clamps) are taken exactly as in the forward evaluation, so this is
+// the derivative of the discrete map.
 //
 // __host__ __device__ so that the algebra can also be checked on the CPU.
 #pragma once
@@ -22,14 +22,6 @@
 #include "bssn_device.hpp"
 
 namespace cosmos {
-
-// Inputs of the pointwise algebra at one point. dX[c][a] = d_a X_c.
-struct PtIn {
-  double chi, gt[6], K, At[6], Gam[3], alpha, beta[3];
-  double dchi[3], d2chi[6], dgt[6][3], d2gt[6][6], dGam[3][3], dalpha[3], d2alpha[6], dbeta[3][3], d2beta[3][6];
-  double dK[3], dAt[6][3];  // dAt: constraint input, unused by the right-hand side
-  double Et, St[3];
-};
 
 __host__ __device__ inline double wsym(int s) { return (s == 0 || s == 3 || s == 5) ? 1.0 : 2.0; }
 
@@ -215,507 +207,672 @@ __host__ __device__ inline void flux_reverse(double w, int a, const FluxIn& in, 
   inv_reverse(in.gt, I, gib, b.gt);
 }
 
-// ---------------------------------------------------------------- pointwise right-hand side
-struct PtTape {
-  InvTape I;
-  RecTape R;
-  double ichi, Sjk[6], Sij[6], Str;
-  double Gl[3][6], Gu[3][6], Gd[3];
-  double DDchi[6], trDD, dc2;
-  double Ric[6];
-  double cda, DDa[6], D2a;
-  double Amix[3][3], Aup[6], AA, divb;
-  double X6[6], trX;
-  double Kij[6], KS, im32, sg[3], sgt, Sda;
-  double Kbg;
-};
-
-__host__ __device__ inline void pt_forward(const DevParams& P, double t, const PtIn& in, PtTape& T, double r[NF],
-                                           bool& fail) {
-  const double* gt = in.gt;
-  const double chi = in.chi, K = in.K, alpha = in.alpha;
-  inv_forward(gt, T.I);
-  const double* gi = T.I.gi;
-  fail = rec_forward(P.w, chi, gi, in.Et, in.St, T.R);
-  const RecTape& R = T.R;
-  T.ichi = 1.0 / chi;
-  for (int s = 0; s < 6; ++s) {
-    const int i = SI(s), j = SJ(s);
-    T.Sjk[s] = R.Sup[i] * R.Sup[j] * R.invX + R.P * chi * gi[s];
-    T.Sij[s] = R.S[i] * R.S[j] * R.invX + R.P * gt[s] * T.ichi;
+// ---------------------------------------------------------------- vector-Jacobian product at one point
+// A reverse sweep taped in statement order would keep every forward
+// intermediate and every input cotangent live at once (several hundred doubles
+// per point, far beyond the registers of a wavefront). The algebra is only a few
+// layers deep, though: the cotangent of every intermediate that feeds an output
+// directly (the curvature source X_ij and its trace, the Ricci tensor, the
+// Hessians of chi and alpha, the matter projections) is fixed by the output
+// cotangents and the point values alone, and only the connection coefficients
+// need a reverse of their own. So the sweep runs forwards through the inputs:
+// metric and output cotangents first; then the first differences of chi, alpha
+// and beta; then the connection (the metric's first differences) with its
+// reverse; then the metric's second differences, d_a Gamma^k, the shift's second
+// differences and d_a K, one field at a time; last the terms of the point values
+// and the fluid. Forward values are formed where they are used (nothing is
+// taped), and every cotangent is handed to `out` as soon as it is final:
+//   out.val(f, v)    cotangent of the point value of field f,
+//   out.d1(f, a, v)  of its first difference along a,
+//   out.d2(f, q, v)  of its second difference, symmetric pair q.
+// `src` provides the inputs where they are needed -- val(f) and cot(f), the point
+// value and the output cotangent of field f; d1(f, d[3]), d12(f, d1[3], d2[6]) and
+// d2(f, d2[6]), its differences -- fence(), a point across which device code is
+// not to be reordered, and pin(x), which makes x be formed before the code goes on
+// (both no-ops on the host).
+template <class Src, class Sink>
+__host__ __device__ inline void pt_vjp(const DevParams& P, double t, const Src& src, Sink& out) {
+  const double third = 1.0 / 3.0;
+  const double chi = src.val(F_CHI), alpha = src.val(F_ALP);
+  double gt[6], gi[6];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) gt[s] = src.val(F_GT + s);
+  {
+    InvTape I;
+    inv_forward(gt, I);
+#pragma unroll
+    for (int s = 0; s < 6; ++s) gi[s] = I.gi[s];
   }
-  T.Str = R.S2 * R.invX + 3.0 * R.P;
-  // connection
-  for (int k = 0; k < 3; ++k)
+  const double ichi = 1.0 / chi, ih = 0.5 / chi, iq = 0.25 / (chi * chi);
+
+  // ---- cotangents fixed by the output cotangents: X_ij, Ricci, Hessians
+  double X6b[6], DDab[6], DDchib[6], trDDb = 0.0, dc2b = 0.0, cdab = 0.0;
+  {
+    double rAt[6], trXb = 0.0;
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+      rAt[s] = src.cot(F_AT + s);
+      trXb -= rAt[s] * chi * gt[s] * third;
+    }
+#pragma unroll
+    for (int s = 0; s < 6; ++s) X6b[s] = rAt[s] * chi + trXb * wsym(s) * gi[s];
+  }
+  const double Cg = -src.cot(F_K) * chi;  // cotangent of the lapse Laplacian, times chi
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    DDab[s] = -X6b[s] + Cg * wsym(s) * gi[s];
+    const double r = X6b[s] * alpha;  // Ricci cotangent
+    trDDb += r * ih * gt[s];
+    dc2b -= r * iq * 3.0 * gt[s];
+    cdab -= DDab[s] * (0.5 / chi) * gt[s];
+  }
+#pragma unroll
+  for (int s = 0; s < 6; ++s) DDchib[s] = X6b[s] * alpha * ih + trDDb * wsym(s) * gi[s];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    out.d2(F_CHI, q, DDchib[q]);
+    out.d2(F_ALP, q, DDab[q]);
+  }
+#pragma unroll
+  for (int s = 0; s < 6; ++s)
+#pragma unroll
+    for (int q = 0; q < 6; ++q) out.d2(F_GT + s, q, -0.5 * X6b[s] * alpha * wsym(q) * gi[q]);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double dGb[3] = {0.0, 0.0, 0.0};
+#pragma unroll
     for (int s = 0; s < 6; ++s) {
       const int i = SI(s), j = SJ(s);
-      T.Gl[k][s] = 0.5 * ((in.dgt[S(k, j)][i] + in.dgt[S(k, i)][j]) - in.dgt[s][k]);
+      const double r = X6b[s] * alpha;
+      dGb[j] += 0.5 * r * gt[S(k, i)];
+      dGb[i] += 0.5 * r * gt[S(k, j)];
     }
-  for (int k = 0; k < 3; ++k)
-    for (int s = 0; s < 6; ++s) T.Gu[k][s] = gi[S(k, 0)] * T.Gl[0][s] + gi[S(k, 1)] * T.Gl[1][s] + gi[S(k, 2)] * T.Gl[2][s];
-  for (int k = 0; k < 3; ++k) T.Gd[k] = contract_sym(gi, T.Gu[k]);
-  // Ricci
-  for (int s = 0; s < 6; ++s) {
-    const int i = SI(s), j = SJ(s);
-    double rr = -0.5 * contract_sym(gi, in.d2gt[s]);
-    for (int k = 0; k < 3; ++k) rr += 0.5 * (gt[S(k, i)] * in.dGam[k][j] + gt[S(k, j)] * in.dGam[k][i]);
-    for (int k = 0; k < 3; ++k) rr += 0.5 * T.Gd[k] * (T.Gl[i][S(j, k)] + T.Gl[j][S(i, k)]);
-    for (int l = 0; l < 3; ++l)
-      for (int m = 0; m < 3; ++m) {
-        const double g = gi[S(l, m)];
-        for (int k = 0; k < 3; ++k)
-          rr += g * ((T.Gu[k][S(l, i)] * T.Gl[j][S(k, m)] + T.Gu[k][S(l, j)] * T.Gl[i][S(k, m)]) +
-                     T.Gu[k][S(i, m)] * T.Gl[k][S(l, j)]);
-      }
-    T.Ric[s] = rr;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) out.d1(F_GAM + k, a, dGb[a]);
   }
-  for (int s = 0; s < 6; ++s)
-    T.DDchi[s] = in.d2chi[s] - (T.Gu[0][s] * in.dchi[0] + T.Gu[1][s] * in.dchi[1] + T.Gu[2][s] * in.dchi[2]);
-  T.trDD = contract_sym(gi, T.DDchi);
-  T.dc2 = 0.0;
-  for (int l = 0; l < 3; ++l)
-    for (int m = 0; m < 3; ++m) T.dc2 += gi[S(l, m)] * in.dchi[l] * in.dchi[m];
-  {
-    const double ih = 0.5 / chi, iq = 0.25 / (chi * chi);
-    for (int s = 0; s < 6; ++s)
-      T.Ric[s] += ih * (T.DDchi[s] + gt[s] * T.trDD) - iq * (in.dchi[SI(s)] * in.dchi[SJ(s)] + 3.0 * gt[s] * T.dc2);
-  }
-  // lapse
-  T.cda = 0.0;
-  for (int k = 0; k < 3; ++k)
-    for (int l = 0; l < 3; ++l) T.cda += gi[S(k, l)] * in.dchi[k] * in.dalpha[l];
-  for (int s = 0; s < 6; ++s) {
-    const int i = SI(s), j = SJ(s);
-    T.DDa[s] = (in.d2alpha[s] - (T.Gu[0][s] * in.dalpha[0] + T.Gu[1][s] * in.dalpha[1] + T.Gu[2][s] * in.dalpha[2])) +
-               (0.5 / chi) * ((in.dchi[i] * in.dalpha[j] + in.dchi[j] * in.dalpha[i]) - gt[s] * T.cda);
-  }
-  T.D2a = chi * contract_sym(gi, T.DDa);
-  // traceless curvature
-  for (int k = 0; k < 3; ++k)
+  src.fence();
+  {  // connection-function and shift cotangents of the shift's second differences, d_a K, Gamma, beta
+    double rGam[3], Yb[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) rGam[i] = src.cot(F_GAM + i);
+#pragma unroll
+    for (int l = 0; l < 3; ++l) Yb[l] = (rGam[0] * gi[S(0, l)] + rGam[1] * gi[S(1, l)] + rGam[2] * gi[S(2, l)]) * third;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      double d2b[6];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) d2b[q] = rGam[k] * wsym(q) * gi[q];
+#pragma unroll
+      for (int l = 0; l < 3; ++l) d2b[S(l, k)] += Yb[l];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) out.d2(F_BET + k, q, d2b[q]);
+    }
+#pragma unroll
     for (int j = 0; j < 3; ++j)
-      T.Amix[k][j] = gi[S(k, 0)] * in.At[S(0, j)] + gi[S(k, 1)] * in.At[S(1, j)] + gi[S(k, 2)] * in.At[S(2, j)];
-  for (int s = 0; s < 6; ++s) {
-    const int i = SI(s), j = SJ(s);
-    T.Aup[s] = T.Amix[i][0] * gi[S(0, j)] + T.Amix[i][1] * gi[S(1, j)] + T.Amix[i][2] * gi[S(2, j)];
-  }
-  T.AA = contract_sym(in.At, T.Aup);
-  const double (*db)[3] = in.dbeta;
-  T.divb = db[0][0] + db[1][1] + db[2][2];
-  // outputs
-  r[F_CHI] = (2.0 / 3.0) * chi * (alpha * K - T.divb);
-  for (int s = 0; s < 6; ++s) {
-    const int i = SI(s), j = SJ(s);
-    double v = 0.0;
-    for (int k = 0; k < 3; ++k) v += gt[S(i, k)] * db[k][j] + gt[S(j, k)] * db[k][i];
-    r[F_GT + s] = v - (2.0 / 3.0) * gt[s] * T.divb - 2.0 * alpha * in.At[s];
-  }
-  r[F_K] = -T.D2a + alpha * (T.AA + K * K * (1.0 / 3.0)) + 4.0 * PI_D * alpha * (R.E + T.Str);
-  for (int s = 0; s < 6; ++s) T.X6[s] = -T.DDa[s] + alpha * (T.Ric[s] - 8.0 * PI_D * T.Sij[s]);
-  T.trX = contract_sym(gi, T.X6);
-  for (int s = 0; s < 6; ++s) {
-    const int i = SI(s), j = SJ(s);
-    double v = 0.0;
-    for (int k = 0; k < 3; ++k) v += in.At[S(i, k)] * db[k][j] + in.At[S(j, k)] * db[k][i];
-    v -= (2.0 / 3.0) * in.At[s] * T.divb;
-    v += chi * (T.X6[s] - gt[s] * T.trX * (1.0 / 3.0));
-    double AAij = 0.0;
-    for (int k = 0; k < 3; ++k) AAij += in.At[S(i, k)] * T.Amix[k][j];
-    r[F_AT + s] = v + alpha * (K * in.At[s] - 2.0 * AAij);
-  }
-  for (int i = 0; i < 3; ++i) {
-    double v = -(T.Gd[0] * db[i][0] + T.Gd[1] * db[i][1] + T.Gd[2] * db[i][2]);
-    v += (2.0 / 3.0) * T.Gd[i] * T.divb;
-    v += contract_sym(gi, in.d2beta[i]);
-    for (int l = 0; l < 3; ++l) {
-      const double Y = in.d2beta[0][S(l, 0)] + in.d2beta[1][S(l, 1)] + in.d2beta[2][S(l, 2)];
-      v += gi[S(i, l)] * Y * (1.0 / 3.0);
-    }
-    v -= 2.0 * (T.Aup[S(i, 0)] * in.dalpha[0] + T.Aup[S(i, 1)] * in.dalpha[1] + T.Aup[S(i, 2)] * in.dalpha[2]);
-    double inner = contract_sym(T.Gu[i], T.Aup);
-    inner -= (1.5 / chi) * (T.Aup[S(i, 0)] * in.dchi[0] + T.Aup[S(i, 1)] * in.dchi[1] + T.Aup[S(i, 2)] * in.dchi[2]);
-    inner -= (2.0 / 3.0) * (gi[S(i, 0)] * in.dK[0] + gi[S(i, 1)] * in.dK[1] + gi[S(i, 2)] * in.dK[2]);
-    v += 2.0 * alpha * inner;
-    v -= 16.0 * PI_D * alpha * (gi[S(i, 0)] * R.S[0] + gi[S(i, 1)] * R.S[1] + gi[S(i, 2)] * R.S[2]);
-    r[F_GAM + i] = v;
-  }
-  T.Kbg = P.lapse_bg ? -3.0 * P.H0 / (1.0 + 2.0 * P.H0 * t) : 0.0;
-  r[F_ALP] = -2.0 * alpha * (K - T.Kbg);
-  for (int i = 0; i < 3; ++i) r[F_BET + i] = P.evolve_shift ? 0.75 * in.Gam[i] - P.eta * in.beta[i] : 0.0;
-  T.im32 = 1.0 / (chi * sqrt(chi));
-  T.KS = 0.0;
-  for (int s = 0; s < 6; ++s) {
-    T.Kij[s] = (in.At[s] + gt[s] * K * (1.0 / 3.0)) / chi;
-    T.KS += wsym(s) * T.Kij[s] * T.Sjk[s];
-  }
-  T.Sda = R.Sup[0] * in.dalpha[0] + R.Sup[1] * in.dalpha[1] + R.Sup[2] * in.dalpha[2];
-  r[F_ET] = T.im32 * (alpha * T.KS - T.Sda);
-  T.sgt = 0.0;
-  for (int s = 0; s < 6; ++s) T.sgt += wsym(s) * T.Sjk[s] * gt[s];
-  for (int a = 0; a < 3; ++a) {
-    T.sg[a] = 0.0;
-    for (int s = 0; s < 6; ++s) T.sg[a] += wsym(s) * T.Sjk[s] * in.dgt[s][a];
-  }
-  for (int i = 0; i < 3; ++i) {
-    double q = -R.E * in.dalpha[i] + (R.S[0] * db[0][i] + R.S[1] * db[1][i] + R.S[2] * db[2][i]);
-    q += 0.5 * alpha * (T.sg[i] * T.ichi - T.sgt * in.dchi[i] * (T.ichi * T.ichi));
-    r[F_ST + i] = T.im32 * q;
-  }
-}
-
-// Reverse sweep: accumulates into b (which the caller zeroes) the cotangents of the inputs.
-__host__ __device__ inline void pt_reverse(const DevParams& P, const PtIn& in, const PtTape& T, const double rb[NF],
-                                           PtIn& b) {
-  const double* gt = in.gt;
-  const double chi = in.chi, K = in.K, alpha = in.alpha;
-  const double* gi = T.I.gi;
-  const RecTape& R = T.R;
-  const double (*db)[3] = in.dbeta;
-  double gib[6] = {0, 0, 0, 0, 0, 0};
-  RecBar B = {0.0, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, 0.0, 0.0, 0.0};
-  double Sjkb[6] = {0, 0, 0, 0, 0, 0}, Sijb[6] = {0, 0, 0, 0, 0, 0}, Strb = 0.0;
-  double Glb[3][6] = {}, Gub[3][6] = {}, Gdb[3] = {0, 0, 0};
-  double DDchib[6] = {}, trDDb = 0.0, dc2b = 0.0, Ricb[6] = {};
-  double cdab = 0.0, DDab[6] = {}, D2ab = 0.0;
-  double Amixb[3][3] = {}, Aupb[6] = {}, AAb = 0.0, divbb = 0.0;
-  double X6b[6] = {}, trXb = 0.0;
-  double Kijb[6] = {}, KSb = 0.0, im32b = 0.0, sgb[3] = {0, 0, 0}, sgtb = 0.0, Sdab = 0.0;
-  double ichib = 0.0;
-
-  // ---- fluid momentum
-  for (int i = 0; i < 3; ++i) {
-    const double q = -R.E * in.dalpha[i] + (R.S[0] * db[0][i] + R.S[1] * db[1][i] + R.S[2] * db[2][i]) +
-                     0.5 * alpha * (T.sg[i] * T.ichi - T.sgt * in.dchi[i] * (T.ichi * T.ichi));
-    im32b += rb[F_ST + i] * q;
-    const double qb = rb[F_ST + i] * T.im32;
-    B.E -= qb * in.dalpha[i];
-    b.dalpha[i] -= qb * R.E;
-    for (int k = 0; k < 3; ++k) {
-      B.S[k] += qb * db[k][i];
-      b.dbeta[k][i] += qb * R.S[k];
-    }
-    const double Tt = T.sg[i] * T.ichi - T.sgt * in.dchi[i] * (T.ichi * T.ichi);
-    b.alpha += qb * 0.5 * Tt;
-    const double Ttb = qb * 0.5 * alpha;
-    sgb[i] += Ttb * T.ichi;
-    ichib += Ttb * T.sg[i];
-    sgtb -= Ttb * in.dchi[i] * T.ichi * T.ichi;
-    b.dchi[i] -= Ttb * T.sgt * T.ichi * T.ichi;
-    ichib -= Ttb * T.sgt * in.dchi[i] * 2.0 * T.ichi;
-  }
-  // ---- fluid energy
-  im32b += rb[F_ET] * (alpha * T.KS - T.Sda);
-  b.alpha += rb[F_ET] * T.im32 * T.KS;
-  KSb += rb[F_ET] * T.im32 * alpha;
-  Sdab -= rb[F_ET] * T.im32;
-  for (int j = 0; j < 3; ++j) {
-    B.Sup[j] += Sdab * in.dalpha[j];
-    b.dalpha[j] += Sdab * R.Sup[j];
-  }
-  for (int s = 0; s < 6; ++s) {
-    Sjkb[s] += sgtb * wsym(s) * gt[s];
-    b.gt[s] += sgtb * wsym(s) * T.Sjk[s];
-    for (int a = 0; a < 3; ++a) {
-      Sjkb[s] += sgb[a] * wsym(s) * in.dgt[s][a];
-      b.dgt[s][a] += sgb[a] * wsym(s) * T.Sjk[s];
-    }
-    Kijb[s] += KSb * wsym(s) * T.Sjk[s];
-    Sjkb[s] += KSb * wsym(s) * T.Kij[s];
-    b.At[s] += Kijb[s] / chi;
-    b.gt[s] += Kijb[s] * K / (3.0 * chi);
-    b.K += Kijb[s] * gt[s] / (3.0 * chi);
-    b.chi -= Kijb[s] * T.Kij[s] / chi;
-  }
-  {  // im32 = 1 / (chi sqrt(chi))
-    const double vb = -im32b * T.im32 * T.im32;
-    const double sq = sqrt(chi);
-    b.chi += vb * sq + vb * chi * 0.5 / sq;
-  }
-  // ---- gauge
-  if (P.evolve_shift)
+      out.d1(F_K, j, -(2.0 / 3.0) * 2.0 * alpha * (rGam[0] * gi[S(0, j)] + rGam[1] * gi[S(1, j)] + rGam[2] * gi[S(2, j)]));
+#pragma unroll
     for (int i = 0; i < 3; ++i) {
-      b.Gam[i] += 0.75 * rb[F_BET + i];
-      b.beta[i] -= P.eta * rb[F_BET + i];
+      const double rb = src.cot(F_BET + i);
+      out.val(F_GAM + i, P.evolve_shift ? 0.75 * rb : 0.0);
+      out.val(F_BET + i, P.evolve_shift ? -P.eta * rb : 0.0);
     }
-  b.alpha -= 2.0 * (K - T.Kbg) * rb[F_ALP];
-  b.K -= 2.0 * alpha * rb[F_ALP];
-  // ---- connection functions
-  for (int i = 0; i < 3; ++i) {
-    const double r = rb[F_GAM + i];
+  }
+  src.fence();
+  // fluid quantities the connection step needs: S^jk and the momentum-source cotangent
+  double Sjk[6], Ttb[3];
+  {
+    const double St[3] = {src.val(F_ST), src.val(F_ST + 1), src.val(F_ST + 2)};
+    RecTape R;
+    rec_forward(P.w, chi, gi, src.val(F_ET), St, R);
+#pragma unroll
+    for (int s = 0; s < 6; ++s) Sjk[s] = R.Sup[SI(s)] * R.Sup[SJ(s)] * R.invX + R.P * chi * gi[s];
+    const double im32 = 1.0 / (chi * sqrt(chi));
+#pragma unroll
+    for (int i = 0; i < 3; ++i) Ttb[i] = src.cot(F_ST + i) * im32 * 0.5 * alpha;
+  }
+  src.fence();
+
+  // ---- first differences of chi, alpha, beta; the conformal-factor terms of the Hessians
+  double dchi[3], dal[3], db[3][3], DDchi[6], DDa[6];  // DDchi, DDa: second differences for now
+  src.d12(F_CHI, dchi, DDchi);
+  src.d12(F_ALP, dal, DDa);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) src.d1(F_BET + c, db[c]);
+  const double divb = db[0][0] + db[1][1] + db[2][2];
+  double bchi = 0.0, balpha = 0.0, bgt[6], gib[6], Xacc[6];  // Xacc: X_ij, summed as its terms appear
+  double bdchi[3] = {0.0, 0.0, 0.0}, bdal[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < 6; ++s) bgt[s] = gib[s] = Xacc[s] = 0.0;
+  {
+    double cda = 0.0, dc2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int l = 0; l < 3; ++l) {
+        cda += gi[S(k, l)] * dchi[k] * dal[l];
+        dc2 += gi[S(k, l)] * dchi[k] * dchi[l];
+      }
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+      const int i = SI(s), j = SJ(s);
+      const double Wv = (dchi[i] * dal[j] + dchi[j] * dal[i]) - gt[s] * cda;
+      DDa[s] += (0.5 / chi) * Wv;
+      const double Wb = DDab[s] * (0.5 / chi);
+      bchi -= DDab[s] * Wv * 0.5 / (chi * chi);
+      bdchi[i] += Wb * dal[j];
+      bdal[j] += Wb * dchi[i];
+      bdchi[j] += Wb * dal[i];
+      bdal[i] += Wb * dchi[j];
+      bgt[s] -= Wb * cda;
+      const double r = X6b[s] * alpha;
+      const double dq = -iq * (dchi[i] * dchi[j] + 3.0 * gt[s] * dc2);
+      Xacc[s] += alpha * dq;
+      balpha += X6b[s] * dq;
+      bdchi[i] -= r * iq * dchi[j];
+      bdchi[j] -= r * iq * dchi[i];
+      bgt[s] -= r * iq * 3.0 * dc2;
+      bchi += r * (dchi[i] * dchi[j] + 3.0 * gt[s] * dc2) * 0.5 / (chi * chi * chi);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int l = 0; l < 3; ++l) {
+        gib[S(k, l)] += cdab * dchi[k] * dal[l] + dc2b * dchi[k] * dchi[l];
+        bdchi[k] += cdab * gi[S(k, l)] * dal[l];
+        bdal[l] += cdab * gi[S(k, l)] * dchi[k];
+        bdchi[l] += dc2b * gi[S(k, l)] * dchi[k];
+        bdchi[k] += dc2b * gi[S(k, l)] * dchi[l];
+      }
+  }
+  src.fence();
+
+  // ---- connection and its reverse
+  double Gl[3][6], sg[3], SjkbD[6];  // SjkbD: the d gamma part of the S^jk cotangent
+  {
+    double dgt[6][3];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) src.d1(F_GT + s, dgt[s]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int s = 0; s < 6; ++s) {
+        const int i = SI(s), j = SJ(s);
+        Gl[k][s] = 0.5 * ((dgt[S(k, j)][i] + dgt[S(k, i)][j]) - dgt[s][k]);
+      }
+#pragma unroll
+    for (int s = 0; s < 6; ++s) SjkbD[s] = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      sg[a] = 0.0;
+#pragma unroll
+      for (int s = 0; s < 6; ++s) {
+        sg[a] += wsym(s) * Sjk[s] * dgt[s][a];
+        SjkbD[s] += Ttb[a] * ichi * wsym(s) * dgt[s][a];
+      }
+    }
+  }
+  double Gu[3][6], Gd[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+#pragma unroll
+    for (int s = 0; s < 6; ++s) Gu[k][s] = gi[S(k, 0)] * Gl[0][s] + gi[S(k, 1)] * Gl[1][s] + gi[S(k, 2)] * Gl[2][s];
+    Gd[k] = contract_sym(gi, Gu[k]);
+  }
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    DDchi[s] -= Gu[0][s] * dchi[0] + Gu[1][s] * dchi[1] + Gu[2][s] * dchi[2];
+    DDa[s] -= Gu[0][s] * dal[0] + Gu[1][s] * dal[1] + Gu[2][s] * dal[2];
+  }
+  {
+    const double trDD = contract_sym(gi, DDchi);
+    bchi += -src.cot(F_K) * contract_sym(gi, DDa);
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+      const double r = X6b[s] * alpha;
+      const double dr = ih * (DDchi[s] + gt[s] * trDD);
+      Xacc[s] += alpha * dr - DDa[s];
+      balpha += X6b[s] * dr;
+      bgt[s] += r * ih * trDD;
+      bchi -= r * (DDchi[s] + gt[s] * trDD) * 0.5 / (chi * chi);
+      gib[s] += trDDb * wsym(s) * DDchi[s] + Cg * wsym(s) * DDa[s];
+    }
+  }
+  double Gub[3][6], Glb[3][6], Gdb[3], AupbG[6];  // AupbG: the connection part of the A^ij cotangent
+  {
+    double Aup[6], innb[3];
+    {
+      double At[6], Amix[3][3];
+#pragma unroll
+      for (int s = 0; s < 6; ++s) At[s] = src.val(F_AT + s);
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+          Amix[k][j] = gi[S(k, 0)] * At[S(0, j)] + gi[S(k, 1)] * At[S(1, j)] + gi[S(k, 2)] * At[S(2, j)];
+#pragma unroll
+      for (int s = 0; s < 6; ++s) {
+        const int i = SI(s), j = SJ(s);
+        Aup[s] = Amix[i][0] * gi[S(0, j)] + Amix[i][1] * gi[S(1, j)] + Amix[i][2] * gi[S(2, j)];
+      }
+    }
+#pragma unroll
     for (int k = 0; k < 3; ++k) {
-      Gdb[k] -= r * db[i][k];
-      b.dbeta[i][k] -= r * T.Gd[k];
+      const double rG = src.cot(F_GAM + k);
+      innb[k] = 2.0 * rG * alpha;
+      Gdb[k] = (2.0 / 3.0) * rG * divb - (src.cot(F_GAM) * db[0][k] + src.cot(F_GAM + 1) * db[1][k] +
+                                           src.cot(F_GAM + 2) * db[2][k]);
+      balpha += 2.0 * rG * contract_sym(Gu[k], Aup);
     }
-    Gdb[i] += r * (2.0 / 3.0) * T.divb;
-    divbb += r * (2.0 / 3.0) * T.Gd[i];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) AupbG[s] = innb[0] * wsym(s) * Gu[0][s] + innb[1] * wsym(s) * Gu[1][s] +
+                                           innb[2] * wsym(s) * Gu[2][s];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int s = 0; s < 6; ++s) {
+        Gub[k][s] = innb[k] * wsym(s) * Aup[s] - DDab[s] * dal[k] - DDchib[s] * dchi[k];
+        Glb[k][s] = 0.0;
+        bdal[k] -= DDab[s] * Gu[k][s];
+        bdchi[k] -= DDchib[s] * Gu[k][s];
+      }
+  }
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    src.fence();
+    const int i = SI(s), j = SJ(s);
+    const double r = X6b[s] * alpha;
+    double dr = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double gsum = Gl[i][S(j, k)] + Gl[j][S(i, k)];
+      dr += 0.5 * Gd[k] * gsum;
+      Gdb[k] += 0.5 * r * gsum;
+      Glb[i][S(j, k)] += 0.5 * r * Gd[k];
+      Glb[j][S(i, k)] += 0.5 * r * Gd[k];
+    }
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        src.fence();
+        const double g = gi[S(l, m)];
+        double term = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          term += (Gu[k][S(l, i)] * Gl[j][S(k, m)] + Gu[k][S(l, j)] * Gl[i][S(k, m)]) + Gu[k][S(i, m)] * Gl[k][S(l, j)];
+          Gub[k][S(l, i)] += r * g * Gl[j][S(k, m)];
+          Glb[j][S(k, m)] += r * g * Gu[k][S(l, i)];
+          Gub[k][S(l, j)] += r * g * Gl[i][S(k, m)];
+          Glb[i][S(k, m)] += r * g * Gu[k][S(l, j)];
+          Gub[k][S(i, m)] += r * g * Gl[k][S(l, j)];
+          Glb[k][S(l, j)] += r * g * Gu[k][S(i, m)];
+        }
+        dr += g * term;
+        gib[S(l, m)] += r * term;
+      }
+    Xacc[s] += alpha * dr;
+    balpha += X6b[s] * dr;
+  }
+  src.fence();
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
     for (int s = 0; s < 6; ++s) {
-      gib[s] += r * wsym(s) * in.d2beta[i][s];
-      b.d2beta[i][s] += r * wsym(s) * gi[s];
+      gib[s] += Gdb[k] * wsym(s) * Gu[k][s];
+      Gub[k][s] += Gdb[k] * wsym(s) * gi[s];
     }
-    for (int l = 0; l < 3; ++l) {
-      const double Y = in.d2beta[0][S(l, 0)] + in.d2beta[1][S(l, 1)] + in.d2beta[2][S(l, 2)];
-      gib[S(i, l)] += r * Y * (1.0 / 3.0);
-      for (int k = 0; k < 3; ++k) b.d2beta[k][S(l, k)] += r * gi[S(i, l)] * (1.0 / 3.0);
-    }
-    for (int j = 0; j < 3; ++j) {
-      Aupb[S(i, j)] -= 2.0 * r * in.dalpha[j];
-      b.dalpha[j] -= 2.0 * r * T.Aup[S(i, j)];
-    }
-    const double Z = T.Aup[S(i, 0)] * in.dchi[0] + T.Aup[S(i, 1)] * in.dchi[1] + T.Aup[S(i, 2)] * in.dchi[2];
-    const double W = gi[S(i, 0)] * in.dK[0] + gi[S(i, 1)] * in.dK[1] + gi[S(i, 2)] * in.dK[2];
-    const double inner = contract_sym(T.Gu[i], T.Aup) - (1.5 / chi) * Z - (2.0 / 3.0) * W;
-    b.alpha += 2.0 * r * inner;
-    const double innb = 2.0 * r * alpha;
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int s = 0; s < 6; ++s)
+#pragma unroll
+      for (int l = 0; l < 3; ++l) {
+        gib[S(k, l)] += Gub[k][s] * Gl[l][s];
+        Glb[l][s] += Gub[k][s] * gi[S(k, l)];
+      }
+  {
+    double bdgt[6][3];
+#pragma unroll
+    for (int s = 0; s < 6; ++s)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) bdgt[s][a] = Ttb[a] * ichi * wsym(s) * Sjk[s];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int s = 0; s < 6; ++s) {
+        const int i = SI(s), j = SJ(s);
+        bdgt[S(k, j)][i] += 0.5 * Glb[k][s];
+        bdgt[S(k, i)][j] += 0.5 * Glb[k][s];
+        bdgt[s][k] -= 0.5 * Glb[k][s];
+      }
+#pragma unroll
+    for (int s = 0; s < 6; ++s)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) out.d1(F_GT + s, a, bdgt[s][a]);
+  }
+  src.fence();
+
+  // ---- streamed: second differences of the metric, d_a Gamma^k, shift second differences, d_a K
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    double d2[6];
+    src.d2(F_GT + s, d2);
+    const double dr = -0.5 * contract_sym(gi, d2);
+    Xacc[s] += alpha * dr;
+    balpha += X6b[s] * dr;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) gib[q] -= 0.5 * X6b[s] * alpha * wsym(q) * d2[q];
+    src.pin(Xacc[s]);
+    src.pin(balpha);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) src.pin(gib[q]);
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double d[3];
+    src.d1(F_GAM + k, d);
+#pragma unroll
     for (int s = 0; s < 6; ++s) {
-      Gub[i][s] += innb * wsym(s) * T.Aup[s];
-      Aupb[s] += innb * wsym(s) * T.Gu[i][s];
+      const int i = SI(s), j = SJ(s);
+      const double dr = 0.5 * (gt[S(k, i)] * d[j] + gt[S(k, j)] * d[i]);
+      Xacc[s] += alpha * dr;
+      balpha += X6b[s] * dr;
+      bgt[S(k, i)] += 0.5 * X6b[s] * alpha * d[j];
+      bgt[S(k, j)] += 0.5 * X6b[s] * alpha * d[i];
     }
-    const double Zb = -innb * 1.5 / chi;
-    b.chi += innb * 1.5 * Z / (chi * chi);
+    src.pin(balpha);
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+      src.pin(Xacc[s]);
+      src.pin(bgt[s]);
+    }
+  }
+  {
+    double Y[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      double d2[6];
+      src.d2(F_BET + k, d2);
+      const double rG = src.cot(F_GAM + k);
+#pragma unroll
+      for (int q = 0; q < 6; ++q) gib[q] += rG * wsym(q) * d2[q];
+#pragma unroll
+      for (int l = 0; l < 3; ++l) Y[l] += d2[S(l, k)];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) src.pin(gib[q]);
+#pragma unroll
+      for (int l = 0; l < 3; ++l) src.pin(Y[l]);
+    }
+    double dK[3];
+    src.d1(F_K, dK);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double rG = src.cot(F_GAM + i);
+      const double W = gi[S(i, 0)] * dK[0] + gi[S(i, 1)] * dK[1] + gi[S(i, 2)] * dK[2];
+      balpha -= 2.0 * rG * (2.0 / 3.0) * W;
+#pragma unroll
+      for (int l = 0; l < 3; ++l) gib[S(i, l)] += rG * Y[l] * third - 2.0 * rG * alpha * (2.0 / 3.0) * dK[l];
+    }
+  }
+  src.fence();
+
+  // ---- terms of the point values, and the fluid
+  const double K = src.val(F_K);
+  double At[6], Amix[3][3], Aup[6];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) At[s] = src.val(F_AT + s);
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      Amix[k][j] = gi[S(k, 0)] * At[S(0, j)] + gi[S(k, 1)] * At[S(1, j)] + gi[S(k, 2)] * At[S(2, j)];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    const int i = SI(s), j = SJ(s);
+    Aup[s] = Amix[i][0] * gi[S(0, j)] + Amix[i][1] * gi[S(1, j)] + Amix[i][2] * gi[S(2, j)];
+  }
+  const double St[3] = {src.val(F_ST), src.val(F_ST + 1), src.val(F_ST + 2)};
+  const double Et = src.val(F_ET);
+  RecTape R;
+  rec_forward(P.w, chi, gi, Et, St, R);
+  const double im32 = 1.0 / (chi * sqrt(chi));
+  const double rK = src.cot(F_K), rEt = src.cot(F_ET), rchi = src.cot(F_CHI);
+  const double AAb = rK * alpha, KSb = rEt * im32 * alpha, Sdab = -rEt * im32;
+  double bK = 0.0, bAt[6], Aupb[6], Amixb[3][3], ichib = 0.0, im32b = 0.0;
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    bAt[s] = AAb * wsym(s) * Aup[s];
+    Aupb[s] = AAb * wsym(s) * At[s] + AupbG[s];
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) Amixb[k][j] = 0.0;
+  RecBar B = {0.0, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, 0.0, 0.0, 0.0};
+  double Kij[6], KS = 0.0, sgt = 0.0;
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    Kij[s] = (At[s] + gt[s] * K * third) / chi;
+    KS += wsym(s) * Kij[s] * Sjk[s];
+    sgt += wsym(s) * Sjk[s] * gt[s];
+  }
+  balpha += rEt * im32 * KS;
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    const double Kijb = KSb * wsym(s) * Sjk[s];
+    bAt[s] += Kijb / chi;
+    bgt[s] += Kijb * K / (3.0 * chi);
+    bK += Kijb * gt[s] / (3.0 * chi);
+    bchi -= Kijb * Kij[s] / chi;
+  }
+  {
+    const double Kbg = P.lapse_bg ? -3.0 * P.H0 / (1.0 + 2.0 * P.H0 * t) : 0.0;
+    const double ra = src.cot(F_ALP);
+    balpha -= 2.0 * (K - Kbg) * ra;
+    bK -= 2.0 * alpha * ra;
+  }
+  double divbb = -(2.0 / 3.0) * rchi * chi, bdb[3][3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) bdb[c][a] = 0.0;
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    const int i = SI(s), j = SJ(s);
+    const double r = src.cot(F_AT + s), rg = src.cot(F_GT + s);
+    double AAij = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) AAij += At[S(i, k)] * Amix[k][j];
+    balpha += r * (K * At[s] - 2.0 * AAij);
+    bK += r * alpha * At[s];
+    bAt[s] += r * alpha * K;
+    const double AAijb = -2.0 * r * alpha;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      bAt[S(i, k)] += AAijb * Amix[k][j];
+      Amixb[k][j] += AAijb * At[S(i, k)];
+      // Lie derivative along the shift
+      bAt[S(i, k)] += r * db[k][j];
+      bdb[k][j] += r * At[S(i, k)];
+      bAt[S(j, k)] += r * db[k][i];
+      bdb[k][i] += r * At[S(j, k)];
+      bgt[S(i, k)] += rg * db[k][j];
+      bdb[k][j] += rg * gt[S(i, k)];
+      bgt[S(j, k)] += rg * db[k][i];
+      bdb[k][i] += rg * gt[S(j, k)];
+    }
+    bAt[s] -= (2.0 / 3.0) * r * divb;
+    bgt[s] -= (2.0 / 3.0) * rg * divb;
+    divbb -= (2.0 / 3.0) * (r * At[s] + rg * gt[s]);
+    balpha -= 2.0 * rg * At[s];
+    bAt[s] -= 2.0 * rg * alpha;
+  }
+  {
+    const double Str = R.S2 * R.invX + 3.0 * R.P;
+    const double AA = contract_sym(At, Aup);
+    const double Strb = rK * 4.0 * PI_D * alpha;
+    balpha += rK * (AA + K * K * third + 4.0 * PI_D * (R.E + Str));
+    bK += rK * alpha * 2.0 * K * third;
+    B.E += rK * 4.0 * PI_D * alpha;
+    B.S2 += Strb * R.invX;
+    B.invX += Strb * R.S2;
+    B.P += 3.0 * Strb;
+  }
+  balpha += rchi * (2.0 / 3.0) * chi * K;
+  bK += rchi * (2.0 / 3.0) * chi * alpha;
+  bchi += rchi * (2.0 / 3.0) * (alpha * K - divb);
+  out.val(F_K, bK);
+  // connection functions: the terms without the connection
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const double r = src.cot(F_GAM + i);
+    double V = 0.0, Z = 0.0;
+#pragma unroll
     for (int j = 0; j < 3; ++j) {
-      Aupb[S(i, j)] += Zb * in.dchi[j];
-      b.dchi[j] += Zb * T.Aup[S(i, j)];
-      gib[S(i, j)] -= innb * (2.0 / 3.0) * in.dK[j];
-      b.dK[j] -= innb * (2.0 / 3.0) * gi[S(i, j)];
+      V += gi[S(i, j)] * R.S[j];
+      Z += Aup[S(i, j)] * dchi[j];
     }
-    const double V = gi[S(i, 0)] * R.S[0] + gi[S(i, 1)] * R.S[1] + gi[S(i, 2)] * R.S[2];
-    b.alpha -= 16.0 * PI_D * r * V;
+    balpha -= 16.0 * PI_D * r * V;
     const double Vb = -16.0 * PI_D * r * alpha;
+    balpha -= 2.0 * r * (1.5 / chi) * Z;
+    const double innb = 2.0 * r * alpha, Zb = -innb * 1.5 / chi;
+    bchi += innb * 1.5 * Z / (chi * chi);
+#pragma unroll
     for (int j = 0; j < 3; ++j) {
       gib[S(i, j)] += Vb * R.S[j];
       B.S[j] += Vb * gi[S(i, j)];
+      Aupb[S(i, j)] += Zb * dchi[j] - 2.0 * r * dal[j];
+      bdchi[j] += Zb * Aup[S(i, j)];
+      bdal[j] -= 2.0 * r * Aup[S(i, j)];
+      bdb[i][j] -= r * Gd[j];
     }
+    divbb += r * (2.0 / 3.0) * Gd[i];
   }
-  // ---- traceless curvature
+  bdb[0][0] += divbb;
+  bdb[1][1] += divbb;
+  bdb[2][2] += divbb;
+  // matter: S_ij in the curvature source, the fluid sources
+#pragma unroll
   for (int s = 0; s < 6; ++s) {
     const int i = SI(s), j = SJ(s);
-    const double r = rb[F_AT + s];
+    const double Sij = R.S[i] * R.S[j] * R.invX + R.P * gt[s] * ichi;
+    Xacc[s] -= 8.0 * PI_D * alpha * Sij;
+    balpha -= 8.0 * PI_D * X6b[s] * Sij;
+    const double Sijb = -8.0 * PI_D * X6b[s] * alpha;
+    B.S[i] += Sijb * R.S[j] * R.invX;
+    B.S[j] += Sijb * R.S[i] * R.invX;
+    B.invX += Sijb * R.S[i] * R.S[j];
+    B.P += Sijb * gt[s] * ichi;
+    bgt[s] += Sijb * R.P * ichi;
+    ichib += Sijb * R.P * gt[s];
+  }
+  double sgtb = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const double qb = src.cot(F_ST + i) * im32;
+    sgtb -= Ttb[i] * dchi[i] * ichi * ichi;
+    B.E -= qb * dal[i];
+    bdal[i] -= qb * R.E;
+#pragma unroll
     for (int k = 0; k < 3; ++k) {
-      b.At[S(i, k)] += r * db[k][j];
-      b.dbeta[k][j] += r * in.At[S(i, k)];
-      b.At[S(j, k)] += r * db[k][i];
-      b.dbeta[k][i] += r * in.At[S(j, k)];
+      B.S[k] += qb * db[k][i];
+      bdb[k][i] += qb * R.S[k];
     }
-    b.At[s] -= (2.0 / 3.0) * r * T.divb;
-    divbb -= (2.0 / 3.0) * r * in.At[s];
-    b.chi += r * (T.X6[s] - gt[s] * T.trX * (1.0 / 3.0));
-    X6b[s] += r * chi;
-    b.gt[s] -= r * chi * T.trX * (1.0 / 3.0);
-    trXb -= r * chi * gt[s] * (1.0 / 3.0);
-    double AAij = 0.0;
-    for (int k = 0; k < 3; ++k) AAij += in.At[S(i, k)] * T.Amix[k][j];
-    b.alpha += r * (K * in.At[s] - 2.0 * AAij);
-    b.K += r * alpha * in.At[s];
-    b.At[s] += r * alpha * K;
-    const double AAb = -2.0 * r * alpha;
-    for (int k = 0; k < 3; ++k) {
-      b.At[S(i, k)] += AAb * T.Amix[k][j];
-      Amixb[k][j] += AAb * in.At[S(i, k)];
-    }
+    bdchi[i] -= Ttb[i] * sgt * ichi * ichi;
+    ichib -= Ttb[i] * sgt * dchi[i] * 2.0 * ichi;
+    const double Tt = sg[i] * ichi - sgt * dchi[i] * (ichi * ichi);
+    const double q = -R.E * dal[i] + (R.S[0] * db[0][i] + R.S[1] * db[1][i] + R.S[2] * db[2][i]) + 0.5 * alpha * Tt;
+    im32b += src.cot(F_ST + i) * q;
+    balpha += qb * 0.5 * Tt;
+    ichib += Ttb[i] * sg[i];
   }
-  for (int s = 0; s < 6; ++s) {
-    gib[s] += trXb * wsym(s) * T.X6[s];
-    X6b[s] += trXb * wsym(s) * gi[s];
-  }
-  for (int s = 0; s < 6; ++s) {
-    DDab[s] -= X6b[s];
-    b.alpha += X6b[s] * (T.Ric[s] - 8.0 * PI_D * T.Sij[s]);
-    Ricb[s] += X6b[s] * alpha;
-    Sijb[s] -= 8.0 * PI_D * X6b[s] * alpha;
-  }
-  // ---- trace K
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) out.d1(F_BET + c, a, bdb[c][a]);
   {
-    const double r = rb[F_K];
-    D2ab -= r;
-    b.alpha += r * (T.AA + K * K * (1.0 / 3.0) + 4.0 * PI_D * (R.E + T.Str));
-    AAb += r * alpha;
-    b.K += r * alpha * 2.0 * K * (1.0 / 3.0);
-    B.E += r * 4.0 * PI_D * alpha;
-    Strb += r * 4.0 * PI_D * alpha;
-  }
-  // ---- conformal metric
-  for (int s = 0; s < 6; ++s) {
-    const int i = SI(s), j = SJ(s);
-    const double r = rb[F_GT + s];
-    for (int k = 0; k < 3; ++k) {
-      b.gt[S(i, k)] += r * db[k][j];
-      b.dbeta[k][j] += r * gt[S(i, k)];
-      b.gt[S(j, k)] += r * db[k][i];
-      b.dbeta[k][i] += r * gt[S(j, k)];
+    const double Sda = R.Sup[0] * dal[0] + R.Sup[1] * dal[1] + R.Sup[2] * dal[2];
+    im32b += rEt * (alpha * KS - Sda);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      B.Sup[j] += Sdab * dal[j];
+      bdal[j] += Sdab * R.Sup[j];
     }
-    b.gt[s] -= (2.0 / 3.0) * r * T.divb;
-    divbb -= (2.0 / 3.0) * r * gt[s];
-    b.alpha -= 2.0 * r * in.At[s];
-    b.At[s] -= 2.0 * r * alpha;
   }
-  // ---- conformal factor
-  {
-    const double r = rb[F_CHI];
-    b.chi += r * (2.0 / 3.0) * (alpha * K - T.divb);
-    b.alpha += r * (2.0 / 3.0) * chi * K;
-    b.K += r * (2.0 / 3.0) * chi * alpha;
-    divbb -= r * (2.0 / 3.0) * chi;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    out.d1(F_CHI, a, bdchi[a]);
+    out.d1(F_ALP, a, bdal[a]);
   }
-  b.dbeta[0][0] += divbb;
-  b.dbeta[1][1] += divbb;
-  b.dbeta[2][2] += divbb;
-  // ---- At contractions
-  for (int s = 0; s < 6; ++s) {
-    b.At[s] += AAb * wsym(s) * T.Aup[s];
-    Aupb[s] += AAb * wsym(s) * in.At[s];
-  }
+#pragma unroll
   for (int s = 0; s < 6; ++s) {
     const int i = SI(s), j = SJ(s);
+    bgt[s] += sgtb * wsym(s) * Sjk[s];
+    const double Sjkb = sgtb * wsym(s) * gt[s] + KSb * wsym(s) * Kij[s] + SjkbD[s];
+    B.Sup[i] += Sjkb * R.Sup[j] * R.invX;
+    B.Sup[j] += Sjkb * R.Sup[i] * R.invX;
+    B.invX += Sjkb * R.Sup[i] * R.Sup[j];
+    B.P += Sjkb * chi * gi[s];
+    bchi += Sjkb * R.P * gi[s];
+    gib[s] += Sjkb * R.P * chi;
+  }
+  {  // im32 = 1 / (chi sqrt(chi))
+    const double vb = -im32b * im32 * im32;
+    const double sq = sqrt(chi);
+    bchi += vb * sq + vb * chi * 0.5 / sq;
+  }
+  bchi -= ichib * ichi * ichi;
+  {
+    double bEt = 0.0, bSt[3] = {0.0, 0.0, 0.0};
+    rec_reverse(P.w, chi, gi, Et, St, R, B, bchi, gib, bEt, bSt);
+    out.val(F_ET, bEt);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out.val(F_ST + c, bSt[c]);
+  }
+  // A^ij and A^i_j back to A_ij and the inverse metric
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    const int i = SI(s), j = SJ(s);
+#pragma unroll
     for (int l = 0; l < 3; ++l) {
       Amixb[i][l] += Aupb[s] * gi[S(l, j)];
-      gib[S(l, j)] += Aupb[s] * T.Amix[i][l];
+      gib[S(l, j)] += Aupb[s] * Amix[i][l];
     }
   }
+#pragma unroll
   for (int k = 0; k < 3; ++k)
+#pragma unroll
     for (int j = 0; j < 3; ++j)
+#pragma unroll
       for (int l = 0; l < 3; ++l) {
-        gib[S(k, l)] += Amixb[k][j] * in.At[S(l, j)];
-        b.At[S(l, j)] += Amixb[k][j] * gi[S(k, l)];
+        gib[S(k, l)] += Amixb[k][j] * At[S(l, j)];
+        bAt[S(l, j)] += Amixb[k][j] * gi[S(k, l)];
       }
-  // ---- lapse Hessian
+#pragma unroll
+  for (int s = 0; s < 6; ++s) out.val(F_AT + s, bAt[s]);
+  // the curvature source X_ij is complete
   {
-    const double c2 = contract_sym(gi, T.DDa);
-    b.chi += D2ab * c2;
-    const double Cg = D2ab * chi;
+    double trXb = 0.0;
+#pragma unroll
+    for (int s = 0; s < 6; ++s) trXb -= src.cot(F_AT + s) * chi * gt[s] * third;
+    const double trX = contract_sym(gi, Xacc);
+#pragma unroll
     for (int s = 0; s < 6; ++s) {
-      gib[s] += Cg * wsym(s) * T.DDa[s];
-      DDab[s] += Cg * wsym(s) * gi[s];
+      const double r = src.cot(F_AT + s);
+      bchi += r * (Xacc[s] - gt[s] * trX * third);
+      bgt[s] -= r * chi * trX * third;
+      gib[s] += trXb * wsym(s) * Xacc[s];
     }
   }
-  for (int s = 0; s < 6; ++s) {
-    const int i = SI(s), j = SJ(s);
-    b.d2alpha[s] += DDab[s];
-    for (int k = 0; k < 3; ++k) {
-      Gub[k][s] -= DDab[s] * in.dalpha[k];
-      b.dalpha[k] -= DDab[s] * T.Gu[k][s];
-    }
-    const double Wv = (in.dchi[i] * in.dalpha[j] + in.dchi[j] * in.dalpha[i]) - gt[s] * T.cda;
-    const double Wb = DDab[s] * (0.5 / chi);
-    b.chi -= DDab[s] * Wv * 0.5 / (chi * chi);
-    b.dchi[i] += Wb * in.dalpha[j];
-    b.dalpha[j] += Wb * in.dchi[i];
-    b.dchi[j] += Wb * in.dalpha[i];
-    b.dalpha[i] += Wb * in.dchi[j];
-    b.gt[s] -= Wb * T.cda;
-    cdab -= Wb * gt[s];
-  }
-  for (int k = 0; k < 3; ++k)
-    for (int l = 0; l < 3; ++l) {
-      gib[S(k, l)] += cdab * in.dchi[k] * in.dalpha[l];
-      b.dchi[k] += cdab * gi[S(k, l)] * in.dalpha[l];
-      b.dalpha[l] += cdab * gi[S(k, l)] * in.dchi[k];
-    }
-  // ---- Ricci: conformal-factor part
   {
-    const double ih = 0.5 / chi, iq = 0.25 / (chi * chi);
-    for (int s = 0; s < 6; ++s) {
-      const int i = SI(s), j = SJ(s);
-      const double r = Ricb[s];
-      DDchib[s] += r * ih;
-      b.gt[s] += r * ih * T.trDD;
-      trDDb += r * ih * gt[s];
-      b.chi -= r * (T.DDchi[s] + gt[s] * T.trDD) * 0.5 / (chi * chi);
-      b.dchi[i] -= r * iq * in.dchi[j];
-      b.dchi[j] -= r * iq * in.dchi[i];
-      b.gt[s] -= r * iq * 3.0 * T.dc2;
-      dc2b -= r * iq * 3.0 * gt[s];
-      b.chi += r * (in.dchi[i] * in.dchi[j] + 3.0 * gt[s] * T.dc2) * 0.5 / (chi * chi * chi);
-    }
+    InvTape I;
+    inv_forward(gt, I);
+    inv_reverse(gt, I, gib, bgt);
   }
-  for (int l = 0; l < 3; ++l)
-    for (int m = 0; m < 3; ++m) {
-      gib[S(l, m)] += dc2b * in.dchi[l] * in.dchi[m];
-      b.dchi[l] += dc2b * gi[S(l, m)] * in.dchi[m];
-      b.dchi[m] += dc2b * gi[S(l, m)] * in.dchi[l];
-    }
-  for (int s = 0; s < 6; ++s) {
-    gib[s] += trDDb * wsym(s) * T.DDchi[s];
-    DDchib[s] += trDDb * wsym(s) * gi[s];
-  }
-  for (int s = 0; s < 6; ++s) {
-    b.d2chi[s] += DDchib[s];
-    for (int k = 0; k < 3; ++k) {
-      Gub[k][s] -= DDchib[s] * in.dchi[k];
-      b.dchi[k] -= DDchib[s] * T.Gu[k][s];
-    }
-  }
-  // ---- Ricci: metric part
-  for (int s = 0; s < 6; ++s) {
-    const int i = SI(s), j = SJ(s);
-    const double r = Ricb[s];
-    for (int q = 0; q < 6; ++q) {
-      gib[q] -= 0.5 * r * wsym(q) * in.d2gt[s][q];
-      b.d2gt[s][q] -= 0.5 * r * wsym(q) * gi[q];
-    }
-    for (int k = 0; k < 3; ++k) {
-      b.gt[S(k, i)] += 0.5 * r * in.dGam[k][j];
-      b.dGam[k][j] += 0.5 * r * gt[S(k, i)];
-      b.gt[S(k, j)] += 0.5 * r * in.dGam[k][i];
-      b.dGam[k][i] += 0.5 * r * gt[S(k, j)];
-      Gdb[k] += 0.5 * r * (T.Gl[i][S(j, k)] + T.Gl[j][S(i, k)]);
-      Glb[i][S(j, k)] += 0.5 * r * T.Gd[k];
-      Glb[j][S(i, k)] += 0.5 * r * T.Gd[k];
-    }
-    for (int l = 0; l < 3; ++l)
-      for (int m = 0; m < 3; ++m) {
-        const double g = gi[S(l, m)];
-        for (int k = 0; k < 3; ++k) {
-          const double term = (T.Gu[k][S(l, i)] * T.Gl[j][S(k, m)] + T.Gu[k][S(l, j)] * T.Gl[i][S(k, m)]) +
-                              T.Gu[k][S(i, m)] * T.Gl[k][S(l, j)];
-          gib[S(l, m)] += r * term;
-          Gub[k][S(l, i)] += r * g * T.Gl[j][S(k, m)];
-          Glb[j][S(k, m)] += r * g * T.Gu[k][S(l, i)];
-          Gub[k][S(l, j)] += r * g * T.Gl[i][S(k, m)];
-          Glb[i][S(k, m)] += r * g * T.Gu[k][S(l, j)];
-          Gub[k][S(i, m)] += r * g * T.Gl[k][S(l, j)];
-          Glb[k][S(l, j)] += r * g * T.Gu[k][S(i, m)];
-        }
-      }
-  }
-  for (int k = 0; k < 3; ++k)
-    for (int s = 0; s < 6; ++s) {
-      gib[s] += Gdb[k] * wsym(s) * T.Gu[k][s];
-      Gub[k][s] += Gdb[k] * wsym(s) * gi[s];
-    }
-  for (int k = 0; k < 3; ++k)
-    for (int s = 0; s < 6; ++s)
-      for (int l = 0; l < 3; ++l) {
-        gib[S(k, l)] += Gub[k][s] * T.Gl[l][s];
-        Glb[l][s] += Gub[k][s] * gi[S(k, l)];
-      }
-  for (int k = 0; k < 3; ++k)
-    for (int s = 0; s < 6; ++s) {
-      const int i = SI(s), j = SJ(s);
-      b.dgt[S(k, j)][i] += 0.5 * Glb[k][s];
-      b.dgt[S(k, i)][j] += 0.5 * Glb[k][s];
-      b.dgt[s][k] -= 0.5 * Glb[k][s];
-    }
-  // ---- matter projections
-  B.S2 += Strb * R.invX;
-  B.invX += Strb * R.S2;
-  B.P += 3.0 * Strb;
-  for (int s = 0; s < 6; ++s) {
-    const int i = SI(s), j = SJ(s);
-    B.S[i] += Sijb[s] * R.S[j] * R.invX;
-    B.S[j] += Sijb[s] * R.S[i] * R.invX;
-    B.invX += Sijb[s] * R.S[i] * R.S[j];
-    B.P += Sijb[s] * gt[s] * T.ichi;
-    b.gt[s] += Sijb[s] * R.P * T.ichi;
-    ichib += Sijb[s] * R.P * gt[s];
-    B.Sup[i] += Sjkb[s] * R.Sup[j] * R.invX;
-    B.Sup[j] += Sjkb[s] * R.Sup[i] * R.invX;
-    B.invX += Sjkb[s] * R.Sup[i] * R.Sup[j];
-    B.P += Sjkb[s] * chi * gi[s];
-    b.chi += Sjkb[s] * R.P * gi[s];
-    gib[s] += Sjkb[s] * R.P * chi;
-  }
-  b.chi -= ichib * T.ichi * T.ichi;
-  rec_reverse(P.w, chi, gi, in.Et, in.St, R, B, b.chi, gib, b.Et, b.St);
-  inv_reverse(gt, T.I, gib, b.gt);
+  out.val(F_CHI, bchi);
+#pragma unroll
+  for (int s = 0; s < 6; ++s) out.val(F_GT + s, bgt[s]);
+  out.val(F_ALP, balpha);
 }
 
 }  // namespace cosmos
