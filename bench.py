@@ -6,14 +6,17 @@ One step = one classic RK4 step = 4 stages, each a pointwise flux pre-pass
 (k_fluid_flux) plus the stage kernel (k_bssn_stage_lds), inputs resident in HBM.
 Prints one JSON line with the roofline of a stage (algorithmic bytes per stage /
 average stage time, measured with HIP events on the launch stream around the
-timed steps) and the CPU oracle timed on a bounded sample of the same workload.
+timed steps), the CPU oracle timed on a bounded sample of the same workload, and
+the two other forms of the metric as sub-objects: "batched" (runs/s of the
+64-run scan) and "adjoint" (cost of the gradient relative to the forward run).
 
 Extra modes:
-  --batched      the 64-run threshold-scan workload (grid sizes drawn from
+  --headline-only  skip the batched and adjoint sub-objects
+  --batched      only the 64-run threshold-scan workload (grid sizes drawn from
                  {48, 64, 80, 96}^3, mu in [0.3, 0.8], sigma in [0.8, 1.6], box 12/H0,
                  300 RK4 steps per run): runs/s of the batched, hipGraph-replayed form
                  against the same runs advanced one after another by the plain solver
-  --adjoint      the differentiation workload: 96^3, box 12/H0, mu = 0.55,
+  --adjoint      only the differentiation workload: 96^3, box 12/H0, mu = 0.55,
                  sigma = 1.2, 200 RK4 steps, checkpoint every 20; gradient of the centre
                  lapse in (mu, sigma) by the discrete adjoint, its cost relative to the
                  plain forward run, and central finite differences (h = 1e-6)
@@ -62,6 +65,7 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-tune", action="store_true", help="use the default tile instead of the autotuned one")
     ap.add_argument("--batched", action="store_true")
+    ap.add_argument("--headline-only", action="store_true", help="no batched / adjoint sub-objects")
     ap.add_argument("--batched-steps", type=int, default=30, help="timed steps (runs/s is scaled to 300 steps)")
     ap.add_argument("--adjoint", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=200, help="RK4 steps of the differentiated run")
@@ -166,10 +170,10 @@ def batched_bench(a):
     st = b.status()
     if any(x["nonfinite"] for x in st):
         raise RuntimeError("non-finite values in the batched run")
-    # the same runs, one after another, on the plain solver (same kernel and brick)
+    # the same runs, one after another, on the plain solver (its default configuration)
     plain_ms = 0.0
     for spec in runs:
-        s = P.Solver(spec.n, spec.L, P.make_params(tile=(16, 4, 4), tile_order=1))
+        s = P.Solver(spec.n, spec.L, P.make_params())
         s.init(mu=spec.mu, sigma=spec.sigma)
         dt = 0.25 * spec.L / spec.n
         s.step(dt)
@@ -189,7 +193,7 @@ def batched_bench(a):
            "higher_is_better": True, "dtype": "f64", "data": "synthetic",
            "config": {"workload": "64 runs, n from {48,64,80,96} (numpy default_rng(2606)), mu U[0.3,0.8], "
                                   "sigma U[0.8,1.6], L = 12/H0, CFL 0.25, hipGraph-replayed RK4 steps"}}
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def adjoint_bench(a):
@@ -231,7 +235,7 @@ def adjoint_bench(a):
            "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"96^3 periodic, L = 12/H0, Gaussian zeta mu = 0.55 sigma = 1.2, {cfg.nsteps} RK4 "
                                   "steps, CFL 0.25, checkpoint every 20, J = centre lapse at the final time"}}
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def main():
@@ -247,10 +251,10 @@ def main():
         copy_probe()
         return
     if a.batched:
-        batched_bench(a)
+        print(json.dumps(batched_bench(a)), flush=True)
         return
     if a.adjoint:
-        adjoint_bench(a)
+        print(json.dumps(adjoint_bench(a)), flush=True)
         return
     import paper_2606_02053_amd as P
     from paper_2606_02053_amd import autotune
@@ -303,6 +307,9 @@ def main():
                       "kernel_config": config_name(kv, tile, order),
                       "parallelism": "single GPU"},
            "roofline": roof}
+    if not a.headline_only:
+        out["batched"] = batched_bench(a)
+        out["adjoint"] = adjoint_bench(a)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(a.cpu_steps)
     print(json.dumps(out), flush=True)

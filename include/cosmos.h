@@ -93,7 +93,9 @@ typedef struct {
  *   tile_order brick order: 0 = XCD slabs (each of the 8 XCDs walks one contiguous slab of bricks),
  *            1 = linear, 2 = XCD-blocked (LDS-staged variant: each XCD owns a slab of brick layers and
  *            its resident workgroups process one compact block of bricks at a time, so shared halos
- *            are read into that XCD's L2 once; the direct variant treats 2 as linear) */
+ *            are read into that XCD's L2 once; used where the brick grid splits evenly into such
+ *            blocks -- brick layers a multiple of 8, blocks dividing each XCD's slab -- and linear
+ *            otherwise; the direct variant treats 2 as linear) */
 typedef struct {
   double w, H0, eta, ko_eps;
   int32_t lapse_bg, evolve_shift, fluid_scheme, variant;

@@ -350,26 +350,30 @@ unsigned resident_groups(K kernel) {
 }
 
 // Block of bricks processed together by the W resident workgroups of one XCD in the
-// XCD-blocked order: gx gy gz = W, the smallest halo-to-interior ratio of the block
-// among the divisor triples that fit the XCD's slab of the brick grid.
+// XCD-blocked order: gx gy gz = W bricks that tile the XCD's slab of the brick grid
+// exactly (every XCD holds nbz / 8 brick layers and the blocks divide the slab), with
+// the smallest halo-to-interior ratio. False when there is no such block: an uneven
+// split would leave some XCDs idle or with half-filled blocks while others work, and
+// the launch then takes the linear order.
 bool blocked_order(Tile& T, unsigned W) {
-  T.zr = (T.nbz + 7) / 8;
+  if (T.nbz % 8) return false;
+  T.zr = T.nbz / 8;
   double best = 1e300;
   for (int gx = 1; gx <= (int)W; ++gx) {
-    if (W % gx || gx > T.nbx) continue;
+    if (W % gx || T.nbx % gx) continue;
     for (int gy = 1; gy <= (int)W / gx; ++gy) {
-      if ((W / gx) % gy || gy > T.nby) continue;
+      if ((W / gx) % gy || T.nby % gy) continue;
       const int gz = (int)W / (gx * gy);
-      if (gz > T.zr) continue;
+      if (T.zr % gz) continue;
       const double ex = gx * T.bx + 6.0, ey = gy * T.by + 6.0, ez = gz * T.bz + 6.0;
       const double ratio = ex * ey * ez / (double(W) * kBlock);
       if (ratio < best) best = ratio, T.gx = gx, T.gy = gy, T.gz = gz;
     }
   }
   if (!(best < 1e300)) return false;
-  T.ngx = (T.nbx + T.gx - 1) / T.gx;
-  T.ngy = (T.nby + T.gy - 1) / T.gy;
-  T.ngroups = T.ngx * T.ngy * ((T.zr + T.gz - 1) / T.gz);
+  T.ngx = T.nbx / T.gx;
+  T.ngy = T.nby / T.gy;
+  T.ngroups = T.ngx * T.ngy * (T.zr / T.gz);
   return true;
 }
 
@@ -381,7 +385,7 @@ void launch_persistent(K kernel, const Tile& T0, hipStream_t s, const double* U,
   const unsigned G = resident_groups(kernel);
   unsigned grid = std::min(tile_blocks(T), G);
   if (T.order == 2) {
-    // needs every XCD busy with whole blocks; small grids fall back to the linear order
+    // needs every XCD busy with whole blocks; other grids fall back to the linear order
     if (T.nbricks >= (int)G && blocked_order(T, G / 8)) grid = G;
     else T.order = 1;
   }

@@ -248,13 +248,15 @@ def test_tile_invariance_bitwise(P, orc):
     assert err_fields(first_rhs[0].cpu().numpy(), first_rhs[1].cpu().numpy())[0] < 1e-13
 
 
-def test_blocked_order_bitwise(P, orc):
-    """The XCD-blocked brick order of the persistent LDS kernel (blocks of bricks per XCD,
-    skipped slots at the slab edges, a partial brick layer in z) visits every brick once:
+@pytest.mark.parametrize("n,L", [((60, 32, 64), (7.5, 4.0, 8.0)), ((64, 44, 42), (8.0, 5.5, 5.25))])
+def test_blocked_order_bitwise(P, orc, n, L):
+    """The XCD-blocked brick order of the persistent LDS kernel visits every brick once:
     right-hand side and RK4 step equal the linear order bitwise, and sampled points match
-    the oracle."""
+    the oracle. 60 x 32 x 64 takes the blocked order (16 brick layers = 2 per XCD, blocks of
+    32 bricks dividing each slab, a partial brick column in x); 64 x 44 x 42 (11 brick
+    layers, a partial layer in z) cannot be split evenly over the XCDs and falls back to
+    the linear order."""
     from paper_2606_02053_amd import autotune
-    n, L = (64, 44, 42), (8.0, 5.5, 5.25)
     s, sol = mk(P, orc, n, L)
     u = fuzz_state(n, seed=21)
     sol.set_state(to_dev(u))
