@@ -221,7 +221,9 @@ __host__ __device__ inline void flux_reverse(double w, int a, const FluxIn& in, 
 // reverse; then the metric's second differences, d_a Gamma^k, the shift's second
 // differences and d_a K, one field at a time; last the terms of the point values
 // and the fluid. Forward values are formed where they are used (nothing is
-// taped), and every cotangent is handed to `out` as soon as it is final:
+// taped), and every cotangent is handed to `out` as soon as it is final (the
+// shift's point values last, after every difference request, so that a source
+// may fold other terms into them on the way):
 //   out.val(f, v)    cotangent of the point value of field f,
 //   out.d1(f, a, v)  of its first difference along a,
 //   out.d2(f, q, v)  of its second difference, symmetric pair q.
@@ -311,11 +313,7 @@ __host__ __device__ inline void pt_vjp(const DevParams& P, double t, const Src& 
     for (int j = 0; j < 3; ++j)
       out.d1(F_K, j, -(2.0 / 3.0) * 2.0 * alpha * (rGam[0] * gi[S(0, j)] + rGam[1] * gi[S(1, j)] + rGam[2] * gi[S(2, j)]));
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const double rb = src.cot(F_BET + i);
-      out.val(F_GAM + i, P.evolve_shift ? 0.75 * rb : 0.0);
-      out.val(F_BET + i, P.evolve_shift ? -P.eta * rb : 0.0);
-    }
+    for (int i = 0; i < 3; ++i) out.val(F_GAM + i, P.evolve_shift ? 0.75 * src.cot(F_BET + i) : 0.0);
   }
   src.fence();
   // fluid quantities the connection step needs: S^jk and the momentum-source cotangent
@@ -873,6 +871,8 @@ __host__ __device__ inline void pt_vjp(const DevParams& P, double t, const Src& 
 #pragma unroll
   for (int s = 0; s < 6; ++s) out.val(F_GT + s, bgt[s]);
   out.val(F_ALP, balpha);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) out.val(F_BET + i, P.evolve_shift ? -P.eta * src.cot(F_BET + i) : 0.0);
 }
 
 }  // namespace cosmos
