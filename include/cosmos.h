@@ -160,6 +160,13 @@ int cosmos_rhs(const cosmos_grid* grid, const cosmos_params* params, double t, c
 int cosmos_rk4_step(const cosmos_grid* grid, const cosmos_params* params, double t, double dt,
                     double* u, void* ws, void* stream);
 
+/* One RK4 step as cosmos_rk4_step (bitwise the same u), keeping the stage states for a reverse
+ * sweep: stages (device, caller-owned, 3 * 25 * N3 doubles, must not overlap u or ws) receives
+ * U2, U3, U4 in that order, each in the state layout, where U_{s+1} = u_n + c_s dt k_s
+ * (c = 1/2, 1/2, 1) is the state the next stage's right-hand side is evaluated at. */
+int cosmos_rk4_step_stages(const cosmos_grid* grid, const cosmos_params* params, double t, double dt,
+                           double* u, double* stages, void* ws, void* stream);
+
 /* Hamiltonian and momentum constraints of u and their grid norms:
  *   H   = R + 2/3 K^2 - At_ij At^ij - 16 pi E
  *   M_i = gt^jk (d_j At_ki - Gt^l_jk At_li - Gt^l_ji At_kl) - 3/(2 chi) At^j_i d_j chi - 2/3 d_i K - 8 pi S_i
@@ -189,6 +196,13 @@ int cosmos_rhs_vjp(const cosmos_grid* grid, const cosmos_params* params, double 
  * cosmos_adjoint_workspace_bytes. lam_n must not alias u_n or lam_np1. */
 int cosmos_adjoint_step(const cosmos_grid* grid, const cosmos_params* params, double t, double dt,
                         const double* u_n, const double* lam_np1, double* lam_n, void* ws, void* stream);
+
+/* cosmos_adjoint_step with the step's stage states supplied instead of recomputed: stages holds
+ * U2, U3, U4 as cosmos_rk4_step_stages wrote them when stepping from u_n (same params and dt).
+ * Same lam_n bitwise, three stage launches fewer. stages must not overlap lam_n or ws. */
+int cosmos_adjoint_step_stages(const cosmos_grid* grid, const cosmos_params* params, double t, double dt,
+                               const double* u_n, const double* stages, const double* lam_np1, double* lam_n,
+                               void* ws, void* stream);
 
 /* Batched form: many independent runs advanced together, one persistent launch per RK4 stage
  * for all of them (work items = (run, 16x4x4 brick)). Run r has a cubic periodic grid of n[r]^3

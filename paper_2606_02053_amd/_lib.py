@@ -64,8 +64,10 @@ def _load():
         "cosmos_init_tangent": ([G, Pr, In, i32, P, P], i32),
         "cosmos_rhs": ([G, Pr, f64, P, P, P, P], i32),
         "cosmos_rk4_step": ([G, Pr, f64, f64, P, P, P], i32),
+        "cosmos_rk4_step_stages": ([G, Pr, f64, f64, P, P, P, P], i32),
         "cosmos_constraints": ([G, Pr, P, P, P, P, P, P], i32),
         "cosmos_adjoint_step": ([G, Pr, f64, f64, P, P, P, P, P], i32),
+        "cosmos_adjoint_step_stages": ([G, Pr, f64, f64, P, P, P, P, P, P], i32),
         "cosmos_adjoint_workspace_bytes": ([G], sz),
         "cosmos_rhs_vjp": ([G, Pr, f64, P, P, P, P, P], i32),
         "cosmos_batch_workspace_bytes": ([B], sz),
@@ -182,6 +184,14 @@ def cosmos_rk4_step(grid, params, t: float, dt: float, u, ws, stream=None):
                                                                         dtype=torch.uint8), _stream(stream)))
 
 
+def cosmos_rk4_step_stages(grid, params, t: float, dt: float, u, stages, ws, stream=None):
+    N = NFIELDS * npts(grid)
+    _check(lib.cosmos_rk4_step_stages(ctypes.byref(grid), ctypes.byref(params), float(t), float(dt), _dev(u, "u", N),
+                                      _dev(stages, "stages", 3 * N),
+                                      _dev(ws, "ws", cosmos_workspace_bytes(grid), dtype=torch.uint8),
+                                      _stream(stream)))
+
+
 def cosmos_constraints(grid, params, u, norms_dev, H_out=None, M_out=None, ws=None, stream=None):
     N3 = npts(grid)
     _check(lib.cosmos_constraints(ctypes.byref(grid), ctypes.byref(params), _dev(u, "u", NFIELDS * N3),
@@ -200,6 +210,15 @@ def cosmos_adjoint_step(grid, params, t: float, dt: float, u_n, lam_np1, lam_n, 
                                    _dev(lam_np1, "lam_np1", N), _dev(lam_n, "lam_n", N),
                                    _dev(ws, "ws", cosmos_adjoint_workspace_bytes(grid), dtype=torch.uint8),
                                    _stream(stream)))
+
+
+def cosmos_adjoint_step_stages(grid, params, t: float, dt: float, u_n, stages, lam_np1, lam_n, ws, stream=None):
+    N = NFIELDS * npts(grid)
+    _check(lib.cosmos_adjoint_step_stages(ctypes.byref(grid), ctypes.byref(params), float(t), float(dt),
+                                          _dev(u_n, "u_n", N), _dev(stages, "stages", 3 * N),
+                                          _dev(lam_np1, "lam_np1", N), _dev(lam_n, "lam_n", N),
+                                          _dev(ws, "ws", cosmos_adjoint_workspace_bytes(grid), dtype=torch.uint8),
+                                          _stream(stream)))
 
 
 def cosmos_rhs_vjp(grid, params, t: float, u, kbar, ubar, ws, stream=None):

@@ -4,9 +4,12 @@ J is the lapse at the box centre after `nsteps` RK4 steps from the initial
 data of a Gaussian curvature perturbation (amplitude mu, width sigma). The
 forward pass stores the state every `checkpoint_every` steps; the backward
 pass recomputes each segment from its checkpoint and applies the adjoint step
-(cosmos_adjoint_step) backwards through it, starting from lambda = dJ/du(T)
-(a unit vector on the centre lapse), and finally contracts lambda_0 with the
-derivatives of the initial data in mu and sigma (cosmos_init_tangent).
+backwards through it, starting from lambda = dJ/du(T) (a unit vector on the
+centre lapse), and finally contracts lambda_0 with the derivatives of the
+initial data in mu and sigma (cosmos_init_tangent). Where device memory allows
+(`keep_stages`), the recomputation also keeps each step's RK4 stage states
+(cosmos_rk4_step_stages) so that the adjoint step does not evaluate them again
+(cosmos_adjoint_step_stages); the result is the same bitwise.
 """
 from __future__ import annotations
 
@@ -27,6 +30,9 @@ class RunConfig:
     cfl: float = 0.25
     params: C.cosmos_params = field(default_factory=C.make_params)
     init_kw: dict = field(default_factory=dict)  # extra cosmos_init fields (profile, center, ...)
+    # keep the stage states of a segment (3 states per step) for the reverse sweep:
+    # True / False, or None to decide by the free device memory
+    keep_stages: bool | None = None
 
     @property
     def dt(self) -> float:
@@ -63,15 +69,28 @@ class CosmosRun(torch.autograd.Function):
         lam_next = torch.empty_like(lam)
         ws_adj = torch.empty(C.cosmos_adjoint_workspace_bytes(grid), dtype=torch.uint8, device=dev)
         ws_fwd = torch.empty(C.cosmos_workspace_bytes(grid), dtype=torch.uint8, device=dev)
+        seg = cfg.checkpoint_every
+        keep = cfg.keep_stages
+        if keep is None:
+            keep = 3 * seg * lam.numel() * 8 < 0.5 * torch.cuda.mem_get_info(dev)[0]
+        stages = torch.empty((seg, 3 * lam.numel()), dtype=torch.float64, device=dev) if keep else None
         for start in sorted(ctx.ckpts, reverse=True):
-            end = min(start + cfg.checkpoint_every, cfg.nsteps)
+            end = min(start + seg, cfg.nsteps)
             states = [ctx.ckpts[start]]
             u = ctx.ckpts[start].clone()
-            for m in range(start, end - 1):  # recompute the segment's states
-                C.cosmos_rk4_step(grid, params, m * dt, dt, u, ws_fwd)
-                states.append(u.clone())
+            for m in range(start, end):  # recompute the segment's states (and stage states)
+                if keep:
+                    C.cosmos_rk4_step_stages(grid, params, m * dt, dt, u, stages[m - start], ws_fwd)
+                elif m < end - 1:
+                    C.cosmos_rk4_step(grid, params, m * dt, dt, u, ws_fwd)
+                if m < end - 1:
+                    states.append(u.clone())
             for m in range(end - 1, start - 1, -1):
-                C.cosmos_adjoint_step(grid, params, m * dt, dt, states[m - start], lam, lam_next, ws_adj)
+                if keep:
+                    C.cosmos_adjoint_step_stages(grid, params, m * dt, dt, states[m - start], stages[m - start], lam,
+                                                 lam_next, ws_adj)
+                else:
+                    C.cosmos_adjoint_step(grid, params, m * dt, dt, states[m - start], lam, lam_next, ws_adj)
                 lam, lam_next = lam_next, lam
         init = C.make_init(mu=ctx.mu, sigma=ctx.sigma, **cfg.init_kw)
         du = torch.empty_like(lam)

@@ -429,6 +429,29 @@ int launch_stage(const cosmos_params* p, const Tile& T, hipStream_t s, const dou
   }
   return COSMOS_OK;
 }
+// One RK4 step in place on u; the stage states go to U2, U3, U4 (U4 may be U2: it is
+// written after U2 has been read for the last time).
+int rk4_step(const cosmos_grid* grid, const cosmos_params* params, double t, double dt, double* u, double* U2,
+             double* U3, double* U4, void* ws, void* stream) {
+  const Layout L = layout(grid);
+  char* w = (char*)ws;
+  double* acc = (double*)(w + L.acc);
+  double* F = (double*)(w + L.F);
+  auto* status = (unsigned long long*)(w + L.status);
+  const DevParams P = dev_params(grid, params);
+  Tile T;
+  int rc;
+  if ((rc = make_tile(grid, params, T))) return rc;
+  const size_t fs = npts(grid);
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = launch_stage(params, T, s, u, F, u, acc, U2, fs, P, t, dt / 6.0, dt / 2.0, 1, status))) return rc;
+  launch_stage(params, T, s, U2, F, u, acc, U3, fs, P, t + dt / 2.0, dt / 3.0, dt / 2.0, 2, status);
+  launch_stage(params, T, s, U3, F, u, acc, U4, fs, P, t + dt / 2.0, dt / 3.0, dt, 2, status);
+  launch_stage(params, T, s, U4, F, nullptr, acc, u, fs, P, t + dt, dt / 6.0, 0.0, 3, status);
+  HIP_TRY(hipGetLastError());
+  return COSMOS_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- ABI
@@ -506,29 +529,31 @@ int cosmos_rhs(const cosmos_grid* grid, const cosmos_params* params, double t, c
   return COSMOS_OK;
 }
 
+
 int cosmos_rk4_step(const cosmos_grid* grid, const cosmos_params* params, double t, double dt, double* u, void* ws,
                     void* stream) {
   int rc;
   if ((rc = check_common(grid, params)) || (rc = check_state(u, "u")) || (rc = check_ws(grid, ws))) return rc;
   if (!(dt > 0.0) || !std::isfinite(dt) || !std::isfinite(t)) return set_error(COSMOS_EINVAL, "dt must be > 0, t finite");
   const Layout L = layout(grid);
-  char* w = (char*)ws;
-  double* acc = (double*)(w + L.acc);
-  double* A = (double*)(w + L.A);
-  double* B = (double*)(w + L.B);
-  double* F = (double*)(w + L.F);
-  auto* status = (unsigned long long*)(w + L.status);
-  const DevParams P = dev_params(grid, params);
-  Tile T;
-  if ((rc = make_tile(grid, params, T))) return rc;
-  const size_t fs = npts(grid);
-  hipStream_t s = (hipStream_t)stream;
-  if ((rc = launch_stage(params, T, s, u, F, u, acc, A, fs, P, t, dt / 6.0, dt / 2.0, 1, status))) return rc;
-  launch_stage(params, T, s, A, F, u, acc, B, fs, P, t + dt / 2.0, dt / 3.0, dt / 2.0, 2, status);
-  launch_stage(params, T, s, B, F, u, acc, A, fs, P, t + dt / 2.0, dt / 3.0, dt, 2, status);
-  launch_stage(params, T, s, A, F, nullptr, acc, u, fs, P, t + dt, dt / 6.0, 0.0, 3, status);
-  HIP_TRY(hipGetLastError());
-  return COSMOS_OK;
+  double* A = (double*)((char*)ws + L.A);
+  double* B = (double*)((char*)ws + L.B);
+  return rk4_step(grid, params, t, dt, u, A, B, A, ws, stream);
+}
+
+int cosmos_rk4_step_stages(const cosmos_grid* grid, const cosmos_params* params, double t, double dt, double* u,
+                           double* stages, void* ws, void* stream) {
+  int rc;
+  if ((rc = check_common(grid, params)) || (rc = check_state(u, "u")) || (rc = check_state(stages, "stages")) ||
+      (rc = check_ws(grid, ws)))
+    return rc;
+  if (!(dt > 0.0) || !std::isfinite(dt) || !std::isfinite(t)) return set_error(COSMOS_EINVAL, "dt must be > 0, t finite");
+  const size_t n = (size_t)NF * npts(grid);
+  const char *a = (const char*)stages, *a1 = a + 3 * n * sizeof(double);
+  const char *b = (const char*)u, *b1 = b + n * sizeof(double);
+  const char *c = (const char*)ws, *c1 = c + cosmos_workspace_bytes(grid);
+  if ((a < b1 && b < a1) || (a < c1 && c < a1)) return set_error(COSMOS_EINVAL, "stages overlaps u or ws");
+  return rk4_step(grid, params, t, dt, u, stages, stages + n, stages + 2 * n, ws, stream);
 }
 
 int cosmos_constraints(const cosmos_grid* grid, const cosmos_params* params, const double* u, double* norms_dev,

@@ -94,3 +94,46 @@ def test_gradient_small_run(P, orc):
                            cfg).item()
         fd.append((jp - jm) / (2 * h))
     assert np.allclose(g, fd, rtol=1e-6, atol=1e-9), (g, fd)
+
+
+def test_stage_keeping_step_and_adjoint_bitwise(P, orc):
+    """cosmos_rk4_step_stages advances u exactly as cosmos_rk4_step and hands over the stage
+    states (U2 = u + dt/2 f(u) against the oracle's right-hand side); cosmos_adjoint_step_stages
+    given them equals cosmos_adjoint_step bitwise."""
+    n, L = (8, 10, 12), (2.4, 3.0, 3.6)
+    s = orc.Setup(n=n, L=L)
+    u = fuzz_state(n, seed=51)
+    lam = fuzz_direction(n, seed=52)
+    dt = 0.25 * min(s.h)
+    grid, params = P.make_grid(n, L), P.make_params()
+    ws = torch.empty(P.cosmos_workspace_bytes(grid), dtype=torch.uint8, device="cuda")
+    wa = torch.empty(P.cosmos_adjoint_workspace_bytes(grid), dtype=torch.uint8, device="cuda")
+    ud = torch.from_numpy(u).cuda()
+    u1, u2 = ud.clone(), ud.clone()
+    stages = torch.full((3,) + tuple(ud.shape), float("nan"), dtype=torch.float64, device="cuda")
+    P.cosmos_rk4_step(grid, params, 0.2, dt, u1, ws)
+    P.cosmos_rk4_step_stages(grid, params, 0.2, dt, u2, stages, ws)
+    assert torch.equal(u1, u2)
+    r, _ = orc.rhs(s, u, t=0.2)
+    U2 = u + 0.5 * dt * r
+    assert rel_err(stages[0].cpu().numpy(), U2) < 1e-12
+    ld = torch.from_numpy(lam).cuda()
+    a, b = torch.empty_like(ld), torch.empty_like(ld)
+    P.cosmos_adjoint_step(grid, params, 0.2, dt, ud, ld, a, wa)
+    P.cosmos_adjoint_step_stages(grid, params, 0.2, dt, ud, stages, ld, b, wa)
+    assert torch.equal(a, b)
+    with pytest.raises(P.CosmosError):
+        P.cosmos_rk4_step_stages(grid, params, 0.2, dt, stages[0], stages, ws)  # stages overlaps u
+
+
+def test_gradient_with_and_without_kept_stages(P):
+    from paper_2606_02053_amd.adjoint import RunConfig, central_lapse
+    g = []
+    for keep in (True, False):
+        cfg = RunConfig(n=16, L=6.0, nsteps=9, checkpoint_every=4, keep_stages=keep)
+        mu = torch.tensor(0.55, dtype=torch.float64, requires_grad=True)
+        sigma = torch.tensor(1.2, dtype=torch.float64, requires_grad=True)
+        J = central_lapse(mu, sigma, cfg)
+        J.backward()
+        g.append((J.item(), mu.grad.item(), sigma.grad.item()))
+    assert g[0] == g[1]
