@@ -58,8 +58,8 @@ enum cosmos_status_code {
   COSMOS_EINVAL = -1,      /* invalid argument (null/misaligned pointer, n < 8, L <= 0, dt <= 0, small workspace) */
   COSMOS_EHIP = -2,        /* a HIP runtime call failed */
   COSMOS_ENOMEM = -3,      /* size overflow */
-  COSMOS_ENONFINITE = -4,  /* returned by cosmos_status_check when non-finite values were seen */
-  COSMOS_EPRIM = -5,       /* returned by cosmos_status_check when the fluid recovery failed */
+  COSMOS_ENONFINITE = -4,  /* reserved: non-finite values are counted on the device (cosmos_status) */
+  COSMOS_EPRIM = -5,       /* reserved: fluid-recovery failures are counted on the device (cosmos_status) */
   COSMOS_EUNSUPPORTED = -6 /* option not implemented (e.g. an unknown fluid scheme) */
 };
 

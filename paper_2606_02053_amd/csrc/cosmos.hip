@@ -327,7 +327,8 @@ __global__ __launch_bounds__(kBlock) void k_bssn_stage_lds(const double* U, cons
 
 namespace {
 // Workgroups of `kernel` resident on the whole device at once, rounded down to a
-// multiple of 8 (one slot per XCD per round), cached per device and kernel.
+// multiple of 8 (one slot per XCD per round), cached per device and kernel (per host
+// thread, so that concurrent callers share no mutable state).
 template <class K>
 unsigned resident_groups(K kernel) {
   struct Entry {
@@ -335,8 +336,8 @@ unsigned resident_groups(K kernel) {
     int dev;
     unsigned n;
   };
-  static Entry cache[64];
-  static int used = 0;
+  static thread_local Entry cache[64];
+  static thread_local int used = 0;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 8;
   for (int e = 0; e < used; ++e)
