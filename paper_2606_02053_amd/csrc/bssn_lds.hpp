@@ -126,6 +126,21 @@ struct HaloCopy {
   double v[kPrefetch][B::NQ];
   __device__ __forceinline__ void init(int i0, int j0, int k0, const int n[3]) { offsets(i0, j0, k0, n, goffb); }
   static __device__ __forceinline__ void offsets(int i0, int j0, int k0, const int n[3], uint32_t goffb[B::NQ]) {
+    // Most bricks' halo boxes lie inside the grid (82 % of the 16x4x4 bricks at 256^3): no
+    // wrap is needed there, and the choice is uniform over the workgroup.
+    const bool inside = i0 >= 3 && i0 + B::HX - 3 <= n[0] && j0 >= 3 && j0 + B::HY - 3 <= n[1] && k0 >= 3 &&
+                        k0 + B::HZ - 3 <= n[2];
+    if (inside) {
+      const int base = (i0 - 3) + n[0] * ((j0 - 3) + n[1] * (k0 - 3));
+#pragma unroll
+      for (int q = 0; q < B::NQ; ++q) {
+        const int e = threadIdx.x + 256 * q;
+        const int ee = e < B::NH ? e : 0;
+        const int hx = ee % B::HX, hy = (ee / B::HX) % B::HY, hz = ee / (B::HX * B::HY);
+        goffb[q] = 8u * (uint32_t)(base + hx + n[0] * (hy + n[1] * hz));
+      }
+      return;
+    }
 #pragma unroll
     for (int q = 0; q < B::NQ; ++q) {
       const int e = threadIdx.x + 256 * q;
@@ -524,8 +539,20 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
   double fa[3][4], fb[3][4];
   Nbr fnb;
   if (active) {
-    const int i = c % P.n[0], jk = c / P.n[0];
-    make_nbr(fnb, i, jk % P.n[1], jk / P.n[1], P.n);
+    const int i = c % P.n[0], jk = c / P.n[0], j = jk % P.n[1], k = jk / P.n[1];
+    if (i >= 3 && i + 3 < P.n[0] && j >= 3 && j + 3 < P.n[1] && k >= 3 && k + 3 < P.n[2]) {
+      // no wrap: uniform over the interior bricks, most of the grid
+      const int sy = P.n[0], sz = P.n[0] * P.n[1];
+      fnb.base = c;
+#pragma unroll
+      for (int o = -3; o <= 3; ++o) {
+        fnb.d[0][o + 3] = o;
+        fnb.d[1][o + 3] = o * sy;
+        fnb.d[2][o + 3] = o * sz;
+      }
+    } else {
+      make_nbr(fnb, i, j, k, P.n);
+    }
   }
 #pragma unroll
   for (int s = 0; s < 6; ++s) {
