@@ -77,3 +77,17 @@ def test_poisoned_run_is_isolated(P):
     for r in (0, 2, 3):
         assert st[r]["nonfinite"] == 0
         assert torch.equal(b.state(r), plain_run(P, runs[r], 2)), r
+
+
+def test_small_work_list_equals_plain_bitwise(P):
+    """Fewer work items than resident workgroups (32 bricks): the plain walk of the list
+    instead of the per-XCD split; same results."""
+    from paper_2606_02053_amd.batch import Batch, RunSpec
+    runs = [RunSpec(n=16, mu=0.5, sigma=1.1, L=6.0), RunSpec(n=16, mu=0.8, sigma=1.4, L=7.0)]
+    b = Batch(runs)
+    b.init()
+    for _ in range(2):
+        b.step()
+    torch.cuda.synchronize()
+    for r, spec in enumerate(runs):
+        assert torch.equal(b.state(r), plain_run(P, spec, 2)), r
