@@ -72,3 +72,29 @@ def test_binding_refuses_host_tensors(C):
     u = torch.zeros((25, 8, 8, 8), dtype=torch.float64)
     with pytest.raises(C.CosmosError):
         C.cosmos_rhs(g, C.make_params(), 0.0, u, u.clone(), torch.zeros(16, dtype=torch.uint8))
+
+
+def test_grid_size_limits(C):
+    """8 <= n_a <= 2048 and fewer than 2^29 points (32-bit byte offsets within one field)."""
+    assert C.cosmos_workspace_bytes(C.make_grid((2048, 1024, 255), 1.0)) > 0
+    assert C.cosmos_workspace_bytes(C.make_grid((2048, 2048, 128), 1.0)) == 0  # exactly 2^29 points
+    assert C.cosmos_workspace_bytes(C.make_grid((2049, 8, 8), 1.0)) == 0
+    assert C.cosmos_adjoint_workspace_bytes(C.make_grid((2048, 2048, 128), 1.0)) == 0
+
+
+def test_stage_keeping_entry_points_validate_on_host(C):
+    g = C.make_grid(16, 4.0)
+    p = C.make_params()
+    lib = C.lib
+    n = 25 * 16 ** 3 * 8
+    u = ctypes.c_void_p(0x10000000)  # never dereferenced: validation fails first
+    ws = ctypes.c_void_p(0x40000000)
+    rc = lib.cosmos_rk4_step_stages(ctypes.byref(g), ctypes.byref(p), 0.0, 0.1, u, None, ws, None)
+    assert rc == C.COSMOS_EINVAL and "stages is NULL" in C.last_error()
+    overlapping = ctypes.c_void_p(0x10000000 + n // 2)
+    rc = lib.cosmos_rk4_step_stages(ctypes.byref(g), ctypes.byref(p), 0.0, 0.1, u, overlapping, ws, None)
+    assert rc == C.COSMOS_EINVAL and "overlaps" in C.last_error()
+    lam = ctypes.c_void_p(0x20000000)
+    rc = lib.cosmos_adjoint_step_stages(ctypes.byref(g), ctypes.byref(p), 0.0, 0.1, u, ctypes.c_void_p(0x20000000 + 8),
+                                        u, lam, ws, None)
+    assert rc == C.COSMOS_EINVAL and "overlaps" in C.last_error()
