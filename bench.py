@@ -20,6 +20,9 @@ Extra modes:
                  sigma = 1.2, 200 RK4 steps, checkpoint every 20; gradient of the centre
                  lapse in (mu, sigma) by the discrete adjoint, its cost relative to the
                  plain forward run, and central finite differences (h = 1e-6)
+  --threshold    only the threshold search (32^3, box 12/H0, sigma = 1.2, 100 RK4 steps):
+                 batched multisection + Newton with the adjoint derivative for the amplitude
+                 whose centre lapse equals that of mu = 0.4371, against serial bisection
   --copy-probe   only a plain device-to-device copy of known size (calibrates
                  rocprofv3 FETCH_SIZE / WRITE_SIZE counters)
   --no-cpu       skip the CPU baseline leg
@@ -68,6 +71,7 @@ def parse():
     ap.add_argument("--headline-only", action="store_true", help="no batched / adjoint sub-objects")
     ap.add_argument("--batched-steps", type=int, default=30, help="timed steps (runs/s is scaled to 300 steps)")
     ap.add_argument("--adjoint", action="store_true")
+    ap.add_argument("--threshold", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=200, help="RK4 steps of the differentiated run")
     ap.add_argument("--no-fd", action="store_true", help="skip the finite-difference check of the adjoint")
     ap.add_argument("--config", default=None,
@@ -238,6 +242,45 @@ def adjoint_bench(a):
     return out
 
 
+def threshold_bench(a):
+    """Time to locate mu* (alpha_centre(T; mu*) = alpha_centre(T; 0.4371)) in [0.3, 0.6] to 1e-10:
+    batched multisection (3 rounds of 16 runs) + Newton with the adjoint derivative, against
+    serial bisection with the plain solver (one run per bisection step, its cost measured).
+    A 32^3 run fills half the GPU, so 16 of them in one batch cost little more than one."""
+    import math
+    import paper_2606_02053_amd as P
+    from paper_2606_02053_amd.threshold import find_threshold
+    n, L, sigma, nsteps, mu_ref, lo, hi, tol = 32, 12.0, 1.2, 100, 0.4371, 0.3, 0.6, 1e-10
+    dt = 0.25 * L / n
+    s = P.Solver(n, L)
+
+    def plain_run(mu):
+        s.init(mu=mu, sigma=sigma)
+        for m in range(nsteps):
+            P.cosmos_rk4_step(s.grid, s.params, m * dt, dt, s.u, s.ws)
+        torch.cuda.synchronize()
+        return float(s.u[17, n // 2, n // 2, n // 2])
+
+    target = plain_run(mu_ref)
+    t0 = time.perf_counter()
+    plain_run(mu_ref)
+    t_run = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    res = find_threshold(sigma, lo, hi, target, n=n, L=L, nsteps=nsteps, K=16, rounds=3, tol=tol)
+    torch.cuda.synchronize()
+    t_search = time.perf_counter() - t0
+    bisect_runs = math.ceil(math.log2((hi - lo) / tol))
+    return {"metric": "threshold search time (batched multisection + adjoint Newton)", "value": t_search,
+            "unit": "s", "higher_is_better": False, "mu_found": res.mu, "mu_reference": mu_ref,
+            "abs_error": abs(res.mu - mu_ref), "J_at_mu": res.J, "dJ_dmu": res.dJ_dmu,
+            "batched_runs": res.batched_runs, "newton_steps": res.newton_steps,
+            "serial_bisection_runs": bisect_runs, "serial_run_s": t_run,
+            "serial_bisection_s_estimate": bisect_runs * t_run, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"{n}^3 periodic, L = 12/H0, Gaussian zeta sigma = 1.2, {nsteps} RK4 steps, "
+                                   f"CFL 0.25; mu* in [{lo}, {hi}] with alpha_centre(T; mu*) = alpha_centre(T; "
+                                   f"{mu_ref}), tolerance {tol}"}}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -255,6 +298,9 @@ def main():
         return
     if a.adjoint:
         print(json.dumps(adjoint_bench(a)), flush=True)
+        return
+    if a.threshold:
+        print(json.dumps(threshold_bench(a)), flush=True)
         return
     import paper_2606_02053_amd as P
     from paper_2606_02053_amd import autotune

@@ -1,0 +1,32 @@
+"""Threshold search (batched multisection + Newton with the adjoint derivative)
+against the oracle: the target lapse is the oracle's centre lapse at a known
+amplitude, so the threshold is that amplitude; the derivative at the root is
+checked against the oracle's exact forward-mode tangent."""
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def test_threshold_search_recovers_oracle_amplitude(orc):
+    from paper_2606_02053_amd.threshold import find_threshold
+    n, L, nsteps, sigma, mu_star = 16, 6.0, 10, 1.2, 0.4137
+    s = orc.Setup(n=(n, n, n), L=(L, L, L))
+    dt = 0.25 * L / n
+    c = n // 2
+    ini = orc.Init(mu=mu_star, sigma=sigma)
+    u, _ = orc.rk4(s, orc.init_fields(s, ini), 0.0, dt, nsteps, parallel=True)
+    target = float(u[17, c, c, c])
+    res = find_threshold(sigma, 0.3, 0.5, target, n=n, L=L, nsteps=nsteps, K=8, rounds=2)
+    batched = [m for stage, m, _ in res.history if stage == "batched"]
+    assert len(batched) == 16 and res.batched_runs == 17
+    # the final bracket closes on the root of the GPU's J, which differs from the oracle's
+    # amplitude by rounding only
+    lo, hi = res.bracket
+    assert min(lo, hi) - 1e-9 <= mu_star <= max(lo, hi) + 1e-9
+    assert abs(res.mu - mu_star) < 1e-9, res
+    assert 2 <= res.newton_steps <= 8  # mu* is off the bracket midpoints: Newton has work to do
+    # dJ/dmu at the root: the oracle's exact derivative of the discrete map
+    u, v = orc.init_fields(s, ini), orc.init_tangent(s, ini, 0)
+    for m in range(nsteps):
+        u, v = orc.jvp(s, u, v, "step", t=m * dt, dt=dt)
+    assert res.dJ_dmu == pytest.approx(float(v[17, c, c, c]), rel=1e-8)
