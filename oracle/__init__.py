@@ -17,7 +17,7 @@ Paper passages followed (the paper's sections; its equations are unnumbered):
     fluid distribution, no elliptic solver);
   * "Statement of need" / "Examples": periodic box of size L.
 Parameter conventions: ``prm = (w, H0, eta, ko_eps)``, ``iprm = (lapse_bg,
-evolve_shift)``; states are float64 arrays of shape (25, nz, ny, nx).
+evolve_shift, fluid_scheme)``; states are float64 arrays of shape (25, nz, ny, nx).
 """
 from __future__ import annotations
 
@@ -81,6 +81,8 @@ def lib():
             "oracle_point_rhs": [P, P, f64, P, f64, P, P],
             "oracle_matter_point": [f64, f64, P, f64, P, P],
             "oracle_flux_point": [P, P, P],
+            "oracle_kt_flux": [P, P, P, i32, P],
+            "oracle_fluid_speeds": [P, P, i32, P],
             "oracle_splitmix64": [u64, u64],
             "oracle_stencil": [P, P, P, i32, i32, i32, i32, i32, i32, P, f64, P],
             "oracle_gamma_constraint": [P, P, P, P],
@@ -110,11 +112,12 @@ class Setup:
     ko_eps: float = 0.1
     lapse_bg: int = 1
     evolve_shift: int = 1
+    fluid_scheme: int = 0  # 0: centred flux divergence + KO; 1: Kurganov-Tadmor fluxes
 
     def arrays(self):
         return (np.ascontiguousarray(self.n, dtype=np.int32), np.ascontiguousarray(self.L, dtype=np.float64),
                 np.array([self.w, self.H0, self.eta, self.ko_eps], dtype=np.float64),
-                np.array([self.lapse_bg, self.evolve_shift], dtype=np.int32))
+                np.array([self.lapse_bg, self.evolve_shift, self.fluid_scheme], dtype=np.int32))
 
     @property
     def shape(self):
@@ -306,6 +309,25 @@ def flux_point(s: Setup, u25) -> np.ndarray:
     out = np.empty(12)
     lib().oracle_flux_point(_p(prm), _p(u25), _p(out))
     return out
+
+
+def kt_flux(s: Setup, uL, uR, a: int) -> np.ndarray:
+    """Kurganov-Tadmor numerical flux along axis a between two interface states (25 values each)."""
+    _, _, prm, _ = s.arrays()
+    uL = np.ascontiguousarray(uL, dtype=np.float64)
+    uR = np.ascontiguousarray(uR, dtype=np.float64)
+    out = np.empty(4)
+    _check(lib().oracle_kt_flux(_p(prm), _p(uL), _p(uR), a, _p(out)), "oracle_kt_flux")
+    return out
+
+
+def fluid_speeds(s: Setup, u25, a: int) -> tuple:
+    """(lambda_minus, lambda_plus), the fluid's characteristic speeds along axis a."""
+    _, _, prm, _ = s.arrays()
+    u25 = np.ascontiguousarray(u25, dtype=np.float64)
+    out = np.empty(2)
+    _check(lib().oracle_fluid_speeds(_p(prm), _p(u25), a, _p(out)), "oracle_fluid_speeds")
+    return float(out[0]), float(out[1])
 
 
 def splitmix64(seed: int, p: int) -> int:

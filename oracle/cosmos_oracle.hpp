@@ -79,6 +79,7 @@ struct Params {
   double ko_eps = 0.1;   // Kreiss-Oliger strength
   int lapse_bg = 1;      // 1: lapse source uses K - K_bg(t); 0: plain 1+log
   int evolve_shift = 1;  // 1: Gamma-driver shift; 0: shift frozen
+  int fluid_scheme = 0;  // 0: centred 4th-order flux divergence + KO; 1: Kurganov-Tadmor interface fluxes
 };
 
 enum Profile : int { GAUSS = 0, SINE = 1, PGAUSS = 2 };
@@ -433,6 +434,100 @@ void fluid_flux(const Params& p, const T u[NF], T out[12]) {
   }
 }
 
+// ------------------------------------------------------------------ Kurganov-Tadmor fluxes
+// The paper's fluid scheme (section "Physical system settings" cites Kurganov &
+// Tadmor 2000 and Shibata & Font 2005): a semi-discrete central scheme in
+// conservation form, d q_i/dt = -sum_a (Fh^a_{i+1/2} - Fh^a_{i-1/2}) / h_a + sources,
+// with the numerical flux at the interface i+1/2 along axis a
+//   Fh = 1/2 (F^a(q_L) + F^a(q_R)) - 1/2 c (q_R - q_L),
+// q = (Et, St_i) the densitised conserved variables reconstructed piecewise
+// linearly with the minmod limiter,
+//   q_L = q_i + s_i / 2,  q_R = q_{i+1} - s_{i+1} / 2,  s_i = minmod(q_i - q_{i-1}, q_{i+1} - q_i),
+// and c the largest characteristic speed magnitude of the two interface states.
+// The geometric fields at the interface are the average of the two neighbours.
+
+// minmod(a, b): the argument of smaller magnitude when both have the same strict
+// sign, else 0 (equal magnitudes give the same value either way).
+template <class T>
+T minmod(const T& a, const T& b) {
+  if (value(a) > 0.0 && value(b) > 0.0) return value(a) < value(b) ? a : b;
+  if (value(a) < 0.0 && value(b) < 0.0) return value(a) > value(b) ? a : b;
+  return T(0.0);
+}
+
+// Characteristic speeds of the perfect fluid along axis a (the sound-wave pair
+// of the relativistic Euler equations in 3+1 form, e.g. Banyuls et al. 1997;
+// sound speed cs^2 = w for P = w rho):
+//   lambda_pm = alpha / (1 - v^2 cs^2) [v^a (1 - cs^2)
+//                 pm cs sqrt((1 - v^2)(gamma^aa (1 - v^2 cs^2) - (v^a)^2 (1 - cs^2)))] - beta^a
+// with the Eulerian velocity v^i = S^i / X and v^2 = S^2 / X^2. A negative
+// radicand (only possible at unphysical states) is taken as 0; a state whose
+// recovery failed has invX = 0, hence v = 0.
+template <class T>
+void fluid_speeds(const Params& p, const T u[NF], int a, T& lm, T& lp) {
+  T gt[6], gi[6], det, St[3];
+  for (int s = 0; s < 6; ++s) gt[s] = u[GT + s];
+  inverse_sym(gt, gi, det);
+  for (int i = 0; i < 3; ++i) St[i] = u[ST + i];
+  Matter<T> M;
+  matter(p, u[CHI], gt, gi, u[ET], St, M);
+  const T cs2 = T(p.w);
+  const T cs = sqrt(cs2);
+  const T va = M.Sup[a] * M.invX;
+  const T v2 = M.S2 * M.invX * M.invX;
+  const T gaa = u[CHI] * gi[SYM[a][a]];
+  T rad = (T(1.0) - v2) * (gaa * (T(1.0) - v2 * cs2) - va * va * (T(1.0) - cs2));
+  if (!(value(rad) > 0.0)) rad = T(0.0);
+  const T root = value(rad) > 0.0 ? sqrt(rad) : T(0.0);
+  const T f = u[ALP] / (T(1.0) - v2 * cs2);
+  lp = f * (va * (T(1.0) - cs2) + cs * root) - u[BET + a];
+  lm = f * (va * (T(1.0) - cs2) - cs * root) - u[BET + a];
+}
+
+template <class T>
+T absval(const T& x) {
+  return value(x) < 0.0 ? -x : x;
+}
+
+template <class T>
+T maxval(const T& x, const T& y) {
+  return value(y) > value(x) ? y : x;
+}
+
+// Numerical flux along axis a between the interface states uL and uR (25 values
+// each): out[q] for q = Et, St_x, St_y, St_z.
+template <class T>
+void kt_flux(const Params& p, const T uL[NF], const T uR[NF], int a, T out[4]) {
+  T FL[12], FR[12];
+  fluid_flux(p, uL, FL);
+  fluid_flux(p, uR, FR);
+  T lmL, lpL, lmR, lpR;
+  fluid_speeds(p, uL, a, lmL, lpL);
+  fluid_speeds(p, uR, a, lmR, lpR);
+  const T c = maxval(maxval(absval(lmL), absval(lpL)), maxval(absval(lmR), absval(lpR)));
+  for (int q = 0; q < 4; ++q)
+    out[q] = T(0.5) * (FL[4 * a + q] + FR[4 * a + q]) - T(0.5) * c * (uR[ET + q] - uL[ET + q]);
+}
+
+// Interface states at i+1/2 along axis a of the padded window, from the points
+// i-1 .. i+2 along a: geometry averaged, fluid reconstructed.
+template <class T, class Window>
+void kt_interface_states(const Window& P, int i, int j, int k, int a, T uL[NF], T uR[NF]) {
+  auto at = [&](int f, int o) {
+    int d[3] = {0, 0, 0};
+    d[a] = o;
+    return P(f, i + d[0], j + d[1], k + d[2]);
+  };
+  for (int f = 0; f < ET; ++f) uL[f] = uR[f] = T(0.5) * (at(f, 0) + at(f, 1));
+  for (int f = ET; f < NF; ++f) {
+    const T qm = at(f, -1), q0 = at(f, 0), q1 = at(f, 1), q2 = at(f, 2);
+    const T s0 = minmod(q0 - qm, q1 - q0);
+    const T s1 = minmod(q1 - q0, q2 - q1);
+    uL[f] = q0 + T(0.5) * s0;
+    uR[f] = q1 - T(0.5) * s1;
+  }
+}
+
 // ------------------------------------------------------------------ RHS
 // Background trace K_bg(t) of the radiation FLRW universe with unit lapse:
 // a(t) = (1 + 2 H0 t)^(1/2), H = H0 / (1 + 2 H0 t), K_bg = -3H.
@@ -597,16 +692,31 @@ void rhs_padded(const Grid& g, const Params& p, double t, const Padded<T>& P, T*
     return (size_t)c + 12 * ((size_t)(i + NG) + (size_t)P.p[0] * ((size_t)(j + NG) + (size_t)P.p[1] * (size_t)(k + NG)));
   };
   const bool par = parallel && std::is_same<T, double>::value;
+  const bool kt = p.fluid_scheme == 1;
+  if (!kt) {
 #pragma omp parallel for schedule(static) if (par)
-  for (int k = -2; k < m[2] + 2; ++k)
-    for (int j = -2; j < m[1] + 2; ++j)
-      for (int i = -2; i < m[0] + 2; ++i) {
-        T u[NF];
-        for (int f = 0; f < NF; ++f) u[f] = P(f, i, j, k);
-        T fl[12];
-        fluid_flux(p, u, fl);
-        for (int c = 0; c < 12; ++c) F[fidx(c, i, j, k)] = fl[c];
-      }
+    for (int k = -2; k < m[2] + 2; ++k)
+      for (int j = -2; j < m[1] + 2; ++j)
+        for (int i = -2; i < m[0] + 2; ++i) {
+          T u[NF];
+          for (int f = 0; f < NF; ++f) u[f] = P(f, i, j, k);
+          T fl[12];
+          fluid_flux(p, u, fl);
+          for (int c = 0; c < 12; ++c) F[fidx(c, i, j, k)] = fl[c];
+        }
+  } else {
+    // F[4a + q] at (i, j, k) holds the KT flux through the interface at i+1/2 along a
+#pragma omp parallel for schedule(static) if (par)
+    for (int k = -1; k < m[2]; ++k)
+      for (int j = -1; j < m[1]; ++j)
+        for (int i = -1; i < m[0]; ++i)
+          for (int a = 0; a < 3; ++a) {
+            T uL[NF], uR[NF], fh[4];
+            kt_interface_states<T>(P, i, j, k, a, uL, uR);
+            kt_flux(p, uL, uR, a, fh);
+            for (int q = 0; q < 4; ++q) F[fidx(4 * a + q, i, j, k)] = fh[q];
+          }
+  }
   const int64_t M3 = (int64_t)m[0] * m[1] * m[2];
   int64_t fails = 0;
 #pragma omp parallel for schedule(static) reduction(+ : fails) if (par)
@@ -627,6 +737,13 @@ void rhs_padded(const Grid& g, const Params& p, double t, const Padded<T>& P, T*
         for (int c = 0; c < 4; ++c) {
           T div = T(0.0);
           for (int a = 0; a < 3; ++a) {
+            if (kt) {
+              int d[3] = {0, 0, 0};
+              d[a] = -1;
+              div = div + (F[fidx(4 * a + c, i, j, k)] - F[fidx(4 * a + c, i + d[0], j + d[1], k + d[2])]) *
+                              T(1.0 / h[a]);
+              continue;
+            }
             T v[4];
             for (int q = 0; q < 4; ++q) {
               int d[3] = {0, 0, 0};
@@ -637,9 +754,11 @@ void rhs_padded(const Grid& g, const Params& p, double t, const Padded<T>& P, T*
           }
           r[ET + c] = r[ET + c] - div;
         }
-        // Kreiss-Oliger dissipation on every evolved field
+        // Kreiss-Oliger dissipation on every evolved field (with the KT scheme,
+        // on the geometric fields only: the scheme carries its own dissipation)
         for (int f = 0; f < NF; ++f) {
           if (f >= BET && f < ET && !p.evolve_shift) continue;
+          if (kt && f >= ET) continue;
           r[f] = r[f] + KO(P, h, p.ko_eps, f, i, j, k);
         }
         const int64_t q = i + (int64_t)m[0] * (j + (int64_t)m[1] * k);

@@ -2,7 +2,7 @@
 // Python through ctypes by tests/, the smoke check and the CPU baseline.
 //
 // Conventions: n[3] grid points and L[3] box lengths per axis; prm = {w, H0,
-// eta, ko_eps}; iprm = {lapse_bg, evolve_shift}; states are SoA float64 arrays
+// eta, ko_eps}; iprm = {lapse_bg, evolve_shift, fluid_scheme}; states are SoA float64 arrays
 // of 25 * n0*n1*n2 values (x fastest). Every function returns 0 on success and
 // a negative value on invalid arguments.
 #include <cstdint>
@@ -31,6 +31,8 @@ static bool make(const int* n, const double* L, const double* prm, const int* ip
   p.ko_eps = prm[3];
   p.lapse_bg = iprm[0];
   p.evolve_shift = iprm[1];
+  p.fluid_scheme = iprm[2];
+  if (p.fluid_scheme != 0 && p.fluid_scheme != 1) return false;
   return true;
 }
 
@@ -403,6 +405,25 @@ int oracle_flux_point(const double* prm, const double* u, double* out) {
   return 0;
 }
 
+// Kurganov-Tadmor numerical flux along axis a between two interface states
+// (25 values each): out[4] for Et, St_x, St_y, St_z.
+int oracle_kt_flux(const double* prm, const double* uL, const double* uR, int a, double* out) {
+  if (!prm || !uL || !uR || !out || a < 0 || a > 2) return -1;
+  Params p;
+  p.w = prm[0];
+  kt_flux(p, uL, uR, a, out);
+  return 0;
+}
+
+// Characteristic speeds (lambda_minus, lambda_plus) of the fluid along axis a at one state.
+int oracle_fluid_speeds(const double* prm, const double* u, int a, double* out) {
+  if (!prm || !u || !out || a < 0 || a > 2) return -1;
+  Params p;
+  p.w = prm[0];
+  fluid_speeds(p, u, a, out[0], out[1]);
+  return 0;
+}
+
 // Stencil operators applied at grid point (i, j, k) to a single periodic grid
 // function f (n0*n1*n2 values): kind 0 = D1 along a, 1 = D2 along a,
 // 2 = D1_a(D1_b f), 3 = advection with shift beta[3], 4 = Kreiss-Oliger (eps).
@@ -411,7 +432,7 @@ int oracle_stencil(const int* n, const double* L, const double* f, int i, int j,
   Grid g;
   Params p;
   const double prm[4] = {1.0 / 3.0, 1.0, 1.0, 0.1};
-  const int iprm[2] = {1, 1};
+  const int iprm[3] = {1, 1, 0};
   if (!make(n, L, prm, iprm, g, p) || !f || !out) return -1;
   const int64_t N3 = g.npts();
   std::vector<double> u((size_t)NF * N3, 0.0);
@@ -438,7 +459,7 @@ int oracle_gamma_constraint(const int* n, const double* L, const double* u, doub
   Grid g;
   Params p;
   const double prm[4] = {1.0 / 3.0, 1.0, 1.0, 0.1};
-  const int iprm[2] = {1, 1};
+  const int iprm[3] = {1, 1, 0};
   if (!make(n, L, prm, iprm, g, p) || !u || !out) return -1;
   Padded<double> P;
   const int o[3] = {0, 0, 0};
