@@ -83,7 +83,14 @@ typedef struct {
  *   lapse_bg 1: d_t alpha = beta.grad alpha - 2 alpha (K - K_bg(t)), K_bg = -3 H0 / (1 + 2 H0 t),
  *            which keeps alpha = 1 on the radiation background; 0: plain 1+log (K_bg = 0)
  *   evolve_shift 1: d_t beta^i = beta.grad beta^i + 3/4 Gt^i - eta beta^i; 0: shift frozen
- *   fluid_scheme 0: centred 4th-order flux divergence (the only scheme implemented)
+ *   fluid_scheme 0: centred 4th-order flux divergence of the point fluxes, KO dissipation on every field;
+ *            1: Kurganov-Tadmor central scheme ("Physical system settings" cites Kurganov & Tadmor 2000):
+ *            conservation form with interface fluxes 1/2 (F(q_L) + F(q_R)) - 1/2 c (q_R - q_L), q_L, q_R
+ *            minmod-limited linear reconstructions of (Et, St_i), the geometry averaged to the interface,
+ *            c the largest characteristic speed of the two sides; no KO on the fluid fields. Supported by
+ *            cosmos_rhs, cosmos_rk4_step(_stages) and cosmos_constraints (which do not depend on it); the
+ *            adjoint and batched entry points return COSMOS_EUNSUPPORTED for it. Other values:
+ *            COSMOS_EUNSUPPORTED
  *   variant  stage-kernel implementation: 0 = LDS-staged bricks (default; bricks 16x4x4, 16x8x2,
  *            8x8x4, 8x4x8), 1 = direct loads through the caches (any brick); same results
  *   alpha_collapse  a point with alpha below this value after a step counts as collapsed (0: off)
@@ -119,7 +126,7 @@ typedef struct {
 
 /* Bytes of device workspace needed by cosmos_rhs / cosmos_rk4_step / cosmos_constraints on this
  * grid: the status counters, the reduction partials, 3 state-sized RK4 buffers and 12 * N3
- * doubles for the fluid fluxes that every stage forms in a pointwise pre-pass. Returns 0 for an
+ * doubles for the fluid fluxes that every stage forms in a pre-pass (the point fluxes; with fluid_scheme 1 the first 4 * N3 hold the Kurganov-Tadmor flux divergence). Returns 0 for an
  * invalid grid. */
 size_t cosmos_workspace_bytes(const cosmos_grid* grid);
 

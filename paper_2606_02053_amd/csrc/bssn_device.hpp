@@ -48,6 +48,8 @@ struct DevParams {
   double i144[3];   // 1 / (144 h_a h_b) for pairs (0,1), (0,2), (1,2)
   double iko[3];    // ko_eps / (64 h_a)
   double i24h[3];   // 1 / (24 h_a)
+  double ih[3];     // 1 / h_a
+  int fluid_scheme; // 0: centred 4th-order flux divergence + KO; 1: Kurganov-Tadmor (divergence from its pre-pass)
 };
 
 // Brick decomposition of the grid for the stage kernel: a workgroup of
@@ -378,10 +380,16 @@ __device__ __forceinline__ void flux_axis_add(const double v[4][4], double i12h,
 
 // The same divergence for one conserved variable q: flux_var_load fetches F^a_q at
 // the four neighbours along each axis a, flux_var_div sums the centred differences
-// over a = 0, 1, 2 (the order flux_divergence uses).
+// over a = 0, 1, 2 (the order flux_divergence uses). With the Kurganov-Tadmor
+// scheme (kt) the pre-pass has stored the whole divergence of q at F[q fs + c]:
+// one load, returned as it is.
 __device__ __forceinline__ void flux_var_load(const double* F, size_t fs, int c, const Nbr& nb, int q,
-                                              double v[3][4]) {
+                                              double v[3][4], bool kt) {
   const uint32_t nbytes = (uint32_t)(fs * 8);
+  if (kt) {
+    v[0][0] = bld(field_ptr(F, q, fs), nbytes, (uint32_t)c * 8u);
+    return;
+  }
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const double* Fa = field_ptr(F, 4 * a + q, fs);
@@ -393,6 +401,7 @@ __device__ __forceinline__ void flux_var_load(const double* F, size_t fs, int c,
 }
 
 __device__ __forceinline__ double flux_var_div(const double v[3][4], const DevParams& P) {
+  if (P.fluid_scheme == 1) return v[0][0];
   double div = 0.0;
 #pragma unroll
   for (int a = 0; a < 3; ++a) div += ((v[a][0] - v[a][3]) + 8.0 * (v[a][2] - v[a][1])) * P.i12h[a];
@@ -401,6 +410,11 @@ __device__ __forceinline__ double flux_var_div(const double v[3][4], const DevPa
 
 __device__ __forceinline__ void flux_divergence(const double* F, size_t fs, int c, const Nbr& nb, const DevParams& P,
                                                 double div[4]) {
+  if (P.fluid_scheme == 1) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) div[q] = ldq(field_ptr(F, q, fs), c);
+    return;
+  }
 #pragma unroll
   for (int q = 0; q < 4; ++q) div[q] = 0.0;
 #pragma unroll
@@ -800,7 +814,8 @@ __device__ __forceinline__ void bssn_rhs_stream(const double* U, const double* F
       KS += (s == 0 || s == 3 || s == 5 ? 1.0 : 2.0) * Kij * rec_Sjk(R, chi, s);
     }
     double dummy[3];
-    const double ko = field_advko<false>(U + F_ET * fs, nb, P, nbeta, dummy);
+    // the Kurganov-Tadmor scheme carries its own dissipation: no KO on the fluid
+    const double ko = P.fluid_scheme == 1 ? 0.0 : field_advko<false>(U + F_ET * fs, nb, P, nbeta, dummy);
     const double Sda = R[R_SUP + 0] * R[R_DAL + 0] + R[R_SUP + 1] * R[R_DAL + 1] + R[R_SUP + 2] * R[R_DAL + 2];
     sink.put(F_ET, ko + (im32 * (alpha * KS - Sda) - div[0]));
   }
@@ -811,7 +826,7 @@ __device__ __forceinline__ void bssn_rhs_stream(const double* U, const double* F
 #pragma unroll
     for (int s = 0; s < 6; ++s) sgt += (s == 0 || s == 3 || s == 5 ? 1.0 : 2.0) * rec_Sjk(R, chi, s) * gt[s];
     double dummy[3];
-    const double ko = field_advko<false>(U + (F_ST + i) * fs, nb, P, nbeta, dummy);
+    const double ko = P.fluid_scheme == 1 ? 0.0 : field_advko<false>(U + (F_ST + i) * fs, nb, P, nbeta, dummy);
     double src = -R[R_E] * R[R_DAL + i] +
                  (R[R_S + 0] * R[R_DB + 0 + i] + R[R_S + 1] * R[R_DB + 3 + i] + R[R_S + 2] * R[R_DB + 6 + i]);
     const double ichi = 1.0 / chi;

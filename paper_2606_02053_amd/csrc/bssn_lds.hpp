@@ -537,6 +537,7 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
   // completes its right-hand side (q = 0 in At phase 4, 1 in At phase 5, 2 in the
   // Et phase, 3 in the first St phase), so their latency overlaps the algebra.
   double fa[3][4], fb[3][4];
+  const bool kt = P.fluid_scheme == 1;  // divergence formed by the Kurganov-Tadmor pre-pass
   Nbr fnb;
   if (active) {
     const int i = c % P.n[0], jk = c / P.n[0], j = jk % P.n[1], k = jk / P.n[1];
@@ -558,8 +559,8 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
   for (int s = 0; s < 6; ++s) {
     prefetch();
     if (active) {
-      if (s == 4) flux_var_load(F, fs, c, fnb, 0, fa);
-      if (s == 5) flux_var_load(F, fs, c, fnb, 1, fb);
+      if (s == 4) flux_var_load(F, fs, c, fnb, 0, fa, kt);
+      if (s == 5) flux_var_load(F, fs, c, fnb, 1, fb, kt);
       double db[3][3];
 #pragma unroll
       for (int q = 0; q < 9; ++q) db[q / 3][q % 3] = R[R3_DB + q];
@@ -580,14 +581,15 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
     advance(0);
   }
 
-  // ---- fluid: flux divergence (fluxes from the pointwise pre-pass), sources, dissipation
+  // ---- fluid: flux divergence (from the pre-pass), sources, dissipation (KO only
+  // with the centred scheme: the Kurganov-Tadmor scheme carries its own)
   const double nbeta[3] = {0.0, 0.0, 0.0};
   const double im32 = 1.0 / (chi * sqrt(chi));
   double sgt = 0.0;  // S^jk gt_jk (formed in the Et phase, used by the St phases)
   prefetch();
   if (active) {
     const double div0 = flux_var_div(fa, P);
-    flux_var_load(F, fs, c, fnb, 2, fa);
+    flux_var_load(F, fs, c, fnb, 2, fa, kt);
     double KS = 0.0;
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
@@ -598,7 +600,7 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
     FieldDerivs d;
     lds_derivs<B, false, false>(cur(), P, nbeta, d);
     const double Sda = Sup[0] * R[R3_DAL + 0] + Sup[1] * R[R3_DAL + 1] + Sup[2] * R[R3_DAL + 2];
-    sink.put(F_ET, d.advko + (im32 * (alpha * KS - Sda) - div0), ep[0][0]);
+    sink.put(F_ET, (kt ? 0.0 : d.advko) + (im32 * (alpha * KS - Sda) - div0), ep[0][0]);
   }
   advance(0);
   double cnext[NF];  // the next brick's point values, loaded during the St phases
@@ -614,7 +616,7 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
       double divi;
       if (i == 0) {
         divi = flux_var_div(fb, P);
-        flux_var_load(F, fs, c, fnb, 3, fb);
+        flux_var_load(F, fs, c, fnb, 3, fb, kt);
       } else {
         divi = flux_var_div(i == 1 ? fa : fb, P);
       }
@@ -623,7 +625,7 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
       double src = -R[R3_E] * R[R3_DAL + i] +
                    (R[R3_S + 0] * R[R3_DB + 0 + i] + R[R3_S + 1] * R[R3_DB + 3 + i] + R[R3_S + 2] * R[R3_DB + 6 + i]);
       src += 0.5 * alpha * (R[R3_SG + i] * ichi - sgt * R[R3_DCHI + i] * (ichi * ichi));
-      sink.put(F_ST + i, d.advko + (im32 * src - divi), ep[0][0]);
+      sink.put(F_ST + i, (kt ? 0.0 : d.advko) + (im32 * src - divi), ep[0][0]);
     }
     if (i < 2) advance(0);
   }

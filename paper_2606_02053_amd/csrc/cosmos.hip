@@ -17,6 +17,7 @@
 #include "init_device.hpp"
 #include "constraints_device.hpp"
 #include "bssn_lds.hpp"
+#include "kt_device.hpp"
 #include "adjoint_point.hpp"
 
 using namespace cosmos;
@@ -85,8 +86,17 @@ int check_common(const cosmos_grid* g, const cosmos_params* p) {
   if (!std::isfinite(p->w) || !std::isfinite(p->H0) || !std::isfinite(p->eta) || !std::isfinite(p->ko_eps) ||
       !(p->w > 0.0))
     return set_error(COSMOS_EINVAL, "invalid params (w must be > 0; all values finite)");
-  if (p->fluid_scheme != 0) return set_error(COSMOS_EUNSUPPORTED, "fluid_scheme %d not implemented", p->fluid_scheme);
+  if (p->fluid_scheme != 0 && p->fluid_scheme != 1)
+    return set_error(COSMOS_EUNSUPPORTED, "fluid_scheme %d not implemented (0: centred, 1: Kurganov-Tadmor)",
+                     p->fluid_scheme);
   if (p->variant != 0 && p->variant != 1) return set_error(COSMOS_EINVAL, "variant must be 0 (LDS-staged) or 1 (direct)");
+  return COSMOS_OK;
+}
+
+// Entry points whose kernels implement the centred fluid scheme only (the batched
+// form and the adjoint).
+int check_centred(const cosmos_params* p, const char* what) {
+  if (p->fluid_scheme != 0) return set_error(COSMOS_EUNSUPPORTED, "%s supports fluid_scheme 0 only", what);
   return COSMOS_OK;
 }
 
@@ -141,7 +151,9 @@ DevParams dev_params(const cosmos_grid* g, const cosmos_params* p) {
     d.i12h2[a] = 1.0 / (12.0 * h[a] * h[a]);
     d.iko[a] = p->ko_eps / (64.0 * h[a]);
     d.i24h[a] = 1.0 / (24.0 * h[a]);
+    d.ih[a] = 1.0 / h[a];
   }
+  d.fluid_scheme = p->fluid_scheme;
   d.i144[0] = 1.0 / (144.0 * h[0] * h[1]);
   d.i144[1] = 1.0 / (144.0 * h[0] * h[2]);
   d.i144[2] = 1.0 / (144.0 * h[1] * h[2]);
@@ -411,8 +423,9 @@ void launch_mode(bool lds, const Tile& T, hipStream_t s, const double* U, const 
   }
 }
 
-// Launch one stage: the flux pre-pass into F (kFluxFields x fs doubles), then the
-// stage kernel with the variant and brick chosen in the params.
+// Launch one stage: the flux pre-pass into F (kFluxFields x fs doubles: the point
+// fluxes, or with the Kurganov-Tadmor scheme the flux divergence in the first 4
+// arrays), then the stage kernel with the variant and brick chosen in the params.
 int launch_stage(const cosmos_params* p, const Tile& T, hipStream_t s, const double* U, double* F, const double* un,
                  double* acc, double* out, size_t fs, const DevParams& P, double t, double ca, double cn, int mode,
                  unsigned long long* status) {
@@ -421,7 +434,14 @@ int launch_stage(const cosmos_params* p, const Tile& T, hipStream_t s, const dou
                (T.bx == 8 && T.by == 8 && T.bz == 4) || (T.bx == 8 && T.by == 4 && T.bz == 8)))
     return set_error(COSMOS_EINVAL, "LDS-staged variant has no %dx%dx%d brick (16x4x4, 16x8x2, 8x8x4, 8x4x8)", T.bx,
                      T.by, T.bz);
-  hipLaunchKernelGGL(k_fluid_flux, dim3((unsigned)((fs + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, U, fs, P.w, F);
+  if (P.fluid_scheme == 1) {
+    const unsigned nb = (unsigned)(((P.n[0] + kKtBX - 1) / kKtBX) * ((P.n[1] + kKtBY - 1) / kKtBY) *
+                                   ((P.n[2] + kKtBZ - 1) / kKtBZ));
+    hipLaunchKernelGGL(k_fluid_kt, dim3(nb), dim3(kKtThreads), 0, s, U, fs, P, F);
+  } else {
+    hipLaunchKernelGGL(k_fluid_flux, dim3((unsigned)((fs + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, U, fs, P.w,
+                       F);
+  }
   switch (mode) {
     case 0: launch_mode<0>(lds, T, s, U, F, un, acc, out, fs, P, t, ca, cn, status); break;
     case 1: launch_mode<1>(lds, T, s, U, F, un, acc, out, fs, P, t, ca, cn, status); break;

@@ -1,0 +1,173 @@
+// Kurganov-Tadmor fluid fluxes (fluid_scheme 1): the paper's fluid scheme
+// (section "Physical system settings" cites Kurganov & Tadmor 2000 and Shibata &
+// Font 2005). The fluid right-hand side takes the conservation form
+//   d q/dt = -sum_a (Fh^a_{i+1/2} - Fh^a_{i-1/2}) / h_a + sources,
+// q = (Et, St_x, St_y, St_z), with the central numerical flux at each interface
+//   Fh = 1/2 (F^a(q_L) + F^a(q_R)) - 1/2 c (q_R - q_L),
+// q_L, q_R the minmod-limited piecewise-linear reconstructions from the two
+// sides, the geometric fields the average of the two neighbouring points, and c
+// the largest characteristic-speed magnitude of the two interface states.
+//
+// One pre-pass kernel per stage forms the whole flux divergence: a workgroup owns
+// an 8 x 8 x 4 brick, evaluates every interface flux of the brick once into LDS
+// (9x8x4 + 8x9x4 + 8x8x5 = 896 interfaces for 256 points, in three wave-aligned
+// segments of 320) and differences them.
+// The stage kernel then reads the divergence at the point itself.
+#pragma once
+#include "bssn_device.hpp"
+
+namespace cosmos {
+
+constexpr int kKtBX = 8, kKtBY = 8, kKtBZ = 4;
+constexpr int kKtNX = (kKtBX + 1) * kKtBY * kKtBZ;  // interfaces normal to x
+constexpr int kKtNY = kKtBX * (kKtBY + 1) * kKtBZ;
+constexpr int kKtNZ = kKtBX * kKtBY * (kKtBZ + 1);
+constexpr int kKtThreads = kKtBX * kKtBY * kKtBZ;  // one point per thread
+// LDS segments of the three axes, each padded to whole waves so that every wave
+// works on one axis (a compile-time constant inside the interface evaluation)
+constexpr int kKtPX = (kKtNX + 63) / 64 * 64, kKtPY = (kKtNY + 63) / 64 * 64, kKtPZ = (kKtNZ + 63) / 64 * 64;
+constexpr int kKtP = kKtPX + kKtPY + kKtPZ;
+
+// Smaller-magnitude argument when both have the same strict sign, else 0.
+__device__ __forceinline__ double minmod(double a, double b) {
+  if (a > 0.0 && b > 0.0) return a < b ? a : b;
+  if (a < 0.0 && b < 0.0) return a > b ? a : b;
+  return 0.0;
+}
+
+// Flux along axis a of one interface state (geometry g, chi, alpha, beta^a;
+// conserved q) into Fa[4]; returns the largest magnitude of the two sound-wave
+// speeds along a,
+//   lambda_pm = alpha / (1 - v^2 w) [v^a (1 - w) pm sqrt(w) sqrt((1 - v^2)(gamma^aa (1 - v^2 w)
+//               - (v^a)^2 (1 - w)))] - beta^a,
+// v^i = S^i / X, v^2 = S^2 / X^2 (a negative radicand counts as 0; a failed
+// recovery has 1/X = 0, so v = 0 there).
+template <int a>
+__device__ __forceinline__ double kt_state(double w, double sw, double chi, const double gi[6], double alpha,
+                                           double ba, const double q[4], double Fa[4]) {
+  Fluid fl;
+  recover(w, chi, gi, q[0], q + 1, fl);
+  const double im32 = 1.0 / (chi * sqrt(chi));
+  Fa[0] = im32 * (alpha * fl.Sup[a] - ba * fl.E);
+  const double t = alpha * fl.Sup[a] * fl.invX;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) Fa[1 + i] = im32 * ((t * fl.S[i] + (i == a ? alpha * fl.P : 0.0)) - ba * fl.S[i]);
+  const double S2 = fl.Sup[0] * fl.S[0] + fl.Sup[1] * fl.S[1] + fl.Sup[2] * fl.S[2];
+  const double va = fl.Sup[a] * fl.invX;
+  const double v2 = S2 * fl.invX * fl.invX;
+  const double gaa = chi * gi[S(a, a)];
+  double rad = (1.0 - v2) * (gaa * (1.0 - v2 * w) - va * va * (1.0 - w));
+  const double root = rad > 0.0 ? sqrt(rad) : 0.0;
+  const double f = alpha / (1.0 - v2 * w);
+  const double lp = f * (va * (1.0 - w) + sw * root) - ba;
+  const double lm = f * (va * (1.0 - w) - sw * root) - ba;
+  return fmax(fabs(lm), fabs(lp));
+}
+
+// Periodic wrap of a coordinate in [-2, 2n] (n >= 8, so one or two corrections).
+__device__ __forceinline__ int kt_wrap(int x, int n) {
+  x += x < 0 ? n : 0;
+  x -= x >= n ? n : 0;
+  x -= x >= n ? n : 0;
+  return x;
+}
+
+// Numerical flux through the interface between points g - e_a and g (global
+// coordinates gx, gy, gz of g, unwrapped) into fh[4].
+template <int a>
+__device__ __forceinline__ void kt_interface(const double* U, size_t fs, const DevParams& P, double sw, int gx, int gy,
+                                             int gz, double fh[4]) {
+  const int n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
+  int idx[4];  // points g-2, g-1, g, g+1 along a
+#pragma unroll
+  for (int o = 0; o < 4; ++o) {
+    const int x = kt_wrap(gx + (a == 0 ? o - 2 : 0), n0);
+    const int y = kt_wrap(gy + (a == 1 ? o - 2 : 0), n1);
+    const int z = kt_wrap(gz + (a == 2 ? o - 2 : 0), n2);
+    idx[o] = x + n0 * (y + n1 * z);
+  }
+  const uint32_t nbytes = (uint32_t)(fs * 8);
+  auto ld = [&](int f, int o) { return bld(field_ptr(U, f, fs), nbytes, (uint32_t)idx[o] * 8u); };
+  // geometry at the interface: average of the two neighbours
+  double g[6], gi[6];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) g[s] = 0.5 * (ld(F_GT + s, 1) + ld(F_GT + s, 2));
+  const double chi = 0.5 * (ld(F_CHI, 1) + ld(F_CHI, 2));
+  const double alpha = 0.5 * (ld(F_ALP, 1) + ld(F_ALP, 2));
+  const double ba = 0.5 * (ld(F_BET + a, 1) + ld(F_BET + a, 2));
+  inv_sym(g, gi);
+  // fluid: minmod-limited linear reconstruction from both sides
+  double qL[4], qR[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const double vm = ld(F_ET + q, 0), v0 = ld(F_ET + q, 1), v1 = ld(F_ET + q, 2), v2 = ld(F_ET + q, 3);
+    qL[q] = v0 + 0.5 * minmod(v0 - vm, v1 - v0);
+    qR[q] = v1 - 0.5 * minmod(v1 - v0, v2 - v1);
+  }
+  double FL[4], FR[4];
+  const double cL = kt_state<a>(P.w, sw, chi, gi, alpha, ba, qL, FL);
+  const double cR = kt_state<a>(P.w, sw, chi, gi, alpha, ba, qR, FR);
+  const double c = fmax(cL, cR);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) fh[q] = 0.5 * (FL[q] + FR[q]) - 0.5 * c * (qR[q] - qL[q]);
+}
+
+// Brick b of the 8 x 8 x 4 decomposition for workgroup v: with nbricks a multiple
+// of 8 the bricks are cut into 8 contiguous chunks, chunk q served by the
+// workgroups v % 8 == q (one XCD each), so neighbouring bricks share an L2.
+__device__ __forceinline__ int kt_brick(int v, int nbricks) {
+  if (nbricks % 8) return v;
+  return (v % 8) * (nbricks / 8) + v / 8;
+}
+
+// Interface e of axis a's segment: the brick-local coordinates of the point on
+// its + side (extent B_a + 1 along a), then the numerical flux into fh[q][slot].
+template <int a>
+__device__ __forceinline__ void kt_segment(const double* U, size_t fs, const DevParams& P, double sw, int e, int slot,
+                                           int ox, int oy, int oz, double (*fh)[kKtP]) {
+  constexpr int EX = kKtBX + (a == 0), EY = kKtBY + (a == 1);
+  const int li = e % EX, lj = (e / EX) % EY, lk = e / (EX * EY);
+  double f[4];
+  kt_interface<a>(U, fs, P, sw, ox + li, oy + lj, oz + lk, f);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) fh[q][slot] = f[q];
+}
+
+// D[q fs + c] = sum_a (Fh^a_q(c + 1/2) - Fh^a_q(c - 1/2)) / h_a for q = 0..3.
+__global__ __launch_bounds__(kKtThreads) void k_fluid_kt(const double* U, size_t fs, DevParams P, double* D) {
+  __shared__ double fh[4][kKtP];
+  const int nbx = (P.n[0] + kKtBX - 1) / kKtBX, nby = (P.n[1] + kKtBY - 1) / kKtBY;
+  const int nbz = (P.n[2] + kKtBZ - 1) / kKtBZ;
+  const int b = kt_brick(blockIdx.x, nbx * nby * nbz);
+  const int ox = (b % nbx) * kKtBX, oy = ((b / nbx) % nby) * kKtBY, oz = (b / (nbx * nby)) * kKtBZ;
+  const double sw = sqrt(P.w);
+  for (int t = threadIdx.x; t < kKtP; t += kKtThreads) {
+    // the segments are whole waves: the axis is uniform over the wave
+    const int a = __builtin_amdgcn_readfirstlane(t < kKtPX ? 0 : (t < kKtPX + kKtPY ? 1 : 2));
+    if (a == 0) {
+      if (t < kKtNX) kt_segment<0>(U, fs, P, sw, t, t, ox, oy, oz, fh);
+    } else if (a == 1) {
+      if (t - kKtPX < kKtNY) kt_segment<1>(U, fs, P, sw, t - kKtPX, t, ox, oy, oz, fh);
+    } else {
+      if (t - kKtPX - kKtPY < kKtNZ) kt_segment<2>(U, fs, P, sw, t - kKtPX - kKtPY, t, ox, oy, oz, fh);
+    }
+  }
+  __syncthreads();
+  const int li = threadIdx.x % kKtBX, lj = (threadIdx.x / kKtBX) % kKtBY, lk = threadIdx.x / (kKtBX * kKtBY);
+  const int x = ox + li, y = oy + lj, z = oz + lk;
+  if (x >= P.n[0] || y >= P.n[1] || z >= P.n[2]) return;
+  // interface slots: the one at the point's minus side and the next along each axis
+  const int sx = li + (kKtBX + 1) * (lj + kKtBY * lk);
+  const int sy = kKtPX + li + kKtBX * (lj + (kKtBY + 1) * lk);
+  const int sz = kKtPX + kKtPY + li + kKtBX * (lj + kKtBY * lk);
+  const size_t c = (size_t)x + (size_t)P.n[0] * ((size_t)y + (size_t)P.n[1] * z);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    double div = (fh[q][sx + 1] - fh[q][sx]) * P.ih[0];
+    div += (fh[q][sy + kKtBX] - fh[q][sy]) * P.ih[1];
+    div += (fh[q][sz + kKtBX * kKtBY] - fh[q][sz]) * P.ih[2];
+    D[q * fs + c] = div;
+  }
+}
+
+}  // namespace cosmos

@@ -58,9 +58,19 @@ def test_invalid_arguments_rejected_on_host(C):
     assert rc == C.COSMOS_EINVAL and "dt" in C.last_error()
     rc = lib.cosmos_rk4_step(ctypes.byref(g), ctypes.byref(p), 0.0, 0.1, ctypes.c_void_p(0x100004), fake, None)
     assert rc == C.COSMOS_EINVAL and "aligned" in C.last_error()
-    q = C.make_params(fluid_scheme=1)
+    q = C.make_params(fluid_scheme=2)
     rc = lib.cosmos_rk4_step(ctypes.byref(g), ctypes.byref(q), 0.0, 0.1, fake, fake, None)
     assert rc == C.COSMOS_EUNSUPPORTED
+    # the Kurganov-Tadmor scheme (1) runs in the plain entry points; the adjoint and the
+    # batched form implement the centred scheme only
+    kt = C.make_params(fluid_scheme=1)
+    rc = lib.cosmos_adjoint_step(ctypes.byref(g), ctypes.byref(kt), 0.0, 0.1, fake, fake, fake, fake, None)
+    assert rc == C.COSMOS_EUNSUPPORTED and "adjoint" in C.last_error()
+    rc = lib.cosmos_rhs_vjp(ctypes.byref(g), ctypes.byref(kt), 0.0, fake, fake, fake, fake, None)
+    assert rc == C.COSMOS_EUNSUPPORTED
+    b = C.make_batch([16, 32], [4.0, 8.0], [0, 25 * 16 ** 3])
+    rc = lib.cosmos_batch_setup(ctypes.byref(b), ctypes.byref(kt), fake, None)
+    assert rc == C.COSMOS_EUNSUPPORTED and "batched" in C.last_error()
     ini = C.make_init(sigma=0.0)
     rc = lib.cosmos_init_fields(ctypes.byref(g), ctypes.byref(p), ctypes.byref(ini), fake, None)
     assert rc == C.COSMOS_EINVAL
