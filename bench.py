@@ -7,11 +7,12 @@ One step = one classic RK4 step = 4 stages, each a pointwise flux pre-pass
 Prints one JSON line with the roofline of a stage (algorithmic bytes per stage /
 average stage time, measured with HIP events on the launch stream around the
 timed steps), the CPU oracle timed on a bounded sample of the same workload, and
-the two other forms of the metric as sub-objects: "batched" (runs/s of the
-64-run scan) and "adjoint" (cost of the gradient relative to the forward run).
+the other forms of the metric as sub-objects: "batched" (runs/s of the 64-run
+scan), "adjoint" (cost of the gradient relative to the forward run) and "kt" (the
+headline workload with the Kurganov-Tadmor fluid scheme).
 
 Extra modes:
-  --headline-only  skip the batched and adjoint sub-objects
+  --headline-only  skip the batched, adjoint and kt sub-objects
   --batched      only the 64-run threshold-scan workload (grid sizes drawn from
                  {48, 64, 80, 96}^3, mu in [0.3, 0.8], sigma in [0.8, 1.6], box 12/H0,
                  300 RK4 steps per run): runs/s of the batched, hipGraph-replayed form
@@ -23,6 +24,8 @@ Extra modes:
   --threshold    only the threshold search (32^3, box 12/H0, sigma = 1.2, 100 RK4 steps):
                  batched multisection + Newton with the adjoint derivative for the amplitude
                  whose centre lapse equals that of mu = 0.4371, against serial bisection
+  --kt           only the headline workload with the Kurganov-Tadmor fluid scheme
+                 (fluid_scheme 1), against the centred scheme on the same configuration
   --copy-probe   only a plain device-to-device copy of known size (calibrates
                  rocprofv3 FETCH_SIZE / WRITE_SIZE counters)
   --no-cpu       skip the CPU baseline leg
@@ -68,10 +71,11 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-tune", action="store_true", help="use the default tile instead of the autotuned one")
     ap.add_argument("--batched", action="store_true")
-    ap.add_argument("--headline-only", action="store_true", help="no batched / adjoint sub-objects")
+    ap.add_argument("--headline-only", action="store_true", help="no batched / adjoint / kt sub-objects")
     ap.add_argument("--batched-steps", type=int, default=30, help="timed steps (runs/s is scaled to 300 steps)")
     ap.add_argument("--adjoint", action="store_true")
     ap.add_argument("--threshold", action="store_true")
+    ap.add_argument("--kt", action="store_true", help="only the Kurganov-Tadmor fluid-scheme leg")
     ap.add_argument("--adjoint-steps", type=int, default=200, help="RK4 steps of the differentiated run")
     ap.add_argument("--no-fd", action="store_true", help="skip the finite-difference check of the adjoint")
     ap.add_argument("--config", default=None,
@@ -126,13 +130,16 @@ def copy_probe():
     print(json.dumps({"copy_probe_bytes_read": nbytes, "copy_probe_bytes_written": nbytes, "launches": 5}))
 
 
+def op_counts():
+    """Algorithmic FP64 operation counts (tests/golden/op_counts.json, written from the
+    oracle's operation-counting scalar by tests/golden/make_golden.py):
+    step_per_point (one RK4 step, centred scheme) and kt_prepass_per_point."""
+    with open(os.path.join(HERE, "tests", "golden", "op_counts.json")) as f:
+        return json.load(f)
+
+
 def flops_per_point_step():
-    """Algorithmic FLOPs of one RK4 step per grid point, counted by the oracle's
-    operation-counting scalar on a small state (the count is data independent)."""
-    import oracle
-    from tests.inputs import fuzz_state
-    s = oracle.Setup(n=(8, 8, 8), L=(2.4, 2.4, 2.4))
-    return oracle.count_flops(s, fuzz_state(s.n, seed=1))["step_per_point"]
+    return op_counts()["step_per_point"]
 
 
 def cpu_baseline(n_steps: int):
@@ -198,6 +205,71 @@ def batched_bench(a):
            "config": {"workload": "64 runs, n from {48,64,80,96} (numpy default_rng(2606)), mu U[0.3,0.8], "
                                   "sigma U[0.8,1.6], L = 12/H0, CFL 0.25, hipGraph-replayed RK4 steps"}}
     return out
+
+
+def kt_bench(a, kv=0, tile=(16, 4, 4), order=2):
+    """The headline workload with the Kurganov-Tadmor fluid scheme (fluid_scheme 1): RK4
+    steps per second on 256^3, each stage a k_fluid_kt pre-pass (interface fluxes and their
+    divergence) plus the stage kernel; timed like the headline, on the same kernel
+    configuration, against the centred scheme measured back to back."""
+    import paper_2606_02053_amd as P
+    from paper_2606_02053_amd import autotune
+    n, L = a.n, 16.0
+    ms = {}
+    for scheme in (1, 0):
+        sol = P.Solver(n, L, autotune.with_tile(P.make_params(fluid_scheme=scheme), kv, tile, order))
+        sol.init(mu=0.6, sigma=2.0)
+        dt = sol.default_dt()
+        for _ in range(a.warmup):
+            sol.step(dt)
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(a.steps):
+            sol.step(dt)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms[scheme] = e0.elapsed_time(e1) / a.steps
+        st = sol.status()
+        if st["nonfinite"] or st["prim_fail"]:
+            raise RuntimeError(f"KT benchmark run (scheme {scheme}) went bad: {st}")
+        del sol
+    # the pre-pass alone (cosmos_kt_divergence: one k_fluid_kt launch), timed with HIP events
+    # on the launch stream; algorithmic bytes: 15 fields read + 4 written per point
+    g = P.make_grid(n, L)
+    u = torch.empty((25, n, n, n), dtype=torch.float64, device="cuda")
+    P.cosmos_init_fields(g, P.make_params(), P.make_init(mu=0.6, sigma=2.0), u)
+    div = torch.empty((4, n, n, n), dtype=torch.float64, device="cuda")
+    kp = P.make_params(fluid_scheme=1)
+    for _ in range(3):
+        P.cosmos_kt_divergence(g, kp, u, div)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 4 * a.steps
+    e0.record(stream)
+    for _ in range(reps):
+        P.cosmos_kt_divergence(g, kp, u, div)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    pre_s = e0.elapsed_time(e1) / 1e3 / reps
+    flops = op_counts()["kt_prepass_per_point"] * n ** 3
+    byts = 19 * 8 * n ** 3
+    del u, div
+    roof = {"bound": "alu", "achieved": round(flops / pre_s / 1e12, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(flops / pre_s / 1e12 / FP64_PEAK_TFLOPS, 4), "traffic": None,
+            "kernel": "k_fluid_kt (interface fluxes + divergence, one launch per stage)",
+            "avg_launch_ms": round(pre_s * 1e3, 4), "algorithmic_flops_per_launch": round(flops),
+            "algorithmic_bytes_per_launch": byts, "hbm_achieved_gbs": round(byts / pre_s / 1e9, 1),
+            "hbm_frac": round(byts / pre_s / 1e9 / HBM_PEAK_GBS, 4)}
+    return {"metric": "grid-point RK4 updates/sec FP64 at 256^3, Kurganov-Tadmor fluid fluxes",
+            "value": n ** 3 / (ms[1] / 1e3), "unit": "point-updates/s", "ms_per_step": ms[1],
+            "centred_ms_per_step": ms[0], "cost_vs_centred": ms[1] / ms[0], "steps": a.steps, "roofline": roof,
+            "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"as the headline ({n}^3, L = 16/H0, mu = 0.6, sigma = 2.0, CFL 0.25) with "
+                                   "fluid_scheme 1 (minmod reconstruction, characteristic-speed bound, no KO on "
+                                   "the fluid)", "kernel_config": config_name(kv, tile, order)}}
 
 
 def adjoint_bench(a):
@@ -302,6 +374,10 @@ def main():
     if a.threshold:
         print(json.dumps(threshold_bench(a)), flush=True)
         return
+    if a.kt:
+        kv, tile, order = parse_config(a.config) if a.config else (0, (16, 4, 4), 2)
+        print(json.dumps(kt_bench(a, kv, tile, order)), flush=True)
+        return
     import paper_2606_02053_amd as P
     from paper_2606_02053_amd import autotune
     n, L = a.n, 16.0
@@ -356,6 +432,7 @@ def main():
     if not a.headline_only:
         out["batched"] = batched_bench(a)
         out["adjoint"] = adjoint_bench(a)
+        out["kt"] = kt_bench(a, kv, tile, order)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(a.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -126,7 +126,8 @@ typedef struct {
 
 /* Bytes of device workspace needed by cosmos_rhs / cosmos_rk4_step / cosmos_constraints on this
  * grid: the status counters, the reduction partials, 3 state-sized RK4 buffers and 12 * N3
- * doubles for the fluid fluxes that every stage forms in a pre-pass (the point fluxes; with fluid_scheme 1 the first 4 * N3 hold the Kurganov-Tadmor flux divergence). Returns 0 for an
+ * doubles for the fluid fluxes that every stage forms in a pre-pass (the point fluxes; with
+ * fluid_scheme 1 the first 4 * N3 hold the Kurganov-Tadmor flux divergence). Returns 0 for an
  * invalid grid. */
 size_t cosmos_workspace_bytes(const cosmos_grid* grid);
 
@@ -154,12 +155,23 @@ int cosmos_init_tangent(const cosmos_grid* grid, const cosmos_params* params, co
 
 /* Discrete right-hand side du/dt at time t (dudt: 25 * N3 values, must not alias u):
  * BSSN chi-form evolution equations with 1+log lapse and Gamma-driver shift, perfect-fluid
- * sources and conservative fluid equations (Et, St_i) with a centred flux divergence, all
- * derivatives by 4th-order centred differences, shift advection beta^k d_k by lopsided
- * radius-3 stencils chosen by the sign of beta^k, plus Kreiss-Oliger dissipation on every
- * evolved field; periodic ghost zones of width 3. ws is used for the status counters. */
+ * sources and conservative fluid equations (Et, St_i) with a centred flux divergence (or the
+ * Kurganov-Tadmor fluxes, fluid_scheme 1), all derivatives by 4th-order centred differences,
+ * shift advection beta^k d_k by lopsided radius-3 stencils chosen by the sign of beta^k, plus
+ * Kreiss-Oliger dissipation on every evolved field (on the geometric fields only with
+ * fluid_scheme 1); periodic ghost zones of width 3. ws is used for the status counters. */
 int cosmos_rhs(const cosmos_grid* grid, const cosmos_params* params, double t, const double* u,
                double* dudt, void* ws, void* stream);
+
+/* Kurganov-Tadmor flux divergence of the fluid alone (the pre-pass of every stage with
+ * fluid_scheme 1; "Physical system settings" names Kurganov & Tadmor 2000 for the fluid):
+ * div[q * N3 + p] = sum_a (Fh^a_q(p + 1/2) - Fh^a_q(p - 1/2)) / h_a for q = Et, St_x, St_y, St_z,
+ * Fh the numerical interface flux described under fluid_scheme above (params.fluid_scheme itself
+ * is not consulted). u: 25 * N3 device values; div: 4 * N3 device values owned by the caller,
+ * not overlapping u. Asynchronous on `stream`; no workspace. Errors: COSMOS_EINVAL for an invalid
+ * grid, NULL, misaligned or overlapping pointers. */
+int cosmos_kt_divergence(const cosmos_grid* grid, const cosmos_params* params, const double* u, double* div,
+                         void* stream);
 
 /* One classic RK4 step of size dt from time t, in place on u:
  * u <- u + dt/6 (k1 + 2 k2 + 2 k3 + k4). The stage update is fused into the right-hand-side

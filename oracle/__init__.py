@@ -82,6 +82,8 @@ def lib():
             "oracle_matter_point": [f64, f64, P, f64, P, P],
             "oracle_flux_point": [P, P, P],
             "oracle_kt_flux": [P, P, P, i32, P],
+            "oracle_kt_divergence": [P, P, P, P, P, P],
+            "oracle_count_kt_flops": [P, P, P, P, P, P],
             "oracle_fluid_speeds": [P, P, i32, P],
             "oracle_splitmix64": [u64, u64],
             "oracle_stencil": [P, P, P, i32, i32, i32, i32, i32, i32, P, f64, P],
@@ -319,6 +321,24 @@ def kt_flux(s: Setup, uL, uR, a: int) -> np.ndarray:
     out = np.empty(4)
     _check(lib().oracle_kt_flux(_p(prm), _p(uL), _p(uR), a, _p(out)), "oracle_kt_flux")
     return out
+
+
+def kt_divergence(s: Setup, u) -> np.ndarray:
+    """Kurganov-Tadmor flux divergence of (Et, St_x, St_y, St_z), shape (4, nz, ny, nx)."""
+    n, L, prm, iprm = s.arrays()
+    u = _state(u, s)
+    out = np.empty((4,) + s.shape[1:])
+    _check(lib().oracle_kt_divergence(_p(n), _p(L), _p(prm), _p(iprm), _p(u), _p(out)), "oracle_kt_divergence")
+    return out
+
+
+def count_kt_flops(s: Setup, u) -> dict:
+    """Operations of one Kurganov-Tadmor interface flux (the count depends on the limiter branches)."""
+    n, L, prm, iprm = s.arrays()
+    u = _state(u, s)
+    out = np.empty(3)
+    _check(lib().oracle_count_kt_flops(_p(n), _p(L), _p(prm), _p(iprm), _p(u), _p(out)), "oracle_count_kt_flops")
+    return {"flops_per_interface": out[0], "sqrt_per_interface": out[1], "oracle_flops_per_interface": out[2]}
 
 
 def fluid_speeds(s: Setup, u25, a: int) -> tuple:

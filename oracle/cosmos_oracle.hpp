@@ -368,7 +368,8 @@ struct Matter {
 };
 
 template <class T>
-bool matter(const Params& p, T chi, const T gt[6], const T gi[6], T Et, const T St[3], Matter<T>& M) {
+bool matter(const Params& p, T chi, const T gt[6], const T gi[6], T Et, const T St[3], Matter<T>& M,
+            bool want_stress = true) {
   bool fail = false;
   T c32 = chi * sqrt(chi);
   M.E = c32 * Et;
@@ -398,6 +399,7 @@ bool matter(const Params& p, T chi, const T gt[6], const T gi[6], T Et, const T 
     for (int k = 0; k < 3; ++k) acc = acc + gi[SYM[j][k]] * M.S[k];
     M.Sup[j] = chi * acc;
   }
+  if (!want_stress) return fail;  // fluxes and speeds need E, S_i, S^i, S^2, P, 1/X only
   for (int s = 0; s < 6; ++s) {
     int i = SI[s], j = SJ[s];
     M.Sij[s] = M.S[i] * M.S[j] * M.invX + M.P * gt[s] / chi;
@@ -421,7 +423,7 @@ void fluid_flux(const Params& p, const T u[NF], T out[12]) {
     beta[i] = u[BET + i];
   }
   Matter<T> M;
-  matter(p, u[CHI], gt, gi, u[ET], St, M);
+  matter(p, u[CHI], gt, gi, u[ET], St, M, false);
   T chi = u[CHI];
   T im32 = T(1.0) / (chi * sqrt(chi));
   T alpha = u[ALP];
@@ -470,7 +472,7 @@ void fluid_speeds(const Params& p, const T u[NF], int a, T& lm, T& lp) {
   inverse_sym(gt, gi, det);
   for (int i = 0; i < 3; ++i) St[i] = u[ST + i];
   Matter<T> M;
-  matter(p, u[CHI], gt, gi, u[ET], St, M);
+  matter(p, u[CHI], gt, gi, u[ET], St, M, false);
   const T cs2 = T(p.w);
   const T cs = sqrt(cs2);
   const T va = M.Sup[a] * M.invX;
@@ -774,6 +776,33 @@ void rhs(const Grid& g, const Params& p, double t, const T* u, T* dudt, Status& 
   const int o[3] = {0, 0, 0};
   pad_periodic(g, u, o, g.n, P);
   rhs_padded(g, p, t, P, dudt, st, parallel);
+}
+
+// Kurganov-Tadmor flux divergence alone on the whole periodic grid:
+// div[q][p] = sum_a (Fh^a_q(p + 1/2) - Fh^a_q(p - 1/2)) / h_a, q = Et, St_x, St_y, St_z
+// (the term the fluid right-hand side subtracts with fluid_scheme 1).
+inline void kt_divergence(const Grid& g, const Params& p, const double* u, double* div) {
+  Padded<double> P;
+  const int o[3] = {0, 0, 0};
+  pad_periodic(g, u, o, g.n, P);
+  const int64_t N3 = g.npts();
+  for (int k = 0; k < g.n[2]; ++k)
+    for (int j = 0; j < g.n[1]; ++j)
+      for (int i = 0; i < g.n[0]; ++i) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int a = 0; a < 3; ++a) {
+          int d[3] = {0, 0, 0};
+          d[a] = -1;
+          double uL[NF], uR[NF], fp[4], fm[4];
+          kt_interface_states<double>(P, i, j, k, a, uL, uR);
+          kt_flux(p, uL, uR, a, fp);
+          kt_interface_states<double>(P, i + d[0], j + d[1], k + d[2], a, uL, uR);
+          kt_flux(p, uL, uR, a, fm);
+          for (int q = 0; q < 4; ++q) acc[q] = acc[q] + (fp[q] - fm[q]) * (1.0 / g.h(a));
+        }
+        const int64_t c = i + (int64_t)g.n[0] * (j + (int64_t)g.n[1] * k);
+        for (int q = 0; q < 4; ++q) div[q * N3 + c] = acc[q];
+      }
 }
 
 // ------------------------------------------------------------------ RK4

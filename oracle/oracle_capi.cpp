@@ -63,6 +63,51 @@ int oracle_rhs(const int* n, const double* L, const double* prm, const int* iprm
   return 0;
 }
 
+int oracle_kt_divergence(const int* n, const double* L, const double* prm, const int* iprm, const double* u,
+                         double* div) {
+  Grid g;
+  Params p;
+  if (!make(n, L, prm, iprm, g, p) || !u || !div) return -1;
+  kt_divergence(g, p, u, div);
+  return 0;
+}
+
+// Operation count of one Kurganov-Tadmor interface flux (reconstruction, two flux and
+// speed evaluations, combination) at the interface x+1/2 of point 0 of the state u.
+int oracle_count_kt_flops(const int* n, const double* L, const double* prm, const int* iprm, const double* u,
+                          double* out) {
+  Grid g;
+  Params p;
+  if (!make(n, L, prm, iprm, g, p) || !u || !out) return -1;
+  const int64_t N3 = g.npts();
+  Padded<Cnt> P;
+  const int o[3] = {0, 0, 0}, m[3] = {1, 1, 1};
+  std::vector<Cnt> x((size_t)NF * N3);
+  for (size_t q = 0; q < x.size(); ++q) x[q] = Cnt(u[q]);
+  pad_periodic(g, x.data(), o, m, P);
+  g_count = OpCount();
+  Cnt uL[NF], uR[NF], fh[4];
+  kt_interface_states<Cnt>(P, 0, 0, 0, 0, uL, uR);
+  kt_flux(p, uL, uR, 0, fh);
+  const OpCount total = g_count;
+  // the speed evaluation repeats the inverse metric and the recovery that the flux of
+  // the same state has formed: counted once
+  g_count = OpCount();
+  {
+    Cnt gt[6], gi[6], det, St[3];
+    for (int s = 0; s < 6; ++s) gt[s] = uL[GT + s];
+    inverse_sym(gt, gi, det);
+    for (int i = 0; i < 3; ++i) St[i] = uL[ST + i];
+    Matter<Cnt> M;
+    matter(p, uL[CHI], gt, gi, uL[ET], St, M, false);
+  }
+  const OpCount dup = g_count;
+  out[0] = (double)(total.flops() - 2 * dup.flops());
+  out[1] = (double)(total.sqrt - 2 * dup.sqrt);
+  out[2] = (double)total.flops();
+  return 0;
+}
+
 int oracle_rk4_steps(const int* n, const double* L, const double* prm, const int* iprm, double t0, double dt,
                      int nsteps, double* u, int64_t* prim_fail, int parallel) {
   Grid g;

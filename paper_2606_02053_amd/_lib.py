@@ -63,6 +63,7 @@ def _load():
         "cosmos_init_fields": ([G, Pr, In, P, P], i32),
         "cosmos_init_tangent": ([G, Pr, In, i32, P, P], i32),
         "cosmos_rhs": ([G, Pr, f64, P, P, P, P], i32),
+        "cosmos_kt_divergence": ([G, Pr, P, P, P], i32),
         "cosmos_rk4_step": ([G, Pr, f64, f64, P, P, P], i32),
         "cosmos_rk4_step_stages": ([G, Pr, f64, f64, P, P, P, P], i32),
         "cosmos_constraints": ([G, Pr, P, P, P, P, P, P], i32),
@@ -176,6 +177,12 @@ def cosmos_rhs(grid, params, t: float, u, dudt, ws, stream=None):
     N = NFIELDS * npts(grid)
     _check(lib.cosmos_rhs(ctypes.byref(grid), ctypes.byref(params), float(t), _dev(u, "u", N),
                           _dev(dudt, "dudt", N), _dev(ws, "ws", dtype=torch.uint8), _stream(stream)))
+
+
+def cosmos_kt_divergence(grid, params, u, div, stream=None):
+    n = npts(grid)
+    _check(lib.cosmos_kt_divergence(ctypes.byref(grid), ctypes.byref(params), _dev(u, "u", NFIELDS * n),
+                                    _dev(div, "div", 4 * n), _stream(stream)))
 
 
 def cosmos_rk4_step(grid, params, t: float, dt: float, u, ws, stream=None):

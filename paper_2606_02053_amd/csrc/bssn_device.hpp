@@ -400,8 +400,8 @@ __device__ __forceinline__ void flux_var_load(const double* F, size_t fs, int c,
   }
 }
 
-__device__ __forceinline__ double flux_var_div(const double v[3][4], const DevParams& P) {
-  if (P.fluid_scheme == 1) return v[0][0];
+__device__ __forceinline__ double flux_var_div(const double v[3][4], const DevParams& P, bool kt) {
+  if (kt) return v[0][0];
   double div = 0.0;
 #pragma unroll
   for (int a = 0; a < 3; ++a) div += ((v[a][0] - v[a][3]) + 8.0 * (v[a][2] - v[a][1])) * P.i12h[a];

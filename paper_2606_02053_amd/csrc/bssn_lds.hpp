@@ -224,7 +224,7 @@ __device__ __forceinline__ void lds_carry_fill(LdsCarry<B, Pre>& cy, const doubl
 // whose point lies inside the grid. On entry `cy` holds this brick's ring,
 // epilogue operands and point values; if nx.valid, on return it holds those of
 // the next brick (loaded during the last phases of this one).
-template <class B, class Sink, class Pre>
+template <class B, bool KT, class Sink, class Pre>
 __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, size_t fs, const DevParams& P, double t,
                                              int c, bool active, LdsCarry<B, Pre>& cy, const NextBrick<B>& nx,
                                              double* buf0, double* buf1, Sink& sink, bool& prim_fail) {
@@ -537,7 +537,7 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
   // completes its right-hand side (q = 0 in At phase 4, 1 in At phase 5, 2 in the
   // Et phase, 3 in the first St phase), so their latency overlaps the algebra.
   double fa[3][4], fb[3][4];
-  const bool kt = P.fluid_scheme == 1;  // divergence formed by the Kurganov-Tadmor pre-pass
+  constexpr bool kt = KT;  // divergence formed by the Kurganov-Tadmor pre-pass
   Nbr fnb;
   if (active) {
     const int i = c % P.n[0], jk = c / P.n[0], j = jk % P.n[1], k = jk / P.n[1];
@@ -588,7 +588,7 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
   double sgt = 0.0;  // S^jk gt_jk (formed in the Et phase, used by the St phases)
   prefetch();
   if (active) {
-    const double div0 = flux_var_div(fa, P);
+    const double div0 = flux_var_div(fa, P, kt);
     flux_var_load(F, fs, c, fnb, 2, fa, kt);
     double KS = 0.0;
 #pragma unroll
@@ -615,10 +615,10 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
       // St_0: q = 1 (loaded in At phase 5), then issue q = 3; St_1: q = 2; St_2: q = 3
       double divi;
       if (i == 0) {
-        divi = flux_var_div(fb, P);
+        divi = flux_var_div(fb, P, kt);
         flux_var_load(F, fs, c, fnb, 3, fb, kt);
       } else {
-        divi = flux_var_div(i == 1 ? fa : fb, P);
+        divi = flux_var_div(i == 1 ? fa : fb, P, kt);
       }
       FieldDerivs d;
       lds_derivs<B, false, false>(cur(), P, nbeta, d);

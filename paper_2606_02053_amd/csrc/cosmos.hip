@@ -248,7 +248,7 @@ __global__ __launch_bounds__(kBlock) void k_bssn_stage(const double* U, const do
 // it * gridDim.x (gridDim.x a multiple of 8, so with the XCD-aware order every
 // brick of a workgroup lies in its XCD's slab), prefetching each next brick
 // during the last phases of the current one.
-template <int BX, int BY, int BZ, int MODE>
+template <int BX, int BY, int BZ, int MODE, bool KT>
 __global__ __launch_bounds__(kBlock) void k_bssn_stage_lds(const double* U, const double* F, const double* un,
                                                             double* acc, double* out, size_t fs, DevParams P, Tile T,
                                                             double t, double ca, double cn,
@@ -314,7 +314,7 @@ __global__ __launch_bounds__(kBlock) void k_bssn_stage_lds(const double* U, cons
     if (nx.valid) HaloCopy<B>::offsets(ni0, nj0, nk0, P.n, nx.goffb);
     Sink sink{un, acc, out, fs, c, ca, cn, P.alpha_collapse};
     bool fail = false;
-    bssn_rhs_lds<B>(U, F, fs, P, t, c, active, cy, nx, smem, smem + B::NP, sink, fail);
+    bssn_rhs_lds<B, KT>(U, F, fs, P, t, c, active, cy, nx, smem, smem + B::NP, sink, fail);
     if (active) {
       nfail += fail;
       if constexpr (MODE == 3) {
@@ -405,6 +405,23 @@ void launch_persistent(K kernel, const Tile& T0, hipStream_t s, const double* U,
   hipLaunchKernelGGL(kernel, dim3(grid), dim3(kBlock), 0, s, U, F, un, acc, out, fs, P, T, t, ca, cn, status);
 }
 
+// KT: the LDS-staged kernel is instantiated per fluid scheme, so the centred
+// scheme's code carries no trace of the other; the direct kernel tests it at run time.
+template <int M, bool KT>
+void launch_lds(const Tile& T, hipStream_t s, const double* U, const double* F, const double* un, double* acc,
+                double* out, size_t fs, const DevParams& P, double t, double ca, double cn,
+                unsigned long long* status) {
+  if (T.bx == 16 && T.by == 4) {
+    launch_persistent(k_bssn_stage_lds<16, 4, 4, M, KT>, T, s, U, F, un, acc, out, fs, P, t, ca, cn, status);
+  } else if (T.bx == 16) {
+    launch_persistent(k_bssn_stage_lds<16, 8, 2, M, KT>, T, s, U, F, un, acc, out, fs, P, t, ca, cn, status);
+  } else if (T.by == 8) {
+    launch_persistent(k_bssn_stage_lds<8, 8, 4, M, KT>, T, s, U, F, un, acc, out, fs, P, t, ca, cn, status);
+  } else {
+    launch_persistent(k_bssn_stage_lds<8, 4, 8, M, KT>, T, s, U, F, un, acc, out, fs, P, t, ca, cn, status);
+  }
+}
+
 template <int M>
 void launch_mode(bool lds, const Tile& T, hipStream_t s, const double* U, const double* F, const double* un,
                  double* acc, double* out, size_t fs, const DevParams& P, double t, double ca, double cn,
@@ -412,14 +429,10 @@ void launch_mode(bool lds, const Tile& T, hipStream_t s, const double* U, const 
   if (!lds) {
     const dim3 g(tile_blocks(T)), b(kBlock);
     hipLaunchKernelGGL(k_bssn_stage<M>, g, b, 0, s, U, F, un, acc, out, fs, P, T, t, ca, cn, status);
-  } else if (T.bx == 16 && T.by == 4) {
-    launch_persistent(k_bssn_stage_lds<16, 4, 4, M>, T, s, U, F, un, acc, out, fs, P, t, ca, cn, status);
-  } else if (T.bx == 16) {
-    launch_persistent(k_bssn_stage_lds<16, 8, 2, M>, T, s, U, F, un, acc, out, fs, P, t, ca, cn, status);
-  } else if (T.by == 8) {
-    launch_persistent(k_bssn_stage_lds<8, 8, 4, M>, T, s, U, F, un, acc, out, fs, P, t, ca, cn, status);
+  } else if (P.fluid_scheme == 1) {
+    launch_lds<M, true>(T, s, U, F, un, acc, out, fs, P, t, ca, cn, status);
   } else {
-    launch_persistent(k_bssn_stage_lds<8, 4, 8, M>, T, s, U, F, un, acc, out, fs, P, t, ca, cn, status);
+    launch_lds<M, false>(T, s, U, F, un, acc, out, fs, P, t, ca, cn, status);
   }
 }
 
@@ -435,9 +448,7 @@ int launch_stage(const cosmos_params* p, const Tile& T, hipStream_t s, const dou
     return set_error(COSMOS_EINVAL, "LDS-staged variant has no %dx%dx%d brick (16x4x4, 16x8x2, 8x8x4, 8x4x8)", T.bx,
                      T.by, T.bz);
   if (P.fluid_scheme == 1) {
-    const unsigned nb = (unsigned)(((P.n[0] + kKtBX - 1) / kKtBX) * ((P.n[1] + kKtBY - 1) / kKtBY) *
-                                   ((P.n[2] + kKtBZ - 1) / kKtBZ));
-    hipLaunchKernelGGL(k_fluid_kt, dim3(nb), dim3(kKtThreads), 0, s, U, fs, P, F);
+    hipLaunchKernelGGL(k_fluid_kt, dim3(kt_bricks(P)), dim3(kKtThreads), 0, s, U, fs, P, F);
   } else {
     hipLaunchKernelGGL(k_fluid_flux, dim3((unsigned)((fs + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, U, fs, P.w,
                        F);
@@ -550,6 +561,18 @@ int cosmos_rhs(const cosmos_grid* grid, const cosmos_params* params, double t, c
   return COSMOS_OK;
 }
 
+
+int cosmos_kt_divergence(const cosmos_grid* grid, const cosmos_params* params, const double* u, double* div,
+                         void* stream) {
+  int rc;
+  if ((rc = check_common(grid, params)) || (rc = check_state(u, "u")) || (rc = check_state(div, "div"))) return rc;
+  const size_t N = npts(grid);
+  if (div < u + (size_t)NF * N && u < div + 4 * N) return set_error(COSMOS_EINVAL, "div must not overlap u");
+  const DevParams P = dev_params(grid, params);
+  hipLaunchKernelGGL(k_fluid_kt, dim3(kt_bricks(P)), dim3(kKtThreads), 0, (hipStream_t)stream, u, N, P, div);
+  HIP_TRY(hipGetLastError());
+  return COSMOS_OK;
+}
 
 int cosmos_rk4_step(const cosmos_grid* grid, const cosmos_params* params, double t, double dt, double* u, void* ws,
                     void* stream) {

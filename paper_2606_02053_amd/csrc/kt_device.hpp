@@ -133,6 +133,11 @@ __device__ __forceinline__ void kt_segment(const double* U, size_t fs, const Dev
   for (int q = 0; q < 4; ++q) fh[q][slot] = f[q];
 }
 
+// Workgroups of k_fluid_kt: one per 8 x 8 x 4 brick (partial bricks at the upper faces).
+inline unsigned kt_bricks(const DevParams& P) {
+  return (unsigned)(((P.n[0] + kKtBX - 1) / kKtBX) * ((P.n[1] + kKtBY - 1) / kKtBY) * ((P.n[2] + kKtBZ - 1) / kKtBZ));
+}
+
 // D[q fs + c] = sum_a (Fh^a_q(c + 1/2) - Fh^a_q(c - 1/2)) / h_a for q = 0..3.
 __global__ __launch_bounds__(kKtThreads) void k_fluid_kt(const double* U, size_t fs, DevParams P, double* D) {
   __shared__ double fh[4][kKtP];

@@ -68,6 +68,13 @@ def test_invalid_arguments_rejected_on_host(C):
     assert rc == C.COSMOS_EUNSUPPORTED and "adjoint" in C.last_error()
     rc = lib.cosmos_rhs_vjp(ctypes.byref(g), ctypes.byref(kt), 0.0, fake, fake, fake, fake, None)
     assert rc == C.COSMOS_EUNSUPPORTED
+    base = 0x100000
+    u_ = ctypes.c_void_p(base)
+    rc = lib.cosmos_kt_divergence(ctypes.byref(g), ctypes.byref(kt), u_, ctypes.c_void_p(base + 8 * 25 * 16 ** 3 - 8),
+                                  None)
+    assert rc == C.COSMOS_EINVAL and "overlap" in C.last_error()
+    rc = lib.cosmos_kt_divergence(ctypes.byref(g), ctypes.byref(kt), u_, None, None)
+    assert rc == C.COSMOS_EINVAL
     b = C.make_batch([16, 32], [4.0, 8.0], [0, 25 * 16 ** 3])
     rc = lib.cosmos_batch_setup(ctypes.byref(b), ctypes.byref(kt), fake, None)
     assert rc == C.COSMOS_EUNSUPPORTED and "batched" in C.last_error()

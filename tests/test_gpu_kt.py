@@ -59,6 +59,21 @@ def test_kt_rhs(P, orc, n, L, rough, variant):
     assert np.abs(r0[21:] - r[21:]).max() > 1e-6
 
 
+@pytest.mark.parametrize("n,L", [((20, 12, 10), (4.0, 2.5, 2.0)), ((8, 8, 8), (2.0, 2.0, 2.0))])
+def test_kt_divergence_entry_point(P, orc, n, L):
+    """The pre-pass alone (cosmos_kt_divergence) against the oracle's flux divergence."""
+    s = orc.Setup(n=n, L=L, **KT)
+    u = rough_state(n, 17)
+    g = P.make_grid(n, L)
+    div = torch.full((4,) + tuple(reversed(n)), float("nan"), dtype=torch.float64, device="cuda")
+    P.cosmos_kt_divergence(g, P.make_params(**KT), to_dev(u), div)
+    ref = orc.kt_divergence(s, u)
+    got = div.cpu().numpy()
+    assert np.isfinite(got).all()
+    for q in range(4):
+        assert np.abs(got[q] - ref[q]).max() < 1e-11 * max(np.abs(ref[q]).max(), 1e-3), q
+
+
 def test_kt_rhs_options(P, orc):
     n, L = (12, 10, 14), (2.5, 2.0, 3.0)
     u = rough_state(n, 7)

@@ -155,6 +155,20 @@ def test_conservation_on_flat_background(orc):
         assert abs(tot) < 1e-13 * scale, (q, tot, scale)
 
 
+def test_divergence_function_matches_flat_rhs(orc):
+    # on a flat background the fluid right-hand side is minus the flux divergence alone
+    n = (12, 8, 10)
+    u = flat_rest(n, 0.0)
+    fz = fuzz_state(n, seed=4)
+    rng = np.random.default_rng(9)
+    u[ET] = fz[ET] * (1.0 + 0.3 * rng.uniform(-1, 1, size=fz[ET].shape))
+    for c in range(3):
+        u[ST + c] = fz[ST + c] + 0.02 * rng.uniform(-1, 1, size=fz[ET].shape)
+    s = orc.Setup(n=n, L=(3.0, 2.0, 2.5), fluid_scheme=1)
+    r, _ = orc.rhs(s, u)
+    assert np.array_equal(orc.kt_divergence(s, u), -r[ET:])
+
+
 SIGN = np.ones(25)
 for f in (2, 3, 9, 10, 14, 18, 22):  # odd in x: gt_xy, gt_xz, At_xy, At_xz, Gt^x, beta^x, St_x
     SIGN[f] = -1.0
@@ -203,3 +217,13 @@ def test_invalid_fluid_scheme_rejected(orc):
     s = orc.Setup(n=(8, 8, 8), fluid_scheme=2)
     with pytest.raises(ValueError):
         orc.rhs(s, fuzz_state((8, 8, 8), seed=1))
+
+
+def test_stored_op_counts_current(orc):
+    """The operation counts bench.py reads are the oracle's current counts."""
+    import json
+    import os
+    from tests.golden.make_golden import op_counts
+    path = os.path.join(os.path.dirname(__file__), "golden", "op_counts.json")
+    with open(path) as f:
+        assert json.load(f) == op_counts()
