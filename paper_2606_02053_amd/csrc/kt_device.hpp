@@ -78,13 +78,20 @@ template <int a>
 __device__ __forceinline__ void kt_interface(const double* U, size_t fs, const DevParams& P, double sw, int gx, int gy,
                                              int gz, double fh[4]) {
   const int n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
-  int idx[4];  // points g-2, g-1, g, g+1 along a
+  int idx[4];  // points g-2, g-1, g, g+1 along a (no wrap needed away from the faces)
+  if (gx >= 2 && gx + 1 < n0 && gy >= 2 && gy + 1 < n1 && gz >= 2 && gz + 1 < n2) {
+    const int st = a == 0 ? 1 : (a == 1 ? n0 : n0 * n1);
+    const int c0 = gx + n0 * (gy + n1 * gz);
 #pragma unroll
-  for (int o = 0; o < 4; ++o) {
-    const int x = kt_wrap(gx + (a == 0 ? o - 2 : 0), n0);
-    const int y = kt_wrap(gy + (a == 1 ? o - 2 : 0), n1);
-    const int z = kt_wrap(gz + (a == 2 ? o - 2 : 0), n2);
-    idx[o] = x + n0 * (y + n1 * z);
+    for (int o = 0; o < 4; ++o) idx[o] = c0 + (o - 2) * st;
+  } else {
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+      const int x = kt_wrap(gx + (a == 0 ? o - 2 : 0), n0);
+      const int y = kt_wrap(gy + (a == 1 ? o - 2 : 0), n1);
+      const int z = kt_wrap(gz + (a == 2 ? o - 2 : 0), n2);
+      idx[o] = x + n0 * (y + n1 * z);
+    }
   }
   const uint32_t nbytes = (uint32_t)(fs * 8);
   auto ld = [&](int f, int o) { return bld(field_ptr(U, f, fs), nbytes, (uint32_t)idx[o] * 8u); };
@@ -112,10 +119,22 @@ __device__ __forceinline__ void kt_interface(const double* U, size_t fs, const D
   for (int q = 0; q < 4; ++q) fh[q] = 0.5 * (FL[q] + FR[q]) - 0.5 * c * (qR[q] - qL[q]);
 }
 
-// Brick b of the 8 x 8 x 4 decomposition for workgroup v: with nbricks a multiple
-// of 8 the bricks are cut into 8 contiguous chunks, chunk q served by the
-// workgroups v % 8 == q (one XCD each), so neighbouring bricks share an L2.
-__device__ __forceinline__ int kt_brick(int v, int nbricks) {
+// Brick b of the 8 x 8 x 4 decomposition for workgroup v. Consecutive workgroups
+// go round-robin to the 8 XCDs, so workgroups v % 8 == q share XCD q's L2. Where the
+// brick grid allows, XCD q owns the q-th slab of brick layers along z and walks it in
+// columns of 4 x 4 bricks, z fastest: the bricks resident together on an XCD (about
+// 160) are neighbours along all three axes and read each other's halos from its L2.
+// Otherwise the bricks are cut into 8 contiguous chunks (nbricks a multiple of 8) or
+// taken in order.
+__device__ __forceinline__ int kt_brick(int v, int nbricks, int nbx, int nby, int nbz) {
+  constexpr int TX = 4, TY = 4;
+  if (nbz % 8 == 0 && nbx % TX == 0 && nby % TY == 0) {
+    const int zr = nbz / 8, l = v / 8, per = TX * TY * zr;
+    const int tile = l / per, w = l % per;
+    const int bzl = w % zr, col = w / zr;
+    const int bx = (tile % (nbx / TX)) * TX + col % TX, by = (tile / (nbx / TX)) * TY + col / TX;
+    return bx + nbx * (by + nby * ((v % 8) * zr + bzl));
+  }
   if (nbricks % 8) return v;
   return (v % 8) * (nbricks / 8) + v / 8;
 }
@@ -143,7 +162,7 @@ __global__ __launch_bounds__(kKtThreads) void k_fluid_kt(const double* U, size_t
   __shared__ double fh[4][kKtP];
   const int nbx = (P.n[0] + kKtBX - 1) / kKtBX, nby = (P.n[1] + kKtBY - 1) / kKtBY;
   const int nbz = (P.n[2] + kKtBZ - 1) / kKtBZ;
-  const int b = kt_brick(blockIdx.x, nbx * nby * nbz);
+  const int b = kt_brick(blockIdx.x, nbx * nby * nbz, nbx, nby, nbz);
   const int ox = (b % nbx) * kKtBX, oy = ((b / nbx) % nby) * kKtBY, oz = (b / (nbx * nby)) * kKtBZ;
   const double sw = sqrt(P.w);
   for (int t = threadIdx.x; t < kKtP; t += kKtThreads) {
