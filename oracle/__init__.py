@@ -82,6 +82,10 @@ def lib():
             "oracle_matter_point": [f64, f64, P, f64, P, P],
             "oracle_flux_point": [P, P, P],
             "oracle_kt_flux": [P, P, P, i32, P],
+            "oracle_rhs_sc": [P, P, P, P, f64, P, P, P, P, P, i32],
+            "oracle_rk4_steps_sc": [P, P, P, P, f64, f64, i32, P, P, P, i32],
+            "oracle_constraints_sc": [P, P, P, P, P, P, P, P, P, i32],
+            "oracle_init_sc": [P, P, P, P, P, P, u64, i32, i32, P, P],
             "oracle_kt_divergence": [P, P, P, P, P, P],
             "oracle_count_kt_flops": [P, P, P, P, P, P],
             "oracle_fluid_speeds": [P, P, i32, P],
@@ -311,6 +315,58 @@ def flux_point(s: Setup, u25) -> np.ndarray:
     out = np.empty(12)
     lib().oracle_flux_point(_p(prm), _p(u25), _p(out))
     return out
+
+
+# ---- massless scalar field: sc is a float64 array of shape (2, nz, ny, nx) holding phi, Pi
+def _scalar(sc, s: Setup):
+    sc = np.ascontiguousarray(sc, dtype=np.float64)
+    if sc.shape != (2,) + s.shape[1:]:
+        raise ValueError(f"scalar state shape {sc.shape} != {(2,) + s.shape[1:]}")
+    return sc
+
+
+def init_fields_sc(s: Setup, ini: Init, sc_mu: float, sc_sigma: float):
+    """Initial data with an iso-curvature mode Upsilon = sc_mu * profile(sc_sigma): returns (u, sc)."""
+    n, L, prm, iprm = s.arrays()
+    u = np.empty(s.shape)
+    sc = np.empty((2,) + s.shape[1:])
+    _check(lib().oracle_init_sc(_p(n), _p(L), _p(prm), _p(iprm), _p(ini.array()),
+                                _p(np.array([sc_mu, sc_sigma], dtype=np.float64)), ini.seed, ini.profile,
+                                ini.density_mode, _p(u), _p(sc)), "oracle_init_sc")
+    return u, sc
+
+
+def rhs_sc(s: Setup, u, sc, t: float = 0.0, parallel: bool = False):
+    """Right-hand side with the scalar field. Returns (dudt, dscdt, prim_fail)."""
+    n, L, prm, iprm = s.arrays()
+    u, sc = _state(u, s), _scalar(sc, s)
+    du, ds = np.empty_like(u), np.empty_like(sc)
+    pf = ctypes.c_int64(0)
+    _check(lib().oracle_rhs_sc(_p(n), _p(L), _p(prm), _p(iprm), t, _p(u), _p(sc), _p(du), _p(ds), ctypes.byref(pf),
+                               int(parallel)), "oracle_rhs_sc")
+    return du, ds, pf.value
+
+
+def rk4_sc(s: Setup, u, sc, t0: float, dt: float, nsteps: int = 1, parallel: bool = False):
+    """nsteps RK4 steps of (u, sc). Returns (u_new, sc_new, prim_fail)."""
+    n, L, prm, iprm = s.arrays()
+    v, w = _state(u, s).copy(), _scalar(sc, s).copy()
+    pf = ctypes.c_int64(0)
+    _check(lib().oracle_rk4_steps_sc(_p(n), _p(L), _p(prm), _p(iprm), t0, dt, nsteps, _p(v), _p(w),
+                                     ctypes.byref(pf), int(parallel)), "oracle_rk4_steps_sc")
+    return v, w, pf.value
+
+
+def constraints_sc(s: Setup, u, sc, want_fields: bool = False, parallel: bool = False):
+    """Constraint norms (as constraints()) with the scalar field's energy and momentum included."""
+    n, L, prm, iprm = s.arrays()
+    u, sc = _state(u, s), _scalar(sc, s)
+    norms = np.empty(8)
+    H = np.empty(s.shape[1:]) if want_fields else None
+    M = np.empty((3,) + s.shape[1:]) if want_fields else None
+    _check(lib().oracle_constraints_sc(_p(n), _p(L), _p(prm), _p(iprm), _p(u), _p(sc), _p(norms), _p(H), _p(M),
+                                       int(parallel)), "oracle_constraints_sc")
+    return (norms, H, M) if want_fields else norms
 
 
 def kt_flux(s: Setup, uL, uR, a: int) -> np.ndarray:

@@ -91,6 +91,9 @@ struct InitSpec {
   uint64_t seed = 2606;
   int profile = GAUSS;
   int density_mode = HAMILTONIAN;
+  // iso-curvature mode of the massless scalar field: Upsilon(x) = sc_mu * (profile
+  // above with width sc_sigma) about the same centre (sc_mu = 0: no scalar field)
+  double sc_mu = 0.0, sc_sigma = 1.0;
 };
 
 struct Status {
@@ -127,10 +130,10 @@ inline int wrap(int i, int n) { return ((i % n) + n) % n; }
 // out of the periodic state u. With o = 0 and m = n this is the ordinary
 // periodic ghost-zone fill of the whole grid.
 template <class T>
-void pad_periodic(const Grid& g, const T* u, const int o[3], const int m[3], Padded<T>& P) {
+void pad_periodic(const Grid& g, const T* u, const int o[3], const int m[3], Padded<T>& P, int nfields = NF) {
   P.resize(m);
   const int64_t N3 = g.npts();
-  for (int f = 0; f < NF; ++f)
+  for (int f = 0; f < nfields; ++f)
     for (int k = -NG; k < m[2] + NG; ++k)
       for (int j = -NG; j < m[1] + NG; ++j)
         for (int i = -NG; i < m[0] + NG; ++i) {
@@ -436,6 +439,45 @@ void fluid_flux(const Params& p, const T u[NF], T out[12]) {
   }
 }
 
+// ------------------------------------------------------------------ massless scalar field
+// The second matter field of the paper ("Physical system settings": the scalar
+// stress tensor T^SC = d phi d phi - 1/2 g (d phi)^2 and the wave equation
+// box phi = 0). Evolved as phi and Pi = n^mu d_mu phi (n the unit normal of the
+// slices), held in a separate 2-field state s[PHI], s[PIF]. The 3+1 form of
+// box phi = 0:
+//   d_t phi = alpha Pi + beta^k d_k phi,
+//   d_t Pi  = beta^k d_k Pi + alpha K Pi + alpha gamma^ij (d_i d_j phi - Gamma^k_ij d_k phi)
+//             + gamma^ij d_i alpha d_j phi,
+// with gamma^ij = chi gt^ij and gamma^ij Gamma^k_ij = chi Gd^k + 1/2 gt^kl d_l chi.
+// Projections of T^SC on the normal frame (the sources of the geometry):
+//   E = 1/2 (Pi^2 + |D phi|^2),  S_i = -Pi d_i phi,
+//   S_ij = d_i phi d_j phi - 1/2 gamma_ij (|D phi|^2 - Pi^2),  S = 3/2 Pi^2 - 1/2 |D phi|^2.
+constexpr int NS = 2;
+enum ScalarField : int { PHI = 0, PIF = 1 };
+
+template <class T>
+struct ScalarIn {
+  T Pi, dphi[3], d2phi[6];
+};
+
+template <class T>
+struct ScalarSrc {
+  T E, S[3], Sij[6], Strace;  // physical (not densitised)
+};
+
+template <class T>
+void scalar_matter(T chi, const T gt[6], const T gi[6], const ScalarIn<T>& sc, ScalarSrc<T>& M) {
+  T g2 = T(0.0);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) g2 = g2 + gi[SYM[i][j]] * sc.dphi[i] * sc.dphi[j];
+  g2 = chi * g2;  // |D phi|^2
+  const T P2 = sc.Pi * sc.Pi;
+  M.E = T(0.5) * (P2 + g2);
+  for (int i = 0; i < 3; ++i) M.S[i] = -sc.Pi * sc.dphi[i];
+  for (int s = 0; s < 6; ++s) M.Sij[s] = sc.dphi[SI[s]] * sc.dphi[SJ[s]] - T(0.5) * (gt[s] / chi) * (g2 - P2);
+  M.Strace = T(1.5) * P2 - T(0.5) * g2;
+}
+
 // ------------------------------------------------------------------ Kurganov-Tadmor fluxes
 // The paper's fluid scheme (section "Physical system settings" cites Kurganov &
 // Tadmor 2000 and Shibata & Font 2005): a semi-discrete central scheme in
@@ -569,14 +611,23 @@ void gather_geom(const Padded<T>& P, const double* h, int i, int j, int k, GeomI
 
 // Pointwise right-hand side of the BSSN + fluid system (without the advection,
 // dissipation and flux-divergence terms, which rhs_padded adds).
+// With a scalar field (sc non-null) its stress tensor adds to the sources of K,
+// At and Gt, and sout[PHI], sout[PIF] receive its right-hand side (without the
+// advection and dissipation terms, which the caller adds).
 template <class T>
-bool rhs_point(const Params& p, double t, const GeomIn<T>& in, T Et, const T St[3], T out[NF]) {
+bool rhs_point(const Params& p, double t, const GeomIn<T>& in, T Et, const T St[3], T out[NF],
+               const ScalarIn<T>* sc = nullptr, T* sout = nullptr) {
   Geom<T> G;
   geometry(in, G);
   const T* gi = G.gi;
   const T chi = in.chi, K = in.K, alpha = in.alpha;
   Matter<T> M;
   bool fail = matter(p, chi, in.gt, gi, Et, St, M);
+  ScalarSrc<T> X;  // scalar-field sources (zero without a scalar field)
+  X.E = X.Strace = T(0.0);
+  for (int c = 0; c < 3; ++c) X.S[c] = T(0.0);
+  for (int q = 0; q < 6; ++q) X.Sij[q] = T(0.0);
+  if (sc) scalar_matter(chi, in.gt, gi, *sc, X);
 
   T DDa[6];
   ddalpha(in, G, DDa);
@@ -616,10 +667,12 @@ bool rhs_point(const Params& p, double t, const GeomIn<T>& in, T Et, const T St[
     out[GT + s] = acc - T(2.0 / 3.0) * in.gt[s] * divb - T(2.0) * alpha * in.At[s];
   }
   // K
-  out[TRK] = -D2a + alpha * (AA + K * K / T(3.0)) + pi4 * alpha * (M.E + M.Strace);
+  T EpS = M.E + M.Strace;
+  if (sc) EpS = EpS + (X.E + X.Strace);
+  out[TRK] = -D2a + alpha * (AA + K * K / T(3.0)) + pi4 * alpha * EpS;
   // At_ij
   T Xs[6];
-  for (int s = 0; s < 6; ++s) Xs[s] = -DDa[s] + alpha * (G.Ric[s] - pi8 * M.Sij[s]);
+  for (int s = 0; s < 6; ++s) Xs[s] = -DDa[s] + alpha * (G.Ric[s] - pi8 * (sc ? M.Sij[s] + X.Sij[s] : M.Sij[s]));
   T trX = T(0.0);
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) trX = trX + gi[SYM[i][j]] * Xs[SYM[i][j]];
@@ -650,7 +703,7 @@ bool rhs_point(const Params& p, double t, const GeomIn<T>& in, T Et, const T St[
     for (int j = 0; j < 3; ++j) inner = inner - T(2.0 / 3.0) * gi[SYM[i][j]] * in.dK[j];
     acc = acc + T(2.0) * alpha * inner;
     T gS = T(0.0);
-    for (int j = 0; j < 3; ++j) gS = gS + gi[SYM[i][j]] * M.S[j];
+    for (int j = 0; j < 3; ++j) gS = gS + gi[SYM[i][j]] * (sc ? M.S[j] + X.S[j] : M.S[j]);
     out[GAM + i] = acc - pi16 * alpha * gS;
   }
   // gauge
@@ -679,13 +732,32 @@ bool rhs_point(const Params& p, double t, const GeomIn<T>& in, T Et, const T St[
       }
     out[ST + i] = im32 * (acc + alpha / T(2.0) * sg);
   }
+  // scalar field
+  if (sc && sout) {
+    sout[PHI] = alpha * sc->Pi;
+    T lap = T(0.0);  // gt^ij (d_i d_j phi) - (Gd^k + 1/(2 chi) gt^kl d_l chi) d_k phi, times chi below
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) lap = lap + gi[SYM[i][j]] * sc->d2phi[SYM[i][j]];
+    for (int k = 0; k < 3; ++k) {
+      T gk = G.Gd[k];
+      for (int l = 0; l < 3; ++l) gk = gk + gi[SYM[k][l]] * in.dchi[l] / (T(2.0) * chi);
+      lap = lap - gk * sc->dphi[k];
+    }
+    T dad = T(0.0);  // gt^ij d_i alpha d_j phi
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) dad = dad + gi[SYM[i][j]] * in.dalpha[i] * sc->dphi[j];
+    sout[PIF] = alpha * K * sc->Pi + alpha * chi * lap + chi * dad;
+  }
   return fail;
 }
 
 // Right-hand side on the interior of a padded window. out is SoA over the
 // window: out[f*m0*m1*m2 + i + m0*(j + m1*k)].
+// With a scalar field, Q is its padded window (fields PHI, PIF) and sout receives
+// its right-hand side in the same layout as out (2 fields).
 template <class T>
-void rhs_padded(const Grid& g, const Params& p, double t, const Padded<T>& P, T* out, Status& st, bool parallel) {
+void rhs_padded(const Grid& g, const Params& p, double t, const Padded<T>& P, T* out, Status& st, bool parallel,
+                const Padded<T>* Q = nullptr, T* sout = nullptr) {
   const double h[3] = {g.h(0), g.h(1), g.h(2)};
   const int* m = P.m;
   // fluxes at every padded point within reach 2 of the interior (pointwise)
@@ -728,8 +800,14 @@ void rhs_padded(const Grid& g, const Params& p, double t, const Padded<T>& P, T*
         GeomIn<T> in;
         gather_geom(P, h, i, j, k, in, false);
         T St[3] = {P(ST, i, j, k), P(ST + 1, i, j, k), P(ST + 2, i, j, k)};
-        T r[NF];
-        if (rhs_point(p, t, in, P(ET, i, j, k), St, r)) ++fails;
+        T r[NF], sr[NS];
+        ScalarIn<T> sci;
+        if (Q) {
+          sci.Pi = (*Q)(PIF, i, j, k);
+          for (int a = 0; a < 3; ++a) sci.dphi[a] = D1(*Q, h, PHI, i, j, k, a);
+          for (int q = 0; q < 6; ++q) sci.d2phi[q] = Dsecond(*Q, h, PHI, i, j, k, SI[q], SJ[q]);
+        }
+        if (rhs_point(p, t, in, P(ET, i, j, k), St, r, Q ? &sci : nullptr, sr)) ++fails;
         // shift advection for the 21 geometric fields
         for (int f = 0; f < ET; ++f) {
           if (f >= BET && !p.evolve_shift) continue;
@@ -765,17 +843,27 @@ void rhs_padded(const Grid& g, const Params& p, double t, const Padded<T>& P, T*
         }
         const int64_t q = i + (int64_t)m[0] * (j + (int64_t)m[1] * k);
         for (int f = 0; f < NF; ++f) out[f * M3 + q] = r[f];
+        if (Q) {  // scalar field: shift advection and KO dissipation of phi and Pi
+          for (int f = 0; f < NS; ++f) {
+            sr[f] = sr[f] + Advect(*Q, h, f, i, j, k, in.beta);
+            sr[f] = sr[f] + KO(*Q, h, p.ko_eps, f, i, j, k);
+            sout[f * M3 + q] = sr[f];
+          }
+        }
       }
   st.prim_fail += fails;
 }
 
-// Right-hand side of the whole periodic grid.
+// Right-hand side of the whole periodic grid (with the scalar field s, 2 x N3
+// values, when s is non-null: its right-hand side goes to dsdt).
 template <class T>
-void rhs(const Grid& g, const Params& p, double t, const T* u, T* dudt, Status& st, bool parallel = false) {
-  Padded<T> P;
+void rhs(const Grid& g, const Params& p, double t, const T* u, T* dudt, Status& st, bool parallel = false,
+         const T* s = nullptr, T* dsdt = nullptr) {
+  Padded<T> P, Q;
   const int o[3] = {0, 0, 0};
   pad_periodic(g, u, o, g.n, P);
-  rhs_padded(g, p, t, P, dudt, st, parallel);
+  if (s) pad_periodic(g, s, o, g.n, Q, NS);
+  rhs_padded(g, p, t, P, dudt, st, parallel, s ? &Q : nullptr, dsdt);
 }
 
 // Kurganov-Tadmor flux divergence alone on the whole periodic grid:
@@ -810,18 +898,27 @@ inline void kt_divergence(const Grid& g, const Params& p, const double* u, doubl
 //   k1 = f(t, u), k2 = f(t + dt/2, u + dt/2 k1), k3 = f(t + dt/2, u + dt/2 k2),
 //   k4 = f(t + dt, u + dt k3),  u' = u + dt/6 (k1 + 2 k2 + 2 k3 + k4)
 template <class T>
-void rk4_step(const Grid& g, const Params& p, double t, double dt, T* u, Status& st, bool parallel = false) {
-  const size_t n = (size_t)NF * g.npts();
-  std::vector<T> k1(n), k2(n), k3(n), k4(n), U(n);
-  rhs(g, p, t, u, k1.data(), st, parallel);
-  for (size_t q = 0; q < n; ++q) U[q] = u[q] + T(dt / 2.0) * k1[q];
-  rhs(g, p, t + dt / 2.0, U.data(), k2.data(), st, parallel);
-  for (size_t q = 0; q < n; ++q) U[q] = u[q] + T(dt / 2.0) * k2[q];
-  rhs(g, p, t + dt / 2.0, U.data(), k3.data(), st, parallel);
-  for (size_t q = 0; q < n; ++q) U[q] = u[q] + T(dt) * k3[q];
-  rhs(g, p, t + dt, U.data(), k4.data(), st, parallel);
-  for (size_t q = 0; q < n; ++q)
-    u[q] = u[q] + T(dt / 6.0) * (k1[q] + T(2.0) * k2[q] + T(2.0) * k3[q] + k4[q]);
+void rk4_step(const Grid& g, const Params& p, double t, double dt, T* u, Status& st, bool parallel = false,
+              T* s = nullptr) {
+  // with a scalar field the RK4 state is (u, s): both advance together
+  const size_t n = (size_t)NF * g.npts(), ns = s ? (size_t)NS * g.npts() : 0;
+  std::vector<T> k1(n + ns), k2(n + ns), k3(n + ns), k4(n + ns), U(n + ns);
+  auto f = [&](double tt, const T* x, T* k) { rhs(g, p, tt, x, k, st, parallel, s ? x + n : nullptr, s ? k + n : nullptr); };
+  std::vector<T> x0(n + ns);
+  for (size_t q = 0; q < n; ++q) x0[q] = u[q];
+  for (size_t q = 0; q < ns; ++q) x0[n + q] = s[q];
+  f(t, x0.data(), k1.data());
+  for (size_t q = 0; q < n + ns; ++q) U[q] = x0[q] + T(dt / 2.0) * k1[q];
+  f(t + dt / 2.0, U.data(), k2.data());
+  for (size_t q = 0; q < n + ns; ++q) U[q] = x0[q] + T(dt / 2.0) * k2[q];
+  f(t + dt / 2.0, U.data(), k3.data());
+  for (size_t q = 0; q < n + ns; ++q) U[q] = x0[q] + T(dt) * k3[q];
+  f(t + dt, U.data(), k4.data());
+  for (size_t q = 0; q < n + ns; ++q) {
+    const T v = x0[q] + T(dt / 6.0) * (k1[q] + T(2.0) * k2[q] + T(2.0) * k3[q] + k4[q]);
+    if (q < n) u[q] = v;
+    else s[q - n] = v;
+  }
 }
 
 // One RK4 step evaluated only at the listed points of a periodic grid, with
@@ -893,13 +990,21 @@ inline void rhs_at_points(const Grid& g, const Params& p, double t, const double
 // ------------------------------------------------------------------ constraints
 // H   = R + 2/3 K^2 - At_ij At^ij - 16 pi E
 // M_i = gt^jk (d_j At_ki - Gt^l_jk At_li - Gt^l_ji At_kl) - 3/(2 chi) At^j_i d_j chi - 2/3 d_i K - 8 pi S_i
+// With a scalar field (sc non-null) E and S_i include its energy and momentum densities.
 template <class T>
-void constraints_point(const Params& p, const GeomIn<T>& in, T Et, const T St[3], T& H, T M[3], T& Hn) {
+void constraints_point(const Params& p, const GeomIn<T>& in, T Et, const T St[3], T& H, T M[3], T& Hn,
+                       const ScalarIn<T>* sc = nullptr) {
   Geom<T> G;
   geometry(in, G);
   const T* gi = G.gi;
   Matter<T> Mt;
   matter(p, in.chi, in.gt, gi, Et, St, Mt);
+  if (sc) {
+    ScalarSrc<T> X;
+    scalar_matter(in.chi, in.gt, gi, *sc, X);
+    Mt.E = Mt.E + X.E;
+    for (int i = 0; i < 3; ++i) Mt.S[i] = Mt.S[i] + X.S[i];
+  }
   T Amix[3][3];
   for (int k = 0; k < 3; ++k)
     for (int j = 0; j < 3; ++j) {
@@ -951,10 +1056,11 @@ struct NSum {
 // A point is non-finite if any state value or H or a component of M is not finite.
 // argmin alpha is the lowest linear index among the minima (NaN never compares less).
 inline void constraints(const Grid& g, const Params& p, const double* u, double norms[8], double* Hout, double* Mout,
-                        bool parallel = false) {
-  Padded<double> P;
+                        bool parallel = false, const double* s = nullptr) {
+  Padded<double> P, Q;
   const int o[3] = {0, 0, 0};
   pad_periodic(g, u, o, g.n, P);
+  if (s) pad_periodic(g, s, o, g.n, Q, NS);
   const double h[3] = {g.h(0), g.h(1), g.h(2)};
   const int64_t N3 = g.npts();
   std::vector<double> Hv(N3), Mv(N3), Hnv(N3), nonf(N3);
@@ -966,10 +1072,18 @@ inline void constraints(const Grid& g, const Params& p, const double* u, double 
         gather_geom(P, h, i, j, k, in, true);
         double St[3] = {P(ST, i, j, k), P(ST + 1, i, j, k), P(ST + 2, i, j, k)};
         double H, M[3], Hn;
-        constraints_point(p, in, P(ET, i, j, k), St, H, M, Hn);
+        ScalarIn<double> sci;
+        if (s) {
+          sci.Pi = Q(PIF, i, j, k);
+          for (int a = 0; a < 3; ++a) sci.dphi[a] = D1(Q, h, PHI, i, j, k, a);
+          for (int c = 0; c < 6; ++c) sci.d2phi[c] = 0.0;  // not used by the constraints
+        }
+        constraints_point(p, in, P(ET, i, j, k), St, H, M, Hn, s ? &sci : nullptr);
         const int64_t q = i + (int64_t)g.n[0] * (j + (int64_t)g.n[1] * k);
         bool bad = !std::isfinite(H) || !std::isfinite(M[0]) || !std::isfinite(M[1]) || !std::isfinite(M[2]);
         for (int f = 0; f < NF; ++f) bad = bad || !std::isfinite(u[f * N3 + q]);
+        if (s)
+          for (int f = 0; f < NS; ++f) bad = bad || !std::isfinite(s[f * N3 + q]);
         Hv[q] = H;
         Mv[q] = std::sqrt(M[0] * M[0] + M[1] * M[1] + M[2] * M[2]);
         Hnv[q] = Hn;
@@ -1019,34 +1133,26 @@ inline double noise_at(uint64_t seed, uint64_t p) {
   return 2.0 * u01 - 1.0;
 }
 
-// Leading-order long-wavelength growing mode for a curvature perturbation
-// zeta(x) on the radiation FLRW background (paper: initial-data paragraph of
-// "Physical system settings"): conformally flat metric gamma_ij = e^{2 zeta}
-// delta_ij (chi = e^{-2 zeta}, gt_ij = delta_ij), K = -3 H0, At = 0, Gt = 0,
-// alpha = 1, beta = 0, fluid at rest. The energy density is fixed by the
-// Hamiltonian constraint with At = 0 and S = 0:  E = (R + 2/3 K^2) / 16 pi,
-// R = -e^{-2 zeta} (4 lap(zeta) + 2 |grad zeta|^2).
-// Returns the 25 field values at grid point (i, j, k) (any integers; wrapped).
+// Profile f = mu * shape(x) of a perturbation about the box point x (x relative to
+// the centre): value, Laplacian and |grad f|^2, in closed form.
+//   GAUSS:  mu exp(-r^2 / 2 sigma^2);  SINE: mu sin(2 pi x_0 / L_0);
+//   PGAUSS: Gaussian in s_a = (L_a / pi) sin(pi x_a / L_a) (smooth and periodic).
 template <class T>
-void init_point(const Grid& g, const Params& p, const InitSpec& s, T mu, T sigma, int i, int j, int k, T out[NF]) {
-  int I[3] = {wrap(i, g.n[0]), wrap(j, g.n[1]), wrap(k, g.n[2])};
-  double x[3];
-  for (int a = 0; a < 3; ++a) x[a] = -0.5 * g.L[a] + I[a] * g.h(a) - s.center[a];
-  T zeta, lap, grad2;
-  if (s.profile == GAUSS) {
+void profile_at(const Grid& g, int profile, T mu, T sigma, const double x[3], T& val, T& lap, T& grad2) {
+  if (profile == GAUSS) {
     double r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
     T s2 = sigma * sigma;
-    zeta = mu * exp(T(-r2) / (T(2.0) * s2));
-    lap = zeta * (T(r2) / (s2 * s2) - T(3.0) / s2);
-    grad2 = zeta * zeta * T(r2) / (s2 * s2);
-  } else if (s.profile == SINE) {
+    val = mu * exp(T(-r2) / (T(2.0) * s2));
+    lap = val * (T(r2) / (s2 * s2) - T(3.0) / s2);
+    grad2 = val * val * T(r2) / (s2 * s2);
+  } else if (profile == SINE) {
     double kx = 2.0 * PI / g.L[0];
     T sn = T(std::sin(kx * x[0]));
     double cs = std::cos(kx * x[0]);
-    zeta = mu * sn;
-    lap = T(-kx * kx) * zeta;
+    val = mu * sn;
+    lap = T(-kx * kx) * val;
     grad2 = mu * mu * T(kx * kx * cs * cs);
-  } else {  // PGAUSS: Gaussian in s_a = (L/pi) sin(pi x_a / L), periodic and smooth
+  } else {
     T s2 = sigma * sigma;
     double sa[3], ca[3], q2 = 0.0;
     for (int a = 0; a < 3; ++a) {
@@ -1055,18 +1161,41 @@ void init_point(const Grid& g, const Params& p, const InitSpec& s, T mu, T sigma
       ca[a] = std::cos(kk * x[a]);
       q2 += sa[a] * sa[a];
     }
-    zeta = mu * exp(T(-q2) / (T(2.0) * s2));
+    val = mu * exp(T(-q2) / (T(2.0) * s2));
     T l = T(0.0), gg = T(0.0);
     for (int a = 0; a < 3; ++a) {
       double kk = PI / g.L[a];
       double sc = sa[a] * ca[a];
-      // d_a zeta = -zeta s c / sigma^2 ; d_a^2 zeta = zeta (s c)^2/sigma^4 - zeta (c^2 - k^2 s^2)/sigma^2
-      l = l + zeta * T(sc * sc) / (s2 * s2) - zeta * T(ca[a] * ca[a] - kk * kk * sa[a] * sa[a]) / s2;
-      gg = gg + zeta * zeta * T(sc * sc) / (s2 * s2);
+      // d_a f = -f s c / sigma^2 ; d_a^2 f = f (s c)^2/sigma^4 - f (c^2 - k^2 s^2)/sigma^2
+      l = l + val * T(sc * sc) / (s2 * s2) - val * T(ca[a] * ca[a] - kk * kk * sa[a] * sa[a]) / s2;
+      gg = gg + val * val * T(sc * sc) / (s2 * s2);
     }
     lap = l;
     grad2 = gg;
   }
+}
+
+// Leading-order long-wavelength growing mode for a curvature perturbation
+// zeta(x) on the radiation FLRW background (paper: initial-data paragraph of
+// "Physical system settings"): conformally flat metric gamma_ij = e^{2 zeta}
+// delta_ij (chi = e^{-2 zeta}, gt_ij = delta_ij), K = -3 H0, At = 0, Gt = 0,
+// alpha = 1, beta = 0, fluid at rest. The energy density is fixed by the
+// Hamiltonian constraint with At = 0 and S = 0:  E = (R + 2/3 K^2) / 16 pi,
+// R = -e^{-2 zeta} (4 lap(zeta) + 2 |grad zeta|^2).
+// With an iso-curvature mode Upsilon(x) of the massless scalar field (paper:
+// "Spherically symmetric iso-curvature" example; the field does not enter the
+// background metric at leading order): phi = Upsilon, Pi = 0, and the fluid
+// carries the rest of the constraint's energy, E_fluid = E - 1/2 chi |grad Upsilon|^2.
+// Returns the 25 field values at grid point (i, j, k) (any integers; wrapped),
+// and phi, Pi in sout when non-null.
+template <class T>
+void init_point(const Grid& g, const Params& p, const InitSpec& s, T mu, T sigma, int i, int j, int k, T out[NF],
+                T* sout = nullptr) {
+  int I[3] = {wrap(i, g.n[0]), wrap(j, g.n[1]), wrap(k, g.n[2])};
+  double x[3];
+  for (int a = 0; a < 3; ++a) x[a] = -0.5 * g.L[a] + I[a] * g.h(a) - s.center[a];
+  T zeta, lap, grad2;
+  profile_at(g, s.profile, mu, sigma, x, zeta, lap, grad2);
   T chi = exp(T(-2.0) * zeta);
   T R = -chi * (T(4.0) * lap + T(2.0) * grad2);
   T K = T(-3.0 * p.H0);
@@ -1075,6 +1204,12 @@ void init_point(const Grid& g, const Params& p, const InitSpec& s, T mu, T sigma
     E = (R + T(2.0 / 3.0) * K * K) / T(16.0 * PI);
   else
     E = T(3.0 * p.H0 * p.H0 / (8.0 * PI));
+  T ups = T(0.0);
+  if (s.sc_mu != 0.0) {
+    T ulap, ug2;
+    profile_at(g, s.profile, T(s.sc_mu), T(s.sc_sigma), x, ups, ulap, ug2);
+    if (s.density_mode == HAMILTONIAN) E = E - T(0.5) * chi * ug2;
+  }
   if (s.noise_amp != 0.0) {
     uint64_t lin = (uint64_t)I[0] + (uint64_t)g.n[0] * ((uint64_t)I[1] + (uint64_t)g.n[1] * (uint64_t)I[2]);
     E = E * T(1.0 + s.noise_amp * noise_at(s.seed, lin));
@@ -1087,18 +1222,24 @@ void init_point(const Grid& g, const Params& p, const InitSpec& s, T mu, T sigma
   out[TRK] = K;
   out[ALP] = T(1.0);
   out[ET] = E / (chi * sqrt(chi));
+  if (sout) {
+    sout[PHI] = ups;
+    sout[PIF] = T(0.0);
+  }
 }
 
 template <class T>
-void init_fields(const Grid& g, const Params& p, const InitSpec& s, T mu, T sigma, T* u) {
+void init_fields(const Grid& g, const Params& p, const InitSpec& s, T mu, T sigma, T* u, T* sc = nullptr) {
   const int64_t N3 = g.npts();
   for (int k = 0; k < g.n[2]; ++k)
     for (int j = 0; j < g.n[1]; ++j)
       for (int i = 0; i < g.n[0]; ++i) {
-        T v[NF];
-        init_point(g, p, s, mu, sigma, i, j, k, v);
+        T v[NF], w[NS];
+        init_point(g, p, s, mu, sigma, i, j, k, v, w);
         const int64_t q = i + (int64_t)g.n[0] * (j + (int64_t)g.n[1] * k);
         for (int f = 0; f < NF; ++f) u[f * N3 + q] = v[f];
+        if (sc)
+          for (int f = 0; f < NS; ++f) sc[f * N3 + q] = w[f];
       }
 }
 

@@ -119,6 +119,51 @@ int oracle_rk4_steps(const int* n, const double* L, const double* prm, const int
   return 0;
 }
 
+// ---- with the massless scalar field: s holds phi and Pi (2 * N3 values, SoA)
+int oracle_rhs_sc(const int* n, const double* L, const double* prm, const int* iprm, double t, const double* u,
+                  const double* s, double* dudt, double* dsdt, int64_t* prim_fail, int parallel) {
+  Grid g;
+  Params p;
+  if (!make(n, L, prm, iprm, g, p) || !u || !s || !dudt || !dsdt) return -1;
+  Status st;
+  rhs(g, p, t, u, dudt, st, parallel != 0, s, dsdt);
+  if (prim_fail) *prim_fail = st.prim_fail;
+  return 0;
+}
+
+int oracle_rk4_steps_sc(const int* n, const double* L, const double* prm, const int* iprm, double t0, double dt,
+                        int nsteps, double* u, double* s, int64_t* prim_fail, int parallel) {
+  Grid g;
+  Params p;
+  if (!make(n, L, prm, iprm, g, p) || !u || !s || nsteps < 0) return -1;
+  Status st;
+  for (int q = 0; q < nsteps; ++q) rk4_step(g, p, t0 + q * dt, dt, u, st, parallel != 0, s);
+  if (prim_fail) *prim_fail = st.prim_fail;
+  return 0;
+}
+
+int oracle_constraints_sc(const int* n, const double* L, const double* prm, const int* iprm, const double* u,
+                          const double* s, double* norms, double* H, double* M, int parallel) {
+  Grid g;
+  Params p;
+  if (!make(n, L, prm, iprm, g, p) || !u || !s || !norms) return -1;
+  constraints(g, p, u, norms, H, M, parallel != 0, s);
+  return 0;
+}
+
+// init_d = {mu, sigma, cx, cy, cz, noise_amp}, sc_d = {sc_mu, sc_sigma}
+int oracle_init_sc(const int* n, const double* L, const double* prm, const int* iprm, const double* init_d,
+                   const double* sc_d, uint64_t seed, int profile, int density_mode, double* u, double* s) {
+  Grid g;
+  Params p;
+  if (!make(n, L, prm, iprm, g, p) || !init_d || !sc_d || !u || !s) return -1;
+  InitSpec spec = make_init(init_d, seed, profile, density_mode);
+  spec.sc_mu = sc_d[0];
+  spec.sc_sigma = sc_d[1];
+  init_fields<double>(g, p, spec, spec.mu, spec.sigma, u, s);
+  return 0;
+}
+
 int oracle_rhs_at_points(const int* n, const double* L, const double* prm, const int* iprm, double t,
                          const double* u, const int64_t* pts, int npts, double* out) {
   Grid g;
