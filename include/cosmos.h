@@ -173,6 +173,43 @@ int cosmos_rhs(const cosmos_grid* grid, const cosmos_params* params, double t, c
 int cosmos_kt_divergence(const cosmos_grid* grid, const cosmos_params* params, const double* u, double* div,
                          void* stream);
 
+/* ---- Massless scalar field ("Physical system settings": the second matter field, stress tensor
+ * d phi d phi - 1/2 g (d phi)^2 and wave equation box phi = 0; "Spherically symmetric
+ * iso-curvature" example for its initial data). The field lives in a separate state s of
+ * 2 * N3 doubles (phi, then Pi = n^mu d_mu phi, each x fastest), caller-owned device memory. Its
+ * evolution: d_t phi = alpha Pi + beta.grad phi, d_t Pi = beta.grad Pi + alpha K Pi + alpha D^i D_i phi
+ * + D^i alpha D_i phi, with KO dissipation on both; its energy E = (Pi^2 + |D phi|^2) / 2, momentum
+ * S_i = -Pi d_i phi and stress S_ij = d_i phi d_j phi - gamma_ij (|D phi|^2 - Pi^2) / 2 join the fluid's
+ * in the K, At and Gt equations and in the constraints (the fluid equations are unchanged).
+ * sws: device workspace of cosmos_scalar_workspace_bytes(grid) bytes, 256-byte aligned (the
+ * 11 source arrays and the scalar's RK4 buffers), used besides ws. With variant 0 the stage kernel
+ * runs the 16x4x4 brick only (other bricks: COSMOS_EUNSUPPORTED); fluid_scheme 0 and 1 are both
+ * supported. The status counters do not look at s (cosmos_constraints_scalar flags non-finite
+ * scalar energies). */
+size_t cosmos_scalar_workspace_bytes(const cosmos_grid* grid);
+
+/* cosmos_init_fields with an iso-curvature mode Upsilon = sc_mu * profile(x; sc_sigma) of the scalar
+ * field (the same profile family and centre as zeta): phi = Upsilon, Pi = 0, and with density_mode 0
+ * the fluid energy is the Hamiltonian constraint's remainder, E = (R + 2/3 K^2) / 16 pi -
+ * chi |grad Upsilon|^2 / 2 (leading order: the field does not enter the background metric). sc_mu = 0
+ * gives exactly cosmos_init_fields and s = 0. Errors: COSMOS_EINVAL (invalid init, sc_sigma <= 0, s
+ * overlapping u). */
+int cosmos_init_fields_scalar(const cosmos_grid* grid, const cosmos_params* params, const cosmos_init* init,
+                              double sc_mu, double sc_sigma, double* u, double* s, void* stream);
+
+/* Right-hand side of (u, s) at time t: dudt (25 * N3) and dsdt (2 * N3); neither may overlap u, s or
+ * the other. */
+int cosmos_rhs_scalar(const cosmos_grid* grid, const cosmos_params* params, double t, const double* u,
+                      const double* s, double* dudt, double* dsdt, void* ws, void* sws, void* stream);
+
+/* One classic RK4 step of (u, s) in place (both advance together). */
+int cosmos_rk4_step_scalar(const cosmos_grid* grid, const cosmos_params* params, double t, double dt, double* u,
+                           double* s, void* ws, void* sws, void* stream);
+
+/* cosmos_constraints with the scalar field's energy and momentum in H and M_i. */
+int cosmos_constraints_scalar(const cosmos_grid* grid, const cosmos_params* params, const double* u, const double* s,
+                              double* norms_dev, double* H_out, double* M_out, void* ws, void* sws, void* stream);
+
 /* One classic RK4 step of size dt from time t, in place on u:
  * u <- u + dt/6 (k1 + 2 k2 + 2 k3 + k4). The stage update is fused into the right-hand-side
  * kernels (k is never stored): 4 launches, 3 state-sized buffers in ws. */

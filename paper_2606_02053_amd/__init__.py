@@ -8,6 +8,7 @@ of include/cosmos.h. This package is the thin Python side: ctypes marshalling
 from ._lib import (COSMOS_EINVAL, COSMOS_EHIP, COSMOS_OK, NFIELDS, CosmosError, cosmos_abi_version,  # noqa: F401
                    cosmos_adjoint_step, cosmos_adjoint_step_stages, cosmos_adjoint_workspace_bytes, cosmos_rhs_vjp,
                    cosmos_constraints, cosmos_init_fields, cosmos_init_tangent, cosmos_kt_divergence, cosmos_rhs,
-                   cosmos_rk4_step, cosmos_rk4_step_stages, cosmos_status, cosmos_status_reset, cosmos_workspace_bytes, last_error,
+                   cosmos_rk4_step, cosmos_rk4_step_stages, cosmos_scalar_workspace_bytes, cosmos_init_fields_scalar,
+                   cosmos_rhs_scalar, cosmos_rk4_step_scalar, cosmos_constraints_scalar, cosmos_status, cosmos_status_reset, cosmos_workspace_bytes, last_error,
                    make_grid, make_init, make_params, npts)
 from .solver import Solver  # noqa: F401

@@ -75,6 +75,11 @@ def _load():
         "cosmos_batch_setup": ([B, Pr, P, P], i32),
         "cosmos_rk4_step_batched": ([B, Pr, P, P, P, P, P], i32),
         "cosmos_batch_status": ([B, P, P, ctypes.POINTER(ctypes.c_int64)], i32),
+        "cosmos_scalar_workspace_bytes": ([G], sz),
+        "cosmos_init_fields_scalar": ([G, Pr, In, f64, f64, P, P, P], i32),
+        "cosmos_rhs_scalar": ([G, Pr, f64, P, P, P, P, P, P, P], i32),
+        "cosmos_rk4_step_scalar": ([G, Pr, f64, f64, P, P, P, P, P], i32),
+        "cosmos_constraints_scalar": ([G, Pr, P, P, P, P, P, P, P, P], i32),
         "cosmos_last_error": ([], ctypes.c_char_p),
         "cosmos_abi_version": ([], i32),
     }
@@ -205,6 +210,46 @@ def cosmos_constraints(grid, params, u, norms_dev, H_out=None, M_out=None, ws=No
                                   _dev(norms_dev, "norms_dev", 8), _dev(H_out, "H_out", N3),
                                   _dev(M_out, "M_out", 3 * N3),
                                   _dev(ws, "ws", cosmos_workspace_bytes(grid), dtype=torch.uint8), _stream(stream)))
+
+
+# ---- massless scalar field: s is a (2, nz, ny, nx) float64 device tensor (phi, Pi)
+def cosmos_scalar_workspace_bytes(grid: cosmos_grid) -> int:
+    return int(lib.cosmos_scalar_workspace_bytes(ctypes.byref(grid)))
+
+
+def cosmos_init_fields_scalar(grid, params, init, sc_mu: float, sc_sigma: float, u, s, stream=None):
+    n = npts(grid)
+    _check(lib.cosmos_init_fields_scalar(ctypes.byref(grid), ctypes.byref(params), ctypes.byref(init), float(sc_mu),
+                                         float(sc_sigma), _dev(u, "u", NFIELDS * n), _dev(s, "s", 2 * n),
+                                         _stream(stream)))
+
+
+def cosmos_rhs_scalar(grid, params, t: float, u, s, dudt, dsdt, ws, sws, stream=None):
+    n = npts(grid)
+    _check(lib.cosmos_rhs_scalar(ctypes.byref(grid), ctypes.byref(params), float(t), _dev(u, "u", NFIELDS * n),
+                                 _dev(s, "s", 2 * n), _dev(dudt, "dudt", NFIELDS * n), _dev(dsdt, "dsdt", 2 * n),
+                                 _dev(ws, "ws", cosmos_workspace_bytes(grid), dtype=torch.uint8),
+                                 _dev(sws, "sws", cosmos_scalar_workspace_bytes(grid), dtype=torch.uint8),
+                                 _stream(stream)))
+
+
+def cosmos_rk4_step_scalar(grid, params, t: float, dt: float, u, s, ws, sws, stream=None):
+    n = npts(grid)
+    _check(lib.cosmos_rk4_step_scalar(ctypes.byref(grid), ctypes.byref(params), float(t), float(dt),
+                                      _dev(u, "u", NFIELDS * n), _dev(s, "s", 2 * n),
+                                      _dev(ws, "ws", cosmos_workspace_bytes(grid), dtype=torch.uint8),
+                                      _dev(sws, "sws", cosmos_scalar_workspace_bytes(grid), dtype=torch.uint8),
+                                      _stream(stream)))
+
+
+def cosmos_constraints_scalar(grid, params, u, s, norms_dev, H_out=None, M_out=None, ws=None, sws=None, stream=None):
+    n = npts(grid)
+    _check(lib.cosmos_constraints_scalar(ctypes.byref(grid), ctypes.byref(params), _dev(u, "u", NFIELDS * n),
+                                         _dev(s, "s", 2 * n), _dev(norms_dev, "norms_dev", 8),
+                                         _dev(H_out, "H_out", n), _dev(M_out, "M_out", 3 * n),
+                                         _dev(ws, "ws", cosmos_workspace_bytes(grid), dtype=torch.uint8),
+                                         _dev(sws, "sws", cosmos_scalar_workspace_bytes(grid), dtype=torch.uint8),
+                                         _stream(stream)))
 
 
 def cosmos_adjoint_workspace_bytes(grid: cosmos_grid) -> int:

@@ -50,7 +50,12 @@ struct DevParams {
   double i24h[3];   // 1 / (24 h_a)
   double ih[3];     // 1 / h_a
   int fluid_scheme; // 0: centred 4th-order flux divergence + KO; 1: Kurganov-Tadmor (divergence from its pre-pass)
+  // scalar-field sources of the geometry (null without a scalar field): kScalarSrc arrays of fs
+  // doubles, [SRC_EPS] E + S, [SRC_E] E, [SRC_S + j] S_j, [SRC_SIJ + s] S_ij (physical densities)
+  const double* xsrc;
 };
+
+constexpr int SRC_EPS = 0, SRC_E = 1, SRC_S = 2, SRC_SIJ = 5, kScalarSrc = 11;
 
 // Brick decomposition of the grid for the stage kernel: a workgroup of
 // bx*by*bz (= 256) threads owns one bx x by x bz brick, one point per thread
@@ -709,7 +714,8 @@ __device__ __forceinline__ void bssn_rhs_stream(const double* U, const double* F
     const double ix = R[R_IX], pr = R[R_P];
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
-      const double Sij = R[R_S + SI(s)] * R[R_S + SJ(s)] * ix + pr * gt[s] * ichi;
+      double Sij = R[R_S + SI(s)] * R[R_S + SJ(s)] * ix + pr * gt[s] * ichi;
+      if (P.xsrc) Sij += ldq(P.xsrc + (SRC_SIJ + s) * fs, c);
       R[R_X + s] = -DDa[s] + alpha * (R[R_RIC + s] - 8.0 * PI_D * Sij);
     }
 #pragma unroll
@@ -745,7 +751,9 @@ __device__ __forceinline__ void bssn_rhs_stream(const double* U, const double* F
     const double AA = contract_sym(At, Aup);
     const double Str = (R[R_SUP + 0] * R[R_S + 0] + R[R_SUP + 1] * R[R_S + 1] + R[R_SUP + 2] * R[R_S + 2]) * R[R_IX] +
                        3.0 * R[R_P];
-    sink.put(F_K, r_adv + (-R[R_D2A] + alpha * (AA + K * K * (1.0 / 3.0)) + 4.0 * PI_D * alpha * (R[R_E] + Str)));
+    double EpS = R[R_E] + Str;
+    if (P.xsrc) EpS += ldq(P.xsrc + SRC_EPS * fs, c);
+    sink.put(F_K, r_adv + (-R[R_D2A] + alpha * (AA + K * K * (1.0 / 3.0)) + 4.0 * PI_D * alpha * EpS));
   }
 
   // ---- traceless extrinsic curvature
@@ -794,8 +802,11 @@ __device__ __forceinline__ void bssn_rhs_stream(const double* U, const double* F
     double inner = contract_sym(Gu, Aup);
     inner -= (1.5 / chi) * (Aup[S(i, 0)] * R[R_DCHI + 0] + Aup[S(i, 1)] * R[R_DCHI + 1] + Aup[S(i, 2)] * R[R_DCHI + 2]);
     r += 2.0 * alpha * inner;
-    r -= 16.0 * PI_D * alpha *
-         (R[R_GI + S(i, 0)] * R[R_S + 0] + R[R_GI + S(i, 1)] * R[R_S + 1] + R[R_GI + S(i, 2)] * R[R_S + 2]);
+    double Sj[3] = {R[R_S + 0], R[R_S + 1], R[R_S + 2]};
+    if (P.xsrc)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) Sj[j] += ldq(P.xsrc + (SRC_S + j) * fs, c);
+    r -= 16.0 * PI_D * alpha * (R[R_GI + S(i, 0)] * Sj[0] + R[R_GI + S(i, 1)] * Sj[1] + R[R_GI + S(i, 2)] * Sj[2]);
     sink.put(F_GAM + i, r);
   }
 

@@ -224,7 +224,7 @@ __device__ __forceinline__ void lds_carry_fill(LdsCarry<B, Pre>& cy, const doubl
 // whose point lies inside the grid. On entry `cy` holds this brick's ring,
 // epilogue operands and point values; if nx.valid, on return it holds those of
 // the next brick (loaded during the last phases of this one).
-template <class B, bool KT, class Sink, class Pre>
+template <class B, bool KT, bool SC, class Sink, class Pre>
 __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, size_t fs, const DevParams& P, double t,
                                              int c, bool active, LdsCarry<B, Pre>& cy, const NextBrick<B>& nx,
                                              double* buf0, double* buf1, Sink& sink, bool& prim_fail) {
@@ -465,7 +465,8 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
     const double ix = R[R3_IX], pr = R[R3_P];
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
-      const double Sij = R[R3_S + SI(s)] * R[R3_S + SJ(s)] * ix + pr * gt[s] * ichi;
+      double Sij = R[R3_S + SI(s)] * R[R3_S + SJ(s)] * ix + pr * gt[s] * ichi;
+      if constexpr (SC) Sij += bld(field_ptr(P.xsrc, SRC_SIJ + s, fs), nbytes, (uint32_t)c * 8u);
       R[R3_RX + s] = -DDa[s] + alpha * (R[R3_RX + s] - 8.0 * PI_D * Sij);
     }
 #pragma unroll
@@ -501,8 +502,9 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
     }
     const double AA = contract_sym(At, Aup);
     const double Str = (Sup[0] * R[R3_S + 0] + Sup[1] * R[R3_S + 1] + Sup[2] * R[R3_S + 2]) * R[R3_IX] + 3.0 * R[R3_P];
-    sink.put(F_K, d.advko + (-R[R3_D2A] + alpha * (AA + K * K * (1.0 / 3.0)) + 4.0 * PI_D * alpha * (R[R3_E] + Str)),
-             ep[0][0]);
+    double EpS = R[R3_E] + Str;
+    if constexpr (SC) EpS += bld(field_ptr(P.xsrc, SRC_EPS, fs), nbytes, (uint32_t)c * 8u);
+    sink.put(F_K, d.advko + (-R[R3_D2A] + alpha * (AA + K * K * (1.0 / 3.0)) + 4.0 * PI_D * alpha * EpS), ep[0][0]);
     // Gt^i: every remaining term
     const double divb = R[R3_DB + 0] + R[R3_DB + 4] + R[R3_DB + 8];
 #pragma unroll
@@ -526,7 +528,14 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
       double inner = contract_sym(Gu, Aup);
       inner -= (1.5 * ichi) * (Aup[S(i, 0)] * R[R3_DCHI + 0] + Aup[S(i, 1)] * R[R3_DCHI + 1] + Aup[S(i, 2)] * R[R3_DCHI + 2]);
       r += 2.0 * alpha * inner;
-      r -= 16.0 * PI_D * alpha * (gi[S(i, 0)] * R[R3_S + 0] + gi[S(i, 1)] * R[R3_S + 1] + gi[S(i, 2)] * R[R3_S + 2]);
+      if constexpr (SC) {
+        double Sj[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) Sj[j] = R[R3_S + j] + bld(field_ptr(P.xsrc, SRC_S + j, fs), nbytes, (uint32_t)c * 8u);
+        r -= 16.0 * PI_D * alpha * (gi[S(i, 0)] * Sj[0] + gi[S(i, 1)] * Sj[1] + gi[S(i, 2)] * Sj[2]);
+      } else {
+        r -= 16.0 * PI_D * alpha * (gi[S(i, 0)] * R[R3_S + 0] + gi[S(i, 1)] * R[R3_S + 1] + gi[S(i, 2)] * R[R3_S + 2]);
+      }
       sink.put(F_GAM + i, r, ep[0][1 + i]);
     }
   }

@@ -35,6 +35,12 @@ __device__ __forceinline__ void constraint_point(const double* __restrict__ U, s
   inv_sym(gt, gi);
   Fluid fl;
   recover(P.w, chi, gi, ldq(U + F_ET * fs, c), St, fl);
+  if (P.xsrc) {  // scalar field: its energy and momentum densities join the fluid's
+    fl.E += ldq(P.xsrc + SRC_E * fs, c);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) fl.S[i] += ldq(P.xsrc + (SRC_S + i) * fs, c);
+    nonfinite = nonfinite || !isfinite(fl.E);
+  }
   const double nob[3] = {0.0, 0.0, 0.0};
 
   double dgt[6][3], Ric[6];

@@ -18,6 +18,7 @@
 #include "constraints_device.hpp"
 #include "bssn_lds.hpp"
 #include "kt_device.hpp"
+#include "scalar_device.hpp"
 #include "adjoint_point.hpp"
 
 using namespace cosmos;
@@ -154,6 +155,7 @@ DevParams dev_params(const cosmos_grid* g, const cosmos_params* p) {
     d.ih[a] = 1.0 / h[a];
   }
   d.fluid_scheme = p->fluid_scheme;
+  d.xsrc = nullptr;
   d.i144[0] = 1.0 / (144.0 * h[0] * h[1]);
   d.i144[1] = 1.0 / (144.0 * h[0] * h[2]);
   d.i144[2] = 1.0 / (144.0 * h[1] * h[2]);
@@ -248,7 +250,7 @@ __global__ __launch_bounds__(kBlock) void k_bssn_stage(const double* U, const do
 // it * gridDim.x (gridDim.x a multiple of 8, so with the XCD-aware order every
 // brick of a workgroup lies in its XCD's slab), prefetching each next brick
 // during the last phases of the current one.
-template <int BX, int BY, int BZ, int MODE, bool KT>
+template <int BX, int BY, int BZ, int MODE, bool KT, bool SC = false>
 __global__ __launch_bounds__(kBlock) void k_bssn_stage_lds(const double* U, const double* F, const double* un,
                                                             double* acc, double* out, size_t fs, DevParams P, Tile T,
                                                             double t, double ca, double cn,
@@ -314,7 +316,7 @@ __global__ __launch_bounds__(kBlock) void k_bssn_stage_lds(const double* U, cons
     if (nx.valid) HaloCopy<B>::offsets(ni0, nj0, nk0, P.n, nx.goffb);
     Sink sink{un, acc, out, fs, c, ca, cn, P.alpha_collapse};
     bool fail = false;
-    bssn_rhs_lds<B, KT>(U, F, fs, P, t, c, active, cy, nx, smem, smem + B::NP, sink, fail);
+    bssn_rhs_lds<B, KT, SC>(U, F, fs, P, t, c, active, cy, nx, smem, smem + B::NP, sink, fail);
     if (active) {
       nfail += fail;
       if constexpr (MODE == 3) {
@@ -411,7 +413,9 @@ template <int M, bool KT>
 void launch_lds(const Tile& T, hipStream_t s, const double* U, const double* F, const double* un, double* acc,
                 double* out, size_t fs, const DevParams& P, double t, double ca, double cn,
                 unsigned long long* status) {
-  if (T.bx == 16 && T.by == 4) {
+  if (P.xsrc) {  // with the scalar field's sources: the 16x4x4 brick only (checked by launch_stage)
+    launch_persistent(k_bssn_stage_lds<16, 4, 4, M, KT, true>, T, s, U, F, un, acc, out, fs, P, t, ca, cn, status);
+  } else if (T.bx == 16 && T.by == 4) {
     launch_persistent(k_bssn_stage_lds<16, 4, 4, M, KT>, T, s, U, F, un, acc, out, fs, P, t, ca, cn, status);
   } else if (T.bx == 16) {
     launch_persistent(k_bssn_stage_lds<16, 8, 2, M, KT>, T, s, U, F, un, acc, out, fs, P, t, ca, cn, status);
@@ -447,6 +451,8 @@ int launch_stage(const cosmos_params* p, const Tile& T, hipStream_t s, const dou
                (T.bx == 8 && T.by == 8 && T.bz == 4) || (T.bx == 8 && T.by == 4 && T.bz == 8)))
     return set_error(COSMOS_EINVAL, "LDS-staged variant has no %dx%dx%d brick (16x4x4, 16x8x2, 8x8x4, 8x4x8)", T.bx,
                      T.by, T.bz);
+  if (lds && P.xsrc && !(T.bx == 16 && T.by == 4 && T.bz == 4))
+    return set_error(COSMOS_EUNSUPPORTED, "with the scalar field the LDS-staged variant runs the 16x4x4 brick only");
   if (P.fluid_scheme == 1) {
     hipLaunchKernelGGL(k_fluid_kt, dim3(kt_bricks(P)), dim3(kKtThreads), 0, s, U, fs, P, F);
   } else {
@@ -522,7 +528,7 @@ int cosmos_init_fields(const cosmos_grid* grid, const cosmos_params* params, con
       init->density_mode > 1)
     return set_error(COSMOS_EINVAL, "invalid init (sigma > 0, profile 0..2, density_mode 0..1)");
   InitArgs a = make_init_args(grid, params, init);
-  hipLaunchKernelGGL(k_init, dim3(nblocks(grid)), dim3(kBlock), 0, (hipStream_t)stream, a, u, -1);
+  hipLaunchKernelGGL(k_init, dim3(nblocks(grid)), dim3(kBlock), 0, (hipStream_t)stream, a, u, -1, nullptr);
   HIP_TRY(hipGetLastError());
   return COSMOS_OK;
 }
@@ -536,7 +542,7 @@ int cosmos_init_tangent(const cosmos_grid* grid, const cosmos_params* params, co
       init->density_mode > 1)
     return set_error(COSMOS_EINVAL, "invalid init (sigma > 0, profile 0..2, density_mode 0..1)");
   InitArgs a = make_init_args(grid, params, init);
-  hipLaunchKernelGGL(k_init, dim3(nblocks(grid)), dim3(kBlock), 0, (hipStream_t)stream, a, du0, which);
+  hipLaunchKernelGGL(k_init, dim3(nblocks(grid)), dim3(kBlock), 0, (hipStream_t)stream, a, du0, which, nullptr);
   HIP_TRY(hipGetLastError());
   return COSMOS_OK;
 }
@@ -623,3 +629,4 @@ int cosmos_constraints(const cosmos_grid* grid, const cosmos_params* params, con
 
 #include "batch.hip.inc"
 #include "adjoint.hip.inc"
+#include "scalar.hip.inc"

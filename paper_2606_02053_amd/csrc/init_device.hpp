@@ -23,6 +23,7 @@ struct InitArgs {
   double mu, sigma, center[3], noise;
   uint64_t seed;
   int profile, density_mode;
+  double sc_mu, sc_sigma;  // iso-curvature mode of the scalar field (sc_mu = 0: none)
 };
 
 inline InitArgs make_init_args(const cosmos_grid* g, const cosmos_params* p, const cosmos_init* in) {
@@ -40,6 +41,8 @@ inline InitArgs make_init_args(const cosmos_grid* g, const cosmos_params* p, con
   a.seed = in->seed;
   a.profile = in->profile;
   a.density_mode = in->density_mode;
+  a.sc_mu = 0.0;
+  a.sc_sigma = 1.0;
   return a;
 }
 
@@ -75,7 +78,51 @@ __device__ __forceinline__ uint64_t sm64(uint64_t seed, uint64_t p) {
 }
 
 // which = -1: write the initial data; 0 / 1: write its derivative in mu / sigma.
-__global__ __launch_bounds__(256) void k_init(InitArgs a, double* __restrict__ u, int which) {
+// Profile f = mu * shape(x) (x relative to the centre): value, Laplacian and
+// |grad f|^2 in closed form. 0: Gaussian mu exp(-r^2 / 2 sigma^2); 1: single mode
+// mu sin(2 pi x / L_x); 2: Gaussian in s_a = (L_a / pi) sin(pi x_a / L_a).
+__device__ __forceinline__ void profile_tan(const InitArgs& a, int profile, Tan mu, Tan sg, const double x[3], Tan& val,
+                                            Tan& lap, Tan& grad2) {
+  if (profile == 0) {  // Gaussian
+    const double r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+    const Tan s2 = sg * sg;
+    val = mu * texp(tc(-r2) / (2.0 * s2));
+    lap = val * (tc(r2) / (s2 * s2) - tc(3.0) / s2);
+    grad2 = val * val * tc(r2) / (s2 * s2);
+  } else if (profile == 1) {  // single sinusoidal mode along x
+    const double kx = 2.0 * PI_D / a.L[0];
+    const double sn = sin(kx * x[0]), cs = cos(kx * x[0]);
+    val = mu * tc(sn);
+    lap = tc(-kx * kx) * val;
+    grad2 = mu * mu * tc(kx * kx * cs * cs);
+  } else {  // Gaussian in s_a = (L_a / pi) sin(pi x_a / L_a)
+    const Tan s2 = sg * sg;
+    double sa[3], ca[3], kk[3], q2 = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      kk[d] = PI_D / a.L[d];
+      sa[d] = sin(kk[d] * x[d]) / kk[d];
+      ca[d] = cos(kk[d] * x[d]);
+      q2 += sa[d] * sa[d];
+    }
+    val = mu * texp(tc(-q2) / (2.0 * s2));
+    Tan l = tc(0.0), gg = tc(0.0);
+    for (int d = 0; d < 3; ++d) {
+      // d_a f = -f s c / sigma^2;  d_a^2 f = f (s c)^2 / sigma^4 - f (c^2 - k^2 s^2) / sigma^2
+      const double sc = sa[d] * ca[d];
+      l = l + val * tc(sc * sc) / (s2 * s2) - val * tc(ca[d] * ca[d] - kk[d] * kk[d] * sa[d] * sa[d]) / s2;
+      gg = gg + val * val * tc(sc * sc) / (s2 * s2);
+    }
+    lap = l;
+    grad2 = gg;
+  }
+}
+
+// which = -1: the state; 0 / 1: its derivative with respect to mu / sigma. With a
+// scalar field (sc non-null, a.sc_mu != 0) its iso-curvature mode Upsilon = sc_mu *
+// profile(sc_sigma) sets phi = Upsilon, Pi = 0, and the fluid takes the rest of the
+// Hamiltonian constraint's energy: E_fluid = E - 1/2 chi |grad Upsilon|^2.
+__global__ __launch_bounds__(256) void k_init(InitArgs a, double* __restrict__ u, int which,
+                                              double* __restrict__ sc) {
   const size_t N3 = (size_t)a.n[0] * a.n[1] * a.n[2];
   const size_t p = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (p >= N3) return;
@@ -87,43 +134,18 @@ __global__ __launch_bounds__(256) void k_init(InitArgs a, double* __restrict__ u
   const Tan mu = {a.mu, which == 0 ? 1.0 : 0.0};
   const Tan sg = {a.sigma, which == 1 ? 1.0 : 0.0};
   Tan zeta, lap, grad2;
-  if (a.profile == 0) {  // Gaussian
-    const double r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
-    const Tan s2 = sg * sg;
-    zeta = mu * texp(tc(-r2) / (2.0 * s2));
-    lap = zeta * (tc(r2) / (s2 * s2) - tc(3.0) / s2);
-    grad2 = zeta * zeta * tc(r2) / (s2 * s2);
-  } else if (a.profile == 1) {  // single sinusoidal mode along x
-    const double kx = 2.0 * PI_D / a.L[0];
-    const double sn = sin(kx * x[0]), cs = cos(kx * x[0]);
-    zeta = mu * tc(sn);
-    lap = tc(-kx * kx) * zeta;
-    grad2 = mu * mu * tc(kx * kx * cs * cs);
-  } else {  // Gaussian in s_a = (L_a / pi) sin(pi x_a / L_a)
-    const Tan s2 = sg * sg;
-    double sa[3], ca[3], kk[3], q2 = 0.0;
-    for (int d = 0; d < 3; ++d) {
-      kk[d] = PI_D / a.L[d];
-      sa[d] = sin(kk[d] * x[d]) / kk[d];
-      ca[d] = cos(kk[d] * x[d]);
-      q2 += sa[d] * sa[d];
-    }
-    zeta = mu * texp(tc(-q2) / (2.0 * s2));
-    Tan l = tc(0.0), gg = tc(0.0);
-    for (int d = 0; d < 3; ++d) {
-      // d_a zeta = -zeta s c / sigma^2;  d_a^2 zeta = zeta (s c)^2 / sigma^4 - zeta (c^2 - k^2 s^2) / sigma^2
-      const double sc = sa[d] * ca[d];
-      l = l + zeta * tc(sc * sc) / (s2 * s2) - zeta * tc(ca[d] * ca[d] - kk[d] * kk[d] * sa[d] * sa[d]) / s2;
-      gg = gg + zeta * zeta * tc(sc * sc) / (s2 * s2);
-    }
-    lap = l;
-    grad2 = gg;
-  }
+  profile_tan(a, a.profile, mu, sg, x, zeta, lap, grad2);
   const Tan chi = texp(-2.0 * zeta);
   const Tan R = tc(0.0) - chi * (4.0 * lap + 2.0 * grad2);
   const double K = -3.0 * a.H0;
   Tan E = (a.density_mode == 0) ? (R + tc((2.0 / 3.0) * K * K)) / tc(16.0 * PI_D)
                                 : tc(3.0 * a.H0 * a.H0 / (8.0 * PI_D));
+  Tan ups = tc(0.0);
+  if (a.sc_mu != 0.0) {
+    Tan ulap, ug2;
+    profile_tan(a, a.profile, tc(a.sc_mu), tc(a.sc_sigma), x, ups, ulap, ug2);
+    if (a.density_mode == 0) E = E - (0.5 * chi) * ug2;
+  }
   if (a.noise != 0.0) {
     const double xi = 2.0 * ((double)(sm64(a.seed, p) >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
     E = E * tc(1.0 + a.noise * xi);
@@ -138,6 +160,10 @@ __global__ __launch_bounds__(256) void k_init(InitArgs a, double* __restrict__ u
   if (!tangent) out[F_GT + 0] = out[F_GT + 3] = out[F_GT + 5] = 1.0;
   out[F_ET] = tangent ? Et.d : Et.v;
   for (int f = 0; f < NF; ++f) u[(size_t)f * N3 + p] = out[f];
+  if (sc) {
+    sc[p] = tangent ? ups.d : ups.v;
+    sc[N3 + p] = 0.0;
+  }
 }
 
 }  // namespace cosmos

@@ -1,0 +1,114 @@
+// Massless scalar field (the second matter field of the paper's "Physical
+// system settings": stress tensor d phi d phi - 1/2 g (d phi)^2 and wave
+// equation box phi = 0), evolved as phi and Pi = n^mu d_mu phi in a separate
+// 2-field state (field-major: phi, then Pi). The 3+1 form of box phi = 0:
+//   d_t phi = alpha Pi + beta^k d_k phi,
+//   d_t Pi  = beta^k d_k Pi + alpha K Pi + alpha chi (gt^ij d_i d_j phi - (Gd^k + gt^kl d_l chi / 2 chi) d_k phi)
+//             + chi gt^ij d_i alpha d_j phi,
+// plus Kreiss-Oliger dissipation on both fields; its normal-frame densities,
+// the sources it adds to the geometry:
+//   E = 1/2 (Pi^2 + |D phi|^2), S = 3/2 Pi^2 - 1/2 |D phi|^2, S_j = -Pi d_j phi,
+//   S_ij = d_i phi d_j phi - 1/2 (gt_ij / chi) (|D phi|^2 - Pi^2),  |D phi|^2 = chi gt^ij d_i phi d_j phi.
+#pragma once
+#include "bssn_device.hpp"
+
+namespace cosmos {
+
+// One RK4 stage of the scalar field from the stage state (U, Sc), one thread per
+// point with direct loads; also writes the geometry's source arrays `src`
+// (kScalarSrc x fs doubles, layout of DevParams::xsrc) for the stage kernel that
+// follows. MODE as the stage kernel's epilogue: 0 sout = f; 1 sacc = Sc + ca f,
+// sout = Sc + cn f; 2 sacc += ca f, sout = sun + cn f; 3 sout = sacc + ca f.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_scalar_stage(const double* __restrict__ U, const double* __restrict__ Sc,
+                                                      double* __restrict__ src, const double* __restrict__ sun,
+                                                      double* __restrict__ sacc, double* __restrict__ sout, size_t fs,
+                                                      DevParams P, double ca, double cn) {
+  const size_t p = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= fs) return;
+  const int i = (int)(p % P.n[0]), j = (int)((p / P.n[0]) % P.n[1]), k = (int)(p / ((size_t)P.n[0] * P.n[1]));
+  Nbr nb;
+  make_nbr(nb, i, j, k, P.n);
+  const int c = (int)p;
+  const double chi = ldq(U + F_CHI * fs, c), K = ldq(U + F_K * fs, c), alpha = ldq(U + F_ALP * fs, c);
+  double gt[6], gi[6], beta[3];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) gt[s] = ldq(U + (F_GT + s) * fs, c);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) beta[a] = ldq(U + (F_BET + a) * fs, c);
+  inv_sym(gt, gi);
+  const double nob[3] = {0.0, 0.0, 0.0};
+  // metric connection Gd^k (and its quadratic Ricci terms, not needed here)
+  double dgt[6][3];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    FieldDerivs d;
+    field_derivs<false, false, false>(U + (F_GT + s) * fs, nb, P, nob, d);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) dgt[s][a] = d.d1[a];
+  }
+  double Gu[3][6], Gd[3], Ric[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  connection_and_quadratic_ricci(dgt, gi, Gu, Gd, Ric);
+  double dchi[3], dal[3];
+  {
+    FieldDerivs d;
+    field_derivs<false, false, false>(U + F_CHI * fs, nb, P, nob, d);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) dchi[a] = d.d1[a];
+    field_derivs<false, false, false>(U + F_ALP * fs, nb, P, nob, d);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) dal[a] = d.d1[a];
+  }
+  FieldDerivs dphi;
+  field_derivs<true, true, true>(Sc, nb, P, beta, dphi);  // d1, d2, upwind advection + KO of phi
+  double d1pi[3];
+  const double advko_pi = field_advko<true>(Sc + fs, nb, P, beta, d1pi);
+  const double Pi = ldq(Sc + fs, c);
+
+  // sources of the geometry
+  double dd[6];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) dd[s] = dphi.d1[SI(s)] * dphi.d1[SJ(s)];
+  const double g2 = chi * contract_sym(gi, dd);
+  const double P2 = Pi * Pi;
+  const double E = 0.5 * (P2 + g2);
+  const double Str = 1.5 * P2 - 0.5 * g2;
+  stq(src + SRC_EPS * fs, c, E + Str);
+  stq(src + SRC_E * fs, c, E);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) stq(src + (SRC_S + a) * fs, c, -Pi * dphi.d1[a]);
+  const double ichi = 1.0 / chi;
+#pragma unroll
+  for (int s = 0; s < 6; ++s) stq(src + (SRC_SIJ + s) * fs, c, dd[s] - 0.5 * (gt[s] * ichi) * (g2 - P2));
+
+  // right-hand side of (phi, Pi)
+  double lap = contract_sym(gi, dphi.d2);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double gk = Gd[a] + (gi[S(a, 0)] * dchi[0] + gi[S(a, 1)] * dchi[1] + gi[S(a, 2)] * dchi[2]) * (0.5 * ichi);
+    lap -= gk * dphi.d1[a];
+  }
+  double dad = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    dad += dal[a] * (gi[S(a, 0)] * dphi.d1[0] + gi[S(a, 1)] * dphi.d1[1] + gi[S(a, 2)] * dphi.d1[2]);
+  const double r[2] = {alpha * Pi + dphi.advko, ((alpha * K * Pi + alpha * chi * lap) + chi * dad) + advko_pi};
+#pragma unroll
+  for (int f = 0; f < 2; ++f) {
+    const size_t q = (size_t)f * fs + p;
+    if constexpr (MODE == 0) {
+      sout[q] = r[f];
+    } else if constexpr (MODE == 1) {
+      const double s0 = Sc[q];
+      sacc[q] = s0 + ca * r[f];
+      sout[q] = s0 + cn * r[f];
+    } else if constexpr (MODE == 2) {
+      sacc[q] = sacc[q] + ca * r[f];
+      sout[q] = sun[q] + cn * r[f];
+    } else {
+      sout[q] = sacc[q] + ca * r[f];
+    }
+  }
+}
+
+}  // namespace cosmos

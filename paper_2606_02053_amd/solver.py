@@ -8,7 +8,11 @@ from . import _lib as C
 
 
 class Solver:
-    def __init__(self, n, L, params: C.cosmos_params | None = None, device: str = "cuda"):
+    """With scalar=True the run also carries the massless scalar field: ``s`` holds
+    (phi, Pi), and init / rhs / step / constraints go through the scalar entry points
+    (rhs then returns (dudt, dsdt))."""
+
+    def __init__(self, n, L, params: C.cosmos_params | None = None, device: str = "cuda", scalar: bool = False):
         self.grid = C.make_grid(n, L)
         self.params = params if params is not None else C.make_params()
         self.device = torch.device(device)
@@ -18,6 +22,10 @@ class Solver:
         self.ws = torch.empty(C.cosmos_workspace_bytes(self.grid), dtype=torch.uint8, device=self.device)
         self.norms = torch.empty(8, dtype=torch.float64, device=self.device)
         self.t = 0.0
+        self.scalar = scalar
+        if scalar:
+            self.s = torch.zeros((2, nz, ny, nx), dtype=torch.float64, device=self.device)
+            self.sws = torch.empty(C.cosmos_scalar_workspace_bytes(self.grid), dtype=torch.uint8, device=self.device)
         C.cosmos_status_reset(self.ws)
 
     @property
@@ -27,23 +35,37 @@ class Solver:
     def default_dt(self, cfl: float = 0.25) -> float:
         return cfl * min(self.h)
 
-    def init(self, **kw):
-        C.cosmos_init_fields(self.grid, self.params, C.make_init(**kw), self.u)
+    def init(self, sc_mu: float = 0.0, sc_sigma: float = 1.0, **kw):
+        """Initial data; with the scalar field, sc_mu and sc_sigma give its iso-curvature mode."""
+        if self.scalar:
+            C.cosmos_init_fields_scalar(self.grid, self.params, C.make_init(**kw), sc_mu, sc_sigma, self.u, self.s)
+        else:
+            C.cosmos_init_fields(self.grid, self.params, C.make_init(**kw), self.u)
         self.t = 0.0
         return self.u
 
-    def set_state(self, u: torch.Tensor, t: float = 0.0):
+    def set_state(self, u: torch.Tensor, t: float = 0.0, s: torch.Tensor | None = None):
         self.u.copy_(u.to(self.device, torch.float64).reshape(self.shape))
+        if s is not None:
+            self.s.copy_(s.to(self.device, torch.float64).reshape(self.s.shape))
         self.t = t
 
-    def rhs(self, t: float | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
+    def rhs(self, t: float | None = None, out: torch.Tensor | None = None):
         out = torch.empty_like(self.u) if out is None else out
-        C.cosmos_rhs(self.grid, self.params, self.t if t is None else t, self.u, out, self.ws)
+        t = self.t if t is None else t
+        if self.scalar:
+            ds = torch.empty_like(self.s)
+            C.cosmos_rhs_scalar(self.grid, self.params, t, self.u, self.s, out, ds, self.ws, self.sws)
+            return out, ds
+        C.cosmos_rhs(self.grid, self.params, t, self.u, out, self.ws)
         return out
 
     def step(self, dt: float | None = None):
         dt = self.default_dt() if dt is None else dt
-        C.cosmos_rk4_step(self.grid, self.params, self.t, dt, self.u, self.ws)
+        if self.scalar:
+            C.cosmos_rk4_step_scalar(self.grid, self.params, self.t, dt, self.u, self.s, self.ws, self.sws)
+        else:
+            C.cosmos_rk4_step(self.grid, self.params, self.t, dt, self.u, self.ws)
         self.t += dt
 
     def run(self, nsteps: int, dt: float | None = None):
@@ -56,7 +78,10 @@ class Solver:
             N = self.shape[1:]
             H = torch.empty(N, dtype=torch.float64, device=self.device)
             M = torch.empty((3,) + N, dtype=torch.float64, device=self.device)
-        C.cosmos_constraints(self.grid, self.params, self.u, self.norms, H, M, self.ws)
+        if self.scalar:
+            C.cosmos_constraints_scalar(self.grid, self.params, self.u, self.s, self.norms, H, M, self.ws, self.sws)
+        else:
+            C.cosmos_constraints(self.grid, self.params, self.u, self.norms, H, M, self.ws)
         norms = self.norms.cpu()
         return (norms, H, M) if want_fields else norms
 

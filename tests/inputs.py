@@ -73,3 +73,25 @@ def sample_points(n, count, seed):
     while len(pts) < min(count, N3):
         pts.add(int(rng.integers(0, N3)))
     return np.array(sorted(pts), dtype=np.int64)
+
+
+def fuzz_scalar(n, seed, kmax=2, modes=3, amp=(0.2, 0.1)):
+    """Smooth periodic random (phi, Pi) of shape (2, nz, ny, nx): Fourier modes about 0."""
+    nx, ny, nz = n
+    rng = np.random.default_rng(seed)
+    i = np.arange(nx)[None, None, :] / nx
+    j = np.arange(ny)[None, :, None] / ny
+    k = np.arange(nz)[:, None, None] / nz
+    s = np.zeros((2, nz, ny, nx))
+    for f in range(2):
+        wsum = 0.0
+        for _ in range(modes):
+            m = rng.integers(-kmax, kmax + 1, size=3)
+            if not m.any():
+                m[0] = 1
+            a = rng.uniform(0.5, 1.0)
+            ph = rng.uniform(0, 2 * np.pi)
+            s[f] += a * np.sin(2 * np.pi * (m[0] * i + m[1] * j + m[2] * k) + ph)
+            wsum += a
+        s[f] *= amp[f] / wsum
+    return s

@@ -115,3 +115,29 @@ def test_stage_keeping_entry_points_validate_on_host(C):
     rc = lib.cosmos_adjoint_step_stages(ctypes.byref(g), ctypes.byref(p), 0.0, 0.1, u, ctypes.c_void_p(0x20000000 + 8),
                                         u, lam, ws, None)
     assert rc == C.COSMOS_EINVAL and "overlaps" in C.last_error()
+
+
+def test_scalar_entry_points_validate_on_host(C):
+    g = C.make_grid(16, 4.0)
+    p = C.make_params()
+    lib = C.lib
+    assert C.cosmos_scalar_workspace_bytes(g) >= 17 * 16 ** 3 * 8
+    assert C.cosmos_scalar_workspace_bytes(C.make_grid((7, 16, 16), 4.0)) == 0
+    base = 0x100000
+    n = 16 ** 3 * 8
+    u, s, ws, sws = (ctypes.c_void_p(base), ctypes.c_void_p(base + 25 * n), ctypes.c_void_p(base + 64 * n),
+                     ctypes.c_void_p(base + 128 * n))
+    rc = lib.cosmos_rk4_step_scalar(ctypes.byref(g), ctypes.byref(p), 0.0, 0.1, u, s, ws, None, None)
+    assert rc == C.COSMOS_EINVAL and "scalar workspace" in C.last_error()
+    rc = lib.cosmos_rk4_step_scalar(ctypes.byref(g), ctypes.byref(p), 0.0, 0.1, u, ctypes.c_void_p(base + 8 * n), ws,
+                                    sws, None)
+    assert rc == C.COSMOS_EINVAL and "overlap" in C.last_error()
+    q = C.make_params(tile=(8, 8, 4))
+    rc = lib.cosmos_rk4_step_scalar(ctypes.byref(g), ctypes.byref(q), 0.0, 0.1, u, s, ws, sws, None)
+    assert rc == C.COSMOS_EUNSUPPORTED and "16x4x4" in C.last_error()
+    rc = lib.cosmos_rhs_scalar(ctypes.byref(g), ctypes.byref(p), 0.0, u, s, u, ctypes.c_void_p(base + 200 * n), ws,
+                               sws, None)
+    assert rc == C.COSMOS_EINVAL and "overlap" in C.last_error()
+    ini = C.make_init()
+    rc = lib.cosmos_init_fields_scalar(ctypes.byref(g), ctypes.byref(p), ctypes.byref(ini), 0.1, 0.0, u, s, None)
+    assert rc == C.COSMOS_EINVAL

@@ -1,0 +1,123 @@
+"""GPU parity of the massless scalar field (phi, Pi) against the oracle, through
+the C ABI: initial data with an iso-curvature mode, right-hand side (both stage
+kernel variants, both fluid schemes), RK4 steps, 100 steps of an iso-curvature
+run, constraints. Metric as in test_gpu_parity (per-field max error over
+max |oracle|, floor 1e-3), applied to the 25 geometry/fluid fields and the 2
+scalar fields separately."""
+import numpy as np
+import pytest
+import torch
+
+from tests.inputs import fuzz_scalar, fuzz_state
+from tests.test_gpu_parity import err_fields, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def err2(gpu, ref):
+    gpu = np.asarray(gpu).reshape(2, -1)
+    ref = np.asarray(ref).reshape(2, -1)
+    d = np.abs(gpu - ref).max(axis=1)
+    s = np.maximum(np.abs(ref).max(axis=1), 1e-3)
+    return (d / s).max(), d / s
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2606_02053_amd as P
+    assert torch.cuda.is_available()
+    return P
+
+
+def mk(P, orc, n, L, **kw):
+    return orc.Setup(n=n, L=L, **kw), P.Solver(n, L, P.make_params(**kw), scalar=True)
+
+
+@pytest.mark.parametrize("profile", [0, 2])
+def test_scalar_init_parity(P, orc, profile):
+    n, L = (16, 12, 20), (10.0, 8.0, 12.0)
+    s, sol = mk(P, orc, n, L)
+    ini = dict(mu=0.2, sigma=1.2, noise_amp=1e-6, seed=2606, profile=profile, center=(0.1, -0.2, 0.3))
+    sol.init(sc_mu=0.15, sc_sigma=1.3, **ini)
+    u, sc = orc.init_fields_sc(s, orc.Init(**ini), 0.15, 1.3)
+    assert err_fields(sol.u.cpu().numpy(), u)[0] < 1e-13
+    assert err2(sol.s.cpu().numpy(), sc)[0] < 1e-13
+
+
+@pytest.mark.parametrize("variant,scheme", [(0, 0), (1, 0), (0, 1), (1, 1)])
+@pytest.mark.parametrize("n,L", [((20, 12, 10), (4.0, 2.5, 2.0)), ((32, 32, 32), (10.0, 10.0, 10.0))])
+def test_scalar_rhs(P, orc, n, L, variant, scheme):
+    s, sol = mk(P, orc, n, L, fluid_scheme=scheme)
+    sol.params.variant = variant
+    u, sc = fuzz_state(n, seed=41), fuzz_scalar(n, seed=42)
+    sol.set_state(to_dev(u), s=to_dev(sc))
+    du, ds = sol.rhs(t=0.2)
+    ru, rs, _ = orc.rhs_sc(s, u, sc, t=0.2, parallel=True)
+    e, per = err_fields(du.cpu().numpy(), ru)
+    assert e < 1e-11, per
+    e2, per2 = err2(ds.cpu().numpy(), rs)
+    assert e2 < 1e-11, per2
+
+
+def test_zero_scalar_field_equals_plain_path(P, orc):
+    n, L = (20, 12, 18), (4.0, 2.5, 3.5)
+    u = fuzz_state(n, seed=3)
+    plain = P.Solver(n, L)
+    plain.set_state(to_dev(u))
+    s, sol = mk(P, orc, n, L)
+    sol.set_state(to_dev(u))  # s = 0
+    du, ds = sol.rhs(t=0.1)
+    assert torch.equal(du, plain.rhs(t=0.1)) and not ds.any()
+
+
+def test_scalar_rk4_steps(P, orc):
+    n, L = (16, 12, 14), (3.0, 2.5, 2.8)
+    s, sol = mk(P, orc, n, L)
+    u, sc = fuzz_state(n, seed=5), fuzz_scalar(n, seed=6)
+    sol.set_state(to_dev(u), t=0.1, s=to_dev(sc))
+    dt = 0.25 * min(s.h)
+    sol.step(dt)
+    ru, rs, _ = orc.rk4_sc(s, u, sc, 0.1, dt, 1, parallel=True)
+    assert err_fields(sol.u.cpu().numpy(), ru)[0] < 1e-11
+    assert err2(sol.s.cpu().numpy(), rs)[0] < 1e-11
+    sol.run(9, dt)
+    ru, rs, _ = orc.rk4_sc(s, ru, rs, 0.1 + dt, dt, 9, parallel=True)
+    assert err_fields(sol.u.cpu().numpy(), ru)[0] < 1e-10
+    assert err2(sol.s.cpu().numpy(), rs)[0] < 1e-10
+
+
+def test_isocurvature_hundred_steps_and_constraints(P, orc):
+    """32^3 box of side 10: iso-curvature Gaussian Upsilon (0.15, sigma 1.3) on a small
+    adiabatic zeta (0.05, sigma 1.5), 100 RK4 steps; then the constraints."""
+    n, L = (32, 32, 32), (10.0, 10.0, 10.0)
+    s, sol = mk(P, orc, n, L)
+    ini = dict(mu=0.05, sigma=1.5)
+    sol.init(sc_mu=0.15, sc_sigma=1.3, **ini)
+    u0, sc0 = orc.init_fields_sc(s, orc.Init(**ini), 0.15, 1.3)
+    dt = 0.25 * s.h[0]
+    sol.run(100, dt)
+    ru, rs, _ = orc.rk4_sc(s, u0, sc0, 0.0, dt, 100, parallel=True)
+    e, per = err_fields(sol.u.cpu().numpy(), ru)
+    e2, per2 = err2(sol.s.cpu().numpy(), rs)
+    print(f"iso-curvature parity after 100 steps: fields {e:.3e}, scalar {e2:.3e}")
+    assert e < 1e-9 and e2 < 1e-9, (per, per2)
+    st = sol.status()
+    assert st["steps"] == 100 and st["nonfinite"] == 0 and st["prim_fail"] == 0
+    norms, H, M = sol.constraints(want_fields=True)
+    rn, rH, rM = orc.constraints_sc(s, ru, rs, want_fields=True, parallel=True)
+    assert np.abs(H.cpu().numpy() - rH).max() < 1e-9 * max(np.abs(rH).max(), 1e-3)
+    assert np.abs(M.cpu().numpy() - rM).max() < 1e-9 * max(np.abs(rM).max(), 1e-3)
+    assert abs(norms[0].item() - rn[0]) < 1e-9 * rn[0] and norms[5].item() == rn[5] == 0
+
+
+def test_scalar_constraints_parity(P, orc):
+    n, L = (16, 20, 12), (4.0, 5.0, 3.0)
+    s, sol = mk(P, orc, n, L)
+    u, sc = fuzz_state(n, seed=9), fuzz_scalar(n, seed=10)
+    sol.set_state(to_dev(u), s=to_dev(sc))
+    norms, H, M = sol.constraints(want_fields=True)
+    rn, rH, rM = orc.constraints_sc(s, u, sc, want_fields=True)
+    assert np.abs(H.cpu().numpy() - rH).max() < 1e-11 * np.abs(rH).max()
+    assert np.abs(M.cpu().numpy() - rM).max() < 1e-11 * np.abs(rM).max()
+    np.testing.assert_allclose(norms.numpy()[:5], rn[:5], rtol=1e-11)
+    assert norms[5].item() == rn[5] and norms[7].item() == rn[7]
