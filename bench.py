@@ -8,11 +8,12 @@ Prints one JSON line with the roofline of a stage (algorithmic bytes per stage /
 average stage time, measured with HIP events on the launch stream around the
 timed steps), the CPU oracle timed on a bounded sample of the same workload, and
 the other forms of the metric as sub-objects: "batched" (runs/s of the 64-run
-scan), "adjoint" (cost of the gradient relative to the forward run) and "kt" (the
-headline workload with the Kurganov-Tadmor fluid scheme).
+scan), "adjoint" (cost of the gradient relative to the forward run), "kt" (the
+headline workload with the Kurganov-Tadmor fluid scheme) and "scalar" (with the
+massless scalar field).
 
 Extra modes:
-  --headline-only  skip the batched, adjoint and kt sub-objects
+  --headline-only  skip the batched, adjoint, kt and scalar sub-objects
   --batched      only the 64-run threshold-scan workload (grid sizes drawn from
                  {48, 64, 80, 96}^3, mu in [0.3, 0.8], sigma in [0.8, 1.6], box 12/H0,
                  300 RK4 steps per run): runs/s of the batched, hipGraph-replayed form
@@ -26,6 +27,8 @@ Extra modes:
                  whose centre lapse equals that of mu = 0.4371, against serial bisection
   --kt           only the headline workload with the Kurganov-Tadmor fluid scheme
                  (fluid_scheme 1), against the centred scheme on the same configuration
+  --scalar       only the headline workload with the massless scalar field (iso-curvature mode
+                 0.1 x Gaussian of width 2), against the plain run on the same configuration
   --copy-probe   only a plain device-to-device copy of known size (calibrates
                  rocprofv3 FETCH_SIZE / WRITE_SIZE counters)
   --no-cpu       skip the CPU baseline leg
@@ -71,11 +74,12 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-tune", action="store_true", help="use the default tile instead of the autotuned one")
     ap.add_argument("--batched", action="store_true")
-    ap.add_argument("--headline-only", action="store_true", help="no batched / adjoint / kt sub-objects")
+    ap.add_argument("--headline-only", action="store_true", help="no batched / adjoint / kt / scalar sub-objects")
     ap.add_argument("--batched-steps", type=int, default=30, help="timed steps (runs/s is scaled to 300 steps)")
     ap.add_argument("--adjoint", action="store_true")
     ap.add_argument("--threshold", action="store_true")
     ap.add_argument("--kt", action="store_true", help="only the Kurganov-Tadmor fluid-scheme leg")
+    ap.add_argument("--scalar", action="store_true", help="only the massless-scalar-field leg")
     ap.add_argument("--adjoint-steps", type=int, default=200, help="RK4 steps of the differentiated run")
     ap.add_argument("--no-fd", action="store_true", help="skip the finite-difference check of the adjoint")
     ap.add_argument("--config", default=None,
@@ -272,6 +276,49 @@ def kt_bench(a, kv=0, tile=(16, 4, 4), order=2):
                                    "the fluid)", "kernel_config": config_name(kv, tile, order)}}
 
 
+def scalar_bench(a, kv=0, tile=(16, 4, 4), order=2):
+    """The headline workload with the massless scalar field (iso-curvature mode Upsilon =
+    0.1 x Gaussian of width 2 on the same zeta): RK4 steps per second on 256^3, each stage
+    k_scalar_stage (the field's stage update and its 11 source arrays) + the flux pre-pass +
+    the stage kernel with the sources; timed like the headline, against the plain run on the
+    same configuration."""
+    import paper_2606_02053_amd as P
+    from paper_2606_02053_amd import autotune
+    n, L = a.n, 16.0
+    ms = {}
+    for scalar in (True, False):
+        sol = P.Solver(n, L, autotune.with_tile(P.make_params(), kv, tile, order), scalar=scalar)
+        if scalar:
+            sol.init(mu=0.6, sigma=2.0, sc_mu=0.1, sc_sigma=2.0)
+        else:
+            sol.init(mu=0.6, sigma=2.0)
+        dt = sol.default_dt()
+        for _ in range(a.warmup):
+            sol.step(dt)
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(a.steps):
+            sol.step(dt)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms[scalar] = e0.elapsed_time(e1) / a.steps
+        st = sol.status()
+        if st["nonfinite"] or st["prim_fail"]:
+            raise RuntimeError(f"scalar benchmark run (scalar={scalar}) went bad: {st}")
+        if scalar and not torch.isfinite(sol.s).all():
+            raise RuntimeError("non-finite scalar field in the benchmark run")
+        del sol
+    return {"metric": "grid-point RK4 updates/sec FP64 at 256^3 with the massless scalar field",
+            "value": n ** 3 / (ms[True] / 1e3), "unit": "point-updates/s", "ms_per_step": ms[True],
+            "plain_ms_per_step": ms[False], "cost_vs_plain": ms[True] / ms[False], "steps": a.steps,
+            "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"as the headline ({n}^3, L = 16/H0, zeta mu = 0.6, sigma = 2.0, CFL 0.25) with "
+                                   "the massless scalar field, iso-curvature Upsilon mu = 0.1, sigma = 2.0",
+                       "kernel_config": config_name(kv, tile, order)}}
+
+
 def adjoint_bench(a):
     from paper_2606_02053_amd.adjoint import RunConfig, central_lapse
     import paper_2606_02053_amd as P
@@ -378,6 +425,10 @@ def main():
         kv, tile, order = parse_config(a.config) if a.config else (0, (16, 4, 4), 2)
         print(json.dumps(kt_bench(a, kv, tile, order)), flush=True)
         return
+    if a.scalar:
+        kv, tile, order = parse_config(a.config) if a.config else (0, (16, 4, 4), 2)
+        print(json.dumps(scalar_bench(a, kv, tile, order)), flush=True)
+        return
     import paper_2606_02053_amd as P
     from paper_2606_02053_amd import autotune
     n, L = a.n, 16.0
@@ -433,6 +484,8 @@ def main():
         out["batched"] = batched_bench(a)
         out["adjoint"] = adjoint_bench(a)
         out["kt"] = kt_bench(a, kv, tile, order)
+        # the LDS-staged kernel takes the scalar sources with the 16x4x4 brick only
+        out["scalar"] = scalar_bench(a, kv, (16, 4, 4) if kv == 0 else tile, order)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(a.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -86,6 +86,8 @@ def lib():
             "oracle_rk4_steps_sc": [P, P, P, P, f64, f64, i32, P, P, P, i32],
             "oracle_constraints_sc": [P, P, P, P, P, P, P, P, P, i32],
             "oracle_init_sc": [P, P, P, P, P, P, u64, i32, i32, P, P],
+            "oracle_rhs_sc_at_points": [P, P, P, P, f64, P, P, P, i32, P, P],
+            "oracle_rk4_sc_at_points": [P, P, P, P, f64, f64, P, P, P, i32, P, P],
             "oracle_kt_divergence": [P, P, P, P, P, P],
             "oracle_count_kt_flops": [P, P, P, P, P, P],
             "oracle_fluid_speeds": [P, P, i32, P],
@@ -367,6 +369,28 @@ def constraints_sc(s: Setup, u, sc, want_fields: bool = False, parallel: bool = 
     _check(lib().oracle_constraints_sc(_p(n), _p(L), _p(prm), _p(iprm), _p(u), _p(sc), _p(norms), _p(H), _p(M),
                                        int(parallel)), "oracle_constraints_sc")
     return (norms, H, M) if want_fields else norms
+
+
+def rhs_sc_at_points(s: Setup, u, sc, pts, t: float = 0.0):
+    """Right-hand side with the scalar field at the listed linear indices: ([npts][25], [npts][2])."""
+    n, L, prm, iprm = s.arrays()
+    u, sc = _state(u, s), _scalar(sc, s)
+    pts = np.ascontiguousarray(pts, dtype=np.int64)
+    out, sout = np.empty((len(pts), NF)), np.empty((len(pts), 2))
+    _check(lib().oracle_rhs_sc_at_points(_p(n), _p(L), _p(prm), _p(iprm), t, _p(u), _p(sc), _p(pts), len(pts),
+                                         _p(out), _p(sout)), "oracle_rhs_sc_at_points")
+    return out, sout
+
+
+def rk4_sc_at_points(s: Setup, u, sc, pts, t: float, dt: float):
+    """One RK4 step of (u, sc) evaluated at the listed points only: ([npts][25], [npts][2])."""
+    n, L, prm, iprm = s.arrays()
+    u, sc = _state(u, s), _scalar(sc, s)
+    pts = np.ascontiguousarray(pts, dtype=np.int64)
+    out, sout = np.empty((len(pts), NF)), np.empty((len(pts), 2))
+    _check(lib().oracle_rk4_sc_at_points(_p(n), _p(L), _p(prm), _p(iprm), t, dt, _p(u), _p(sc), _p(pts), len(pts),
+                                         _p(out), _p(sout)), "oracle_rk4_sc_at_points")
+    return out, sout
 
 
 def kt_flux(s: Setup, uL, uR, a: int) -> np.ndarray:

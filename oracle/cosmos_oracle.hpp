@@ -927,7 +927,9 @@ void rk4_step(const Grid& g, const Params& p, double t, double dt, T* u, Status&
 // formed on the window of radius 3*(4-s) around the point: k_s is evaluated on
 // that window from the stage state on the window widened by NG.
 inline void rk4_step_at_points(const Grid& g, const Params& p, double t, double dt, const double* u,
-                               const int64_t* pts, int npts, double* out /* [npts][NF] */, Status& st) {
+                               const int64_t* pts, int npts, double* out /* [npts][NF] */, Status& st,
+                               const double* sc = nullptr, double* sout = nullptr /* [npts][NS] */) {
+  // with the scalar field (sc non-null) its windows follow the same radii as u's
   const double tst[4] = {t, t + dt / 2.0, t + dt / 2.0, t + dt};
   const double cst[3] = {dt / 2.0, dt / 2.0, dt};  // U_{s+1} = u + cst[s] k_s
   for (int q = 0; q < npts; ++q) {
@@ -936,54 +938,72 @@ inline void rk4_step_at_points(const Grid& g, const Params& p, double t, double 
     int r = 3 * NG;  // interior radius of the first stage window
     const int o[3] = {c[0] - r, c[1] - r, c[2] - r};
     const int m[3] = {2 * r + 1, 2 * r + 1, 2 * r + 1};
-    Padded<double> U0;  // u on the widest window (radius 12 with ghosts)
+    Padded<double> U0, S0;  // u (and the scalar) on the widest window (radius 12 with ghosts)
     pad_periodic(g, u, o, m, U0);
-    Padded<double> P = U0;
-    double kc[4][NF];
+    if (sc) pad_periodic(g, sc, o, m, S0, NS);
+    Padded<double> P = U0, Q = S0;
+    double kc[4][NF], ks[4][NS];
     for (int s = 0; s < 4; ++s) {
       const int mw = 2 * r + 1;
       const int64_t M3 = (int64_t)mw * mw * mw;
-      std::vector<double> k((size_t)NF * M3);
-      rhs_padded(g, p, tst[s], P, k.data(), st, false);
-      for (int f = 0; f < NF; ++f) kc[s][f] = k[f * M3 + r + (int64_t)mw * (r + (int64_t)mw * r)];
+      std::vector<double> k((size_t)NF * M3), kq(sc ? (size_t)NS * M3 : 0);
+      rhs_padded(g, p, tst[s], P, k.data(), st, false, sc ? &Q : nullptr, sc ? kq.data() : nullptr);
+      const int64_t mid = r + (int64_t)mw * (r + (int64_t)mw * r);
+      for (int f = 0; f < NF; ++f) kc[s][f] = k[f * M3 + mid];
+      if (sc)
+        for (int f = 0; f < NS; ++f) ks[s][f] = kq[f * M3 + mid];
       if (s == 3) break;
       // next stage: interior radius r - NG; its padded points cover this window
       const int rn = r - NG;
       const int mn[3] = {2 * rn + 1, 2 * rn + 1, 2 * rn + 1};
-      Padded<double> Pn;
+      Padded<double> Pn, Qn;
       Pn.resize(mn);
-      for (int f = 0; f < NF; ++f)
-        for (int kk = -NG; kk < mn[2] + NG; ++kk)
-          for (int jj = -NG; jj < mn[1] + NG; ++jj)
-            for (int ii = -NG; ii < mn[0] + NG; ++ii) {
-              // offsets from the point: (ii - rn, ...); index in this window: + r; in U0: + 3*NG
-              const int I = ii - rn + r, J = jj - rn + r, K = kk - rn + r;
-              const double kv = k[f * M3 + I + (int64_t)mw * (J + (int64_t)mw * K)];
-              const double u0 = U0(f, ii - rn + 3 * NG, jj - rn + 3 * NG, kk - rn + 3 * NG);
-              Pn(f, ii, jj, kk) = u0 + cst[s] * kv;
-            }
+      if (sc) Qn.resize(mn);
+      for (int kk = -NG; kk < mn[2] + NG; ++kk)
+        for (int jj = -NG; jj < mn[1] + NG; ++jj)
+          for (int ii = -NG; ii < mn[0] + NG; ++ii) {
+            // offsets from the point: (ii - rn, ...); index in this window: + r; in U0: + 3*NG
+            const int I = ii - rn + r, J = jj - rn + r, K = kk - rn + r;
+            const int64_t w = I + (int64_t)mw * (J + (int64_t)mw * K);
+            for (int f = 0; f < NF; ++f)
+              Pn(f, ii, jj, kk) = U0(f, ii - rn + 3 * NG, jj - rn + 3 * NG, kk - rn + 3 * NG) + cst[s] * k[f * M3 + w];
+            if (sc)
+              for (int f = 0; f < NS; ++f)
+                Qn(f, ii, jj, kk) = S0(f, ii - rn + 3 * NG, jj - rn + 3 * NG, kk - rn + 3 * NG) + cst[s] * kq[f * M3 + w];
+          }
       P = Pn;
+      if (sc) Q = Qn;
       r = rn;
     }
     for (int f = 0; f < NF; ++f) {
       const double u0 = U0(f, 3 * NG, 3 * NG, 3 * NG);
       out[(size_t)q * NF + f] = u0 + (dt / 6.0) * (kc[0][f] + 2.0 * kc[1][f] + 2.0 * kc[2][f] + kc[3][f]);
     }
+    if (sc)
+      for (int f = 0; f < NS; ++f) {
+        const double s0 = S0(f, 3 * NG, 3 * NG, 3 * NG);
+        sout[(size_t)q * NS + f] = s0 + (dt / 6.0) * (ks[0][f] + 2.0 * ks[1][f] + 2.0 * ks[2][f] + ks[3][f]);
+      }
   }
 }
 
-// Right-hand side evaluated only at the listed points of a periodic grid.
+// Right-hand side evaluated only at the listed points of a periodic grid (with
+// the scalar field's right-hand side in sout when sc is non-null).
 inline void rhs_at_points(const Grid& g, const Params& p, double t, const double* u, const int64_t* pts, int npts,
-                          double* out /* [npts][NF] */, Status& st) {
+                          double* out /* [npts][NF] */, Status& st, const double* sc = nullptr,
+                          double* sout = nullptr /* [npts][NS] */) {
   for (int q = 0; q < npts; ++q) {
     const int64_t lin = pts[q];
     const int o[3] = {(int)(lin % g.n[0]), (int)((lin / g.n[0]) % g.n[1]), (int)(lin / ((int64_t)g.n[0] * g.n[1]))};
     const int m[3] = {1, 1, 1};
-    Padded<double> P;
+    Padded<double> P, Q;
     pad_periodic(g, u, o, m, P);
-    double r[NF];
-    rhs_padded(g, p, t, P, r, st, false);
+    if (sc) pad_periodic(g, sc, o, m, Q, NS);
+    double r[NF], rs[NS];
+    rhs_padded(g, p, t, P, r, st, false, sc ? &Q : nullptr, sc ? rs : nullptr);
     for (int f = 0; f < NF; ++f) out[(size_t)q * NF + f] = r[f];
+    if (sc)
+      for (int f = 0; f < NS; ++f) sout[(size_t)q * NS + f] = rs[f];
   }
 }
 

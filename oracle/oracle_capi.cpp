@@ -164,6 +164,28 @@ int oracle_init_sc(const int* n, const double* L, const double* prm, const int* 
   return 0;
 }
 
+int oracle_rhs_sc_at_points(const int* n, const double* L, const double* prm, const int* iprm, double t,
+                            const double* u, const double* s, const int64_t* pts, int npts, double* out,
+                            double* sout) {
+  Grid g;
+  Params p;
+  if (!make(n, L, prm, iprm, g, p) || !u || !s || !pts || !out || !sout) return -1;
+  Status st;
+  rhs_at_points(g, p, t, u, pts, npts, out, st, s, sout);
+  return 0;
+}
+
+int oracle_rk4_sc_at_points(const int* n, const double* L, const double* prm, const int* iprm, double t, double dt,
+                            const double* u, const double* s, const int64_t* pts, int npts, double* out,
+                            double* sout) {
+  Grid g;
+  Params p;
+  if (!make(n, L, prm, iprm, g, p) || !u || !s || !pts || !out || !sout) return -1;
+  Status st;
+  rk4_step_at_points(g, p, t, dt, u, pts, npts, out, st, s, sout);
+  return 0;
+}
+
 int oracle_rhs_at_points(const int* n, const double* L, const double* prm, const int* iprm, double t,
                          const double* u, const int64_t* pts, int npts, double* out) {
   Grid g;

@@ -15,7 +15,8 @@
 namespace cosmos {
 
 // One RK4 stage of the scalar field from the stage state (U, Sc), one thread per
-// point with direct loads; also writes the geometry's source arrays `src`
+// point of a 16x4x4 brick (bricks in XCD slabs, so the stencil halos of
+// neighbouring bricks meet in one L2) with direct loads; also writes the geometry's source arrays `src`
 // (kScalarSrc x fs doubles, layout of DevParams::xsrc) for the stage kernel that
 // follows. MODE as the stage kernel's epilogue: 0 sout = f; 1 sacc = Sc + ca f,
 // sout = Sc + cn f; 2 sacc += ca f, sout = sun + cn f; 3 sout = sacc + ca f.
@@ -23,10 +24,10 @@ template <int MODE>
 __global__ __launch_bounds__(256) void k_scalar_stage(const double* __restrict__ U, const double* __restrict__ Sc,
                                                       double* __restrict__ src, const double* __restrict__ sun,
                                                       double* __restrict__ sacc, double* __restrict__ sout, size_t fs,
-                                                      DevParams P, double ca, double cn) {
-  const size_t p = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (p >= fs) return;
-  const int i = (int)(p % P.n[0]), j = (int)((p / P.n[0]) % P.n[1]), k = (int)(p / ((size_t)P.n[0] * P.n[1]));
+                                                      DevParams P, Tile T, double ca, double cn) {
+  int i, j, k;
+  if (!tile_point(T, P.n, i, j, k)) return;
+  const size_t p = (size_t)i + (size_t)P.n[0] * ((size_t)j + (size_t)P.n[1] * k);
   Nbr nb;
   make_nbr(nb, i, j, k, P.n);
   const int c = (int)p;
@@ -38,7 +39,7 @@ __global__ __launch_bounds__(256) void k_scalar_stage(const double* __restrict__
   for (int a = 0; a < 3; ++a) beta[a] = ldq(U + (F_BET + a) * fs, c);
   inv_sym(gt, gi);
   const double nob[3] = {0.0, 0.0, 0.0};
-  // metric connection Gd^k (and its quadratic Ricci terms, not needed here)
+  // first derivatives of the conformal metric, for the contracted connection Gd^k
   double dgt[6][3];
 #pragma unroll
   for (int s = 0; s < 6; ++s) {
@@ -47,8 +48,25 @@ __global__ __launch_bounds__(256) void k_scalar_stage(const double* __restrict__
 #pragma unroll
     for (int a = 0; a < 3; ++a) dgt[s][a] = d.d1[a];
   }
-  double Gu[3][6], Gd[3], Ric[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  connection_and_quadratic_ricci(dgt, gi, Gu, Gd, Ric);
+  // Gd^k = gt^ij Gt^k_ij = gt^kl (gt^ij d_i gt_lj - 1/2 gt^ij d_l gt_ij)
+  double Gd[3];
+  {
+    double A[3];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      double a = 0.0, b = 0.0;
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        const int x = SI(q), y = SJ(q);
+        const double w = (x == y) ? 1.0 : 2.0;
+        b += w * gi[q] * dgt[q][l];
+        a += gi[q] * (x == y ? dgt[S(l, y)][x] : dgt[S(l, y)][x] + dgt[S(l, x)][y]);
+      }
+      A[l] = a - 0.5 * b;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) Gd[k] = gi[S(k, 0)] * A[0] + gi[S(k, 1)] * A[1] + gi[S(k, 2)] * A[2];
+  }
   double dchi[3], dal[3];
   {
     FieldDerivs d;

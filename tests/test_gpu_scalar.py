@@ -121,3 +121,35 @@ def test_scalar_constraints_parity(P, orc):
     assert np.abs(M.cpu().numpy() - rM).max() < 1e-11 * np.abs(rM).max()
     np.testing.assert_allclose(norms.numpy()[:5], rn[:5], rtol=1e-11)
     assert norms[5].item() == rn[5] and norms[7].item() == rn[7]
+
+
+def test_scalar_bench_configuration_sampled(P, orc):
+    """The benchmark's scalar-field workload: 256^3, L = 16, zeta mu = 0.6, sigma = 2 and an
+    iso-curvature mode Upsilon (0.1, sigma 2), default launch configuration: initial data,
+    one right-hand side and one RK4 step at sampled points."""
+    from tests.inputs import sample_points
+    n, L = (256, 256, 256), (16.0, 16.0, 16.0)
+    s, sol = mk(P, orc, n, L)
+    ini = dict(mu=0.6, sigma=2.0)
+    sol.init(sc_mu=0.1, sc_sigma=2.0, **ini)
+    u0, sc0 = orc.init_fields_sc(s, orc.Init(**ini), 0.1, 2.0)
+    assert np.abs(sol.s.cpu().numpy() - sc0).max() < 1e-13 * np.abs(sc0).max()
+    # random points plus the centre and points at about one width from it, where the
+    # perturbation (and so each field's scale, the metric's denominator) peaks
+    c, o = n[0] // 2, 32
+    near = [(c, c, c), (c + o, c, c), (c, c - o, c), (c, c, c + o), (c + o // 2, c + o // 2, c - o // 2)]
+    pts = np.concatenate([[i + n[0] * (j + n[1] * k) for i, j, k in near], sample_points(n, 8, seed=4)])
+    idx = torch.from_numpy(pts).cuda()
+    du, ds = sol.rhs(t=0.0)
+    ru, rs = orc.rhs_sc_at_points(s, u0, sc0, pts, t=0.0)
+    g = du.reshape(25, -1)[:, idx].T.cpu().numpy()
+    assert (np.abs(g - ru).max(axis=0) / np.maximum(np.abs(ru).max(axis=0), 1e-3)).max() < 1e-11
+    g = ds.reshape(2, -1)[:, idx].T.cpu().numpy()
+    assert (np.abs(g - rs).max(axis=0) / np.maximum(np.abs(rs).max(axis=0), 1e-3)).max() < 1e-11
+    dt = 0.25 * s.h[0]
+    sol.step(dt)
+    qu, qs = orc.rk4_sc_at_points(s, u0, sc0, pts[:4], 0.0, dt)
+    g = sol.u.reshape(25, -1)[:, idx[:4]].T.cpu().numpy()
+    assert (np.abs(g - qu).max(axis=0) / np.maximum(np.abs(qu).max(axis=0), 1e-3)).max() < 1e-11
+    g = sol.s.reshape(2, -1)[:, idx[:4]].T.cpu().numpy()
+    assert (np.abs(g - qs).max(axis=0) / np.maximum(np.abs(qs).max(axis=0), 1e-3)).max() < 1e-11

@@ -126,3 +126,21 @@ def test_zero_amplitude_equals_plain_path(orc):
     ini = orc.Init(mu=0.2, sigma=1.0)
     u1, sc1 = orc.init_fields_sc(s, ini, 0.0, 1.0)
     assert np.array_equal(u1, orc.init_fields(s, ini)) and not sc1.any()
+
+
+def test_point_sampled_forms_match_full_grid(orc):
+    """The point-sampled right-hand side and RK4 step (used at sizes where the whole grid is
+    out of reach) reproduce the full-grid ones bitwise at the sampled points."""
+    from inputs import fuzz_scalar, sample_points
+    n = (14, 12, 16)
+    s = orc.Setup(n=n, L=(3.5, 3.0, 4.0))
+    u, sc = fuzz_state(n, seed=13), fuzz_scalar(n, seed=14)
+    pts = sample_points(n, 5, seed=2)
+    du, ds, _ = orc.rhs_sc(s, u, sc, t=0.3)
+    pu, ps = orc.rhs_sc_at_points(s, u, sc, pts, t=0.3)
+    assert np.array_equal(pu, du.reshape(25, -1)[:, pts].T) and np.array_equal(ps, ds.reshape(2, -1)[:, pts].T)
+    dt = 0.05
+    u1, s1, _ = orc.rk4_sc(s, u, sc, 0.3, dt, 1)
+    qu, qs = orc.rk4_sc_at_points(s, u, sc, pts, 0.3, dt)
+    assert np.allclose(qu, u1.reshape(25, -1)[:, pts].T, rtol=0, atol=1e-13)
+    assert np.allclose(qs, s1.reshape(2, -1)[:, pts].T, rtol=0, atol=1e-13)
