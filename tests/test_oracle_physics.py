@@ -154,3 +154,30 @@ def test_constraint_propagation_converges_4th_order(orc):
     ratios = out[1] / out[2]
     assert np.all(ratios > 12.0), (out, ratios)
     assert np.all(out[0] / out[1] > 8.0), out
+
+
+def test_linear_sound_wave_travels_at_sqrt_w(orc):
+    """Linear perturbation theory of the fluid: on a flat background with a tiny fluid
+    density (so gravity's back-reaction is negligible) a small standing wave
+    Et = E0 + A cos(k x) obeys d_t dE = -d_x S, d_t S = -w d_x dE, i.e. dE = A cos(k x)
+    cos(c k t) with c = sqrt(w); the run reproduces it to the discretisation error,
+    which falls at 4th order (the paper's first example compares a single-mode evolution
+    with linear perturbation theory; this is that comparison for the fluid sector)."""
+    w, E0, A, L, T = 1.0 / 3.0, 1e-7, 1e-11, 2.0, 0.6
+    errs = []
+    for n in (16, 32):
+        s = orc.Setup(n=(n, 8, 8), L=(L, L * 8 / n, L * 8 / n), w=w, ko_eps=0.0, lapse_bg=0, evolve_shift=0)
+        x = np.arange(n) * (L / n) - L / 2
+        k = 2 * np.pi / L
+        u = np.zeros(s.shape)
+        u[0] = u[1] = u[4] = u[6] = u[17] = 1.0
+        u[21] = (E0 + A * np.cos(k * x))[None, None, :]
+        nsteps = n
+        u, pf = orc.rk4(s, u, 0.0, T / nsteps, nsteps)
+        assert pf == 0
+        exact = A * np.cos(k * x) * np.cos(np.sqrt(w) * k * T)
+        # the uniform background drifts (E0 with K = 0 is not a Friedmann state): compare the
+        # zero-mean part, which is the wave
+        dE = u[21, 4, 4, :] - u[21, 4, 4, :].mean()
+        errs.append(np.abs(dE - exact).max() / A)
+    assert errs[0] < 2e-3 and errs[0] / errs[1] > 10, errs
