@@ -88,9 +88,10 @@ typedef struct {
  *            conservation form with interface fluxes 1/2 (F(q_L) + F(q_R)) - 1/2 c (q_R - q_L), q_L, q_R
  *            minmod-limited linear reconstructions of (Et, St_i), the geometry averaged to the interface,
  *            c the largest characteristic speed of the two sides; no KO on the fluid fields. Supported by
- *            cosmos_rhs, cosmos_rk4_step(_stages) and cosmos_constraints (which do not depend on it); the
- *            adjoint and batched entry points return COSMOS_EUNSUPPORTED for it. Other values:
- *            COSMOS_EUNSUPPORTED
+ *            cosmos_rhs, cosmos_rk4_step(_stages), the batched form (cosmos_rk4_step_batched must then
+ *            be given the fluid_scheme given to cosmos_batch_setup) and cosmos_constraints (which does
+ *            not depend on it); the adjoint entry points return COSMOS_EUNSUPPORTED for it. Other
+ *            values: COSMOS_EUNSUPPORTED
  *   variant  stage-kernel implementation: 0 = LDS-staged bricks (default; bricks 16x4x4, 16x8x2,
  *            8x8x4, 8x4x8), 1 = direct loads through the caches (any brick); same results
  *   alpha_collapse  a point with alpha below this value after a step counts as collapsed (0: off)
@@ -284,7 +285,9 @@ int cosmos_batch_setup(const cosmos_batch* batch, const cosmos_params* params, v
 /* One classic RK4 step of every run: run r advances by dt_dev[r] from time t_dev[r]; t_dev is
  * advanced on the device (t_dev, dt_dev: device arrays of nruns doubles). Enqueues 4 stage
  * launches and one time update and nothing else, so it can be captured in a hipGraph and
- * replayed; the results equal those of cosmos_rk4_step on each run with a 16x4x4 brick. */
+ * replayed; the results equal those of cosmos_rk4_step on each run with a 16x4x4 brick. The
+ * runs' parameters are those given to cosmos_batch_setup; params->fluid_scheme selects the
+ * kernels and must be that same scheme. */
 int cosmos_rk4_step_batched(const cosmos_batch* batch, const cosmos_params* params, double* arena,
                             double* t_dev, const double* dt_dev, void* bws, void* stream);
 

@@ -18,15 +18,22 @@
 
 namespace cosmos {
 
-constexpr int kKtBX = 8, kKtBY = 8, kKtBZ = 4;
-constexpr int kKtNX = (kKtBX + 1) * kKtBY * kKtBZ;  // interfaces normal to x
-constexpr int kKtNY = kKtBX * (kKtBY + 1) * kKtBZ;
-constexpr int kKtNZ = kKtBX * kKtBY * (kKtBZ + 1);
-constexpr int kKtThreads = kKtBX * kKtBY * kKtBZ;  // one point per thread
-// LDS segments of the three axes, each padded to whole waves so that every wave
-// works on one axis (a compile-time constant inside the interface evaluation)
-constexpr int kKtPX = (kKtNX + 63) / 64 * 64, kKtPY = (kKtNY + 63) / 64 * 64, kKtPZ = (kKtNZ + 63) / 64 * 64;
-constexpr int kKtP = kKtPX + kKtPY + kKtPZ;
+// Interface bookkeeping of a BX x BY x BZ brick (one point per thread): the
+// interfaces normal to each axis (the brick's own plus the one past its upper
+// face) and their LDS segments, each padded to whole waves so that every wave
+// works on one axis (a compile-time constant inside the interface evaluation).
+template <int BX, int BY, int BZ>
+struct KtBrick {
+  static constexpr int threads = BX * BY * BZ;
+  static constexpr int NX = (BX + 1) * BY * BZ, NY = BX * (BY + 1) * BZ, NZ = BX * BY * (BZ + 1);
+  static constexpr int PX = (NX + 63) / 64 * 64, PY = (NY + 63) / 64 * 64, PZ = (NZ + 63) / 64 * 64;
+  static constexpr int P = PX + PY + PZ;
+};
+constexpr int kKtBX = 8, kKtBY = 8, kKtBZ = 4;  // brick of k_fluid_kt
+using KtB = KtBrick<kKtBX, kKtBY, kKtBZ>;
+constexpr int kKtThreads = KtB::threads;
+constexpr int kKtP = KtB::P;  // 960 interface slots (the 16 x 4 x 4 brick has as many)
+static_assert(KtBrick<16, 4, 4>::P == kKtP, "both bricks use the same LDS segment sizes");
 
 // Smaller-magnitude argument when both have the same strict sign, else 0.
 __device__ __forceinline__ double minmod(double a, double b) {
@@ -141,10 +148,10 @@ __device__ __forceinline__ int kt_brick(int v, int nbricks, int nbx, int nby, in
 
 // Interface e of axis a's segment: the brick-local coordinates of the point on
 // its + side (extent B_a + 1 along a), then the numerical flux into fh[q][slot].
-template <int a>
+template <int BX, int BY, int a>
 __device__ __forceinline__ void kt_segment(const double* U, size_t fs, const DevParams& P, double sw, int e, int slot,
                                            int ox, int oy, int oz, double (*fh)[kKtP]) {
-  constexpr int EX = kKtBX + (a == 0), EY = kKtBY + (a == 1);
+  constexpr int EX = BX + (a == 0), EY = BY + (a == 1);
   const int li = e % EX, lj = (e / EX) % EY, lk = e / (EX * EY);
   double f[4];
   kt_interface<a>(U, fs, P, sw, ox + li, oy + lj, oz + lk, f);
@@ -152,46 +159,59 @@ __device__ __forceinline__ void kt_segment(const double* U, size_t fs, const Dev
   for (int q = 0; q < 4; ++q) fh[q][slot] = f[q];
 }
 
+// The divergence for the brick with origin (ox, oy, oz): every interface flux of
+// the brick once into LDS, then D[q fs + c] = sum_a (Fh^a_q(c + 1/2) - Fh^a_q(c - 1/2)) / h_a
+// for its points inside the grid. All threads of the workgroup call it (it
+// synchronises); fh is the workgroup's LDS.
+template <int BX, int BY, int BZ>
+__device__ __forceinline__ void kt_brick_divergence(const double* U, size_t fs, const DevParams& P, double* D, int ox,
+                                                    int oy, int oz, double (*fh)[kKtP]) {
+  using KB = KtBrick<BX, BY, BZ>;
+  const double sw = sqrt(P.w);
+  for (int t = threadIdx.x; t < KB::P; t += KB::threads) {
+    // the segments are whole waves: the axis is uniform over the wave
+    const int a = __builtin_amdgcn_readfirstlane(t < KB::PX ? 0 : (t < KB::PX + KB::PY ? 1 : 2));
+    if (a == 0) {
+      if (t < KB::NX) kt_segment<BX, BY, 0>(U, fs, P, sw, t, t, ox, oy, oz, fh);
+    } else if (a == 1) {
+      if (t - KB::PX < KB::NY) kt_segment<BX, BY, 1>(U, fs, P, sw, t - KB::PX, t, ox, oy, oz, fh);
+    } else {
+      if (t - KB::PX - KB::PY < KB::NZ) kt_segment<BX, BY, 2>(U, fs, P, sw, t - KB::PX - KB::PY, t, ox, oy, oz, fh);
+    }
+  }
+  __syncthreads();
+  const int li = threadIdx.x % BX, lj = (threadIdx.x / BX) % BY, lk = threadIdx.x / (BX * BY);
+  const int x = ox + li, y = oy + lj, z = oz + lk;
+  if (x < P.n[0] && y < P.n[1] && z < P.n[2]) {
+    // interface slots: the one at the point's minus side and the next along each axis
+    const int sx = li + (BX + 1) * (lj + BY * lk);
+    const int sy = KB::PX + li + BX * (lj + (BY + 1) * lk);
+    const int sz = KB::PX + KB::PY + li + BX * (lj + BY * lk);
+    const size_t c = (size_t)x + (size_t)P.n[0] * ((size_t)y + (size_t)P.n[1] * z);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double div = (fh[q][sx + 1] - fh[q][sx]) * P.ih[0];
+      div += (fh[q][sy + BX] - fh[q][sy]) * P.ih[1];
+      div += (fh[q][sz + BX * BY] - fh[q][sz]) * P.ih[2];
+      D[q * fs + c] = div;
+    }
+  }
+  __syncthreads();  // fh may be refilled for another brick
+}
+
 // Workgroups of k_fluid_kt: one per 8 x 8 x 4 brick (partial bricks at the upper faces).
 inline unsigned kt_bricks(const DevParams& P) {
   return (unsigned)(((P.n[0] + kKtBX - 1) / kKtBX) * ((P.n[1] + kKtBY - 1) / kKtBY) * ((P.n[2] + kKtBZ - 1) / kKtBZ));
 }
 
-// D[q fs + c] = sum_a (Fh^a_q(c + 1/2) - Fh^a_q(c - 1/2)) / h_a for q = 0..3.
+// The Kurganov-Tadmor divergence of one grid, one 8 x 8 x 4 brick per workgroup.
 __global__ __launch_bounds__(kKtThreads) void k_fluid_kt(const double* U, size_t fs, DevParams P, double* D) {
   __shared__ double fh[4][kKtP];
   const int nbx = (P.n[0] + kKtBX - 1) / kKtBX, nby = (P.n[1] + kKtBY - 1) / kKtBY;
   const int nbz = (P.n[2] + kKtBZ - 1) / kKtBZ;
   const int b = kt_brick(blockIdx.x, nbx * nby * nbz, nbx, nby, nbz);
   const int ox = (b % nbx) * kKtBX, oy = ((b / nbx) % nby) * kKtBY, oz = (b / (nbx * nby)) * kKtBZ;
-  const double sw = sqrt(P.w);
-  for (int t = threadIdx.x; t < kKtP; t += kKtThreads) {
-    // the segments are whole waves: the axis is uniform over the wave
-    const int a = __builtin_amdgcn_readfirstlane(t < kKtPX ? 0 : (t < kKtPX + kKtPY ? 1 : 2));
-    if (a == 0) {
-      if (t < kKtNX) kt_segment<0>(U, fs, P, sw, t, t, ox, oy, oz, fh);
-    } else if (a == 1) {
-      if (t - kKtPX < kKtNY) kt_segment<1>(U, fs, P, sw, t - kKtPX, t, ox, oy, oz, fh);
-    } else {
-      if (t - kKtPX - kKtPY < kKtNZ) kt_segment<2>(U, fs, P, sw, t - kKtPX - kKtPY, t, ox, oy, oz, fh);
-    }
-  }
-  __syncthreads();
-  const int li = threadIdx.x % kKtBX, lj = (threadIdx.x / kKtBX) % kKtBY, lk = threadIdx.x / (kKtBX * kKtBY);
-  const int x = ox + li, y = oy + lj, z = oz + lk;
-  if (x >= P.n[0] || y >= P.n[1] || z >= P.n[2]) return;
-  // interface slots: the one at the point's minus side and the next along each axis
-  const int sx = li + (kKtBX + 1) * (lj + kKtBY * lk);
-  const int sy = kKtPX + li + kKtBX * (lj + (kKtBY + 1) * lk);
-  const int sz = kKtPX + kKtPY + li + kKtBX * (lj + kKtBY * lk);
-  const size_t c = (size_t)x + (size_t)P.n[0] * ((size_t)y + (size_t)P.n[1] * z);
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    double div = (fh[q][sx + 1] - fh[q][sx]) * P.ih[0];
-    div += (fh[q][sy + kKtBX] - fh[q][sy]) * P.ih[1];
-    div += (fh[q][sz + kKtBX * kKtBY] - fh[q][sz]) * P.ih[2];
-    D[q * fs + c] = div;
-  }
+  kt_brick_divergence<kKtBX, kKtBY, kKtBZ>(U, fs, P, D, ox, oy, oz, fh);
 }
 
 }  // namespace cosmos
