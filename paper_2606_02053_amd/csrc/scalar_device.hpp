@@ -3,8 +3,8 @@
 // equation box phi = 0), evolved as phi and Pi = n^mu d_mu phi in a separate
 // 2-field state (field-major: phi, then Pi). The 3+1 form of box phi = 0:
 //   d_t phi = alpha Pi + beta^k d_k phi,
-//   d_t Pi  = beta^k d_k Pi + alpha K Pi + alpha chi (gt^ij d_i d_j phi - (Gd^k + gt^kl d_l chi / 2 chi) d_k phi)
-//             + chi gt^ij d_i alpha d_j phi,
+//   d_t Pi  = beta^k d_k Pi + alpha K Pi + alpha chi (gt^ij d_i d_j phi - (Gt^k + gt^kl d_l chi / 2 chi) d_k phi)
+//             + chi gt^ij d_i alpha d_j phi   (Gt^k the evolved connection functions),
 // plus Kreiss-Oliger dissipation on both fields; its normal-frame densities,
 // the sources it adds to the geometry:
 //   E = 1/2 (Pi^2 + |D phi|^2), S = 3/2 Pi^2 - 1/2 |D phi|^2, S_j = -Pi d_j phi,
@@ -20,8 +20,9 @@ namespace cosmos {
 // (kScalarSrc x fs doubles, layout of DevParams::xsrc) for the stage kernel that
 // follows. MODE as the stage kernel's epilogue: 0 sout = f; 1 sacc = Sc + ca f,
 // sout = Sc + cn f; 2 sacc += ca f, sout = sun + cn f; 3 sout = sacc + ca f.
+// (4 waves per SIMD: the register budget the kernel fits without spilling)
 template <int MODE>
-__global__ __launch_bounds__(256) void k_scalar_stage(const double* __restrict__ U, const double* __restrict__ Sc,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_scalar_stage(const double* __restrict__ U, const double* __restrict__ Sc,
                                                       double* __restrict__ src, const double* __restrict__ sun,
                                                       double* __restrict__ sacc, double* __restrict__ sout, size_t fs,
                                                       DevParams P, Tile T, double ca, double cn) {
@@ -39,34 +40,8 @@ __global__ __launch_bounds__(256) void k_scalar_stage(const double* __restrict__
   for (int a = 0; a < 3; ++a) beta[a] = ldq(U + (F_BET + a) * fs, c);
   inv_sym(gt, gi);
   const double nob[3] = {0.0, 0.0, 0.0};
-  // first derivatives of the conformal metric, for the contracted connection Gd^k
-  double dgt[6][3];
-#pragma unroll
-  for (int s = 0; s < 6; ++s) {
-    FieldDerivs d;
-    field_derivs<false, false, false>(U + (F_GT + s) * fs, nb, P, nob, d);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) dgt[s][a] = d.d1[a];
-  }
-  // Gd^k = gt^ij Gt^k_ij = gt^kl (gt^ij d_i gt_lj - 1/2 gt^ij d_l gt_ij)
-  double Gd[3];
-  {
-    double A[3];
-#pragma unroll
-    for (int l = 0; l < 3; ++l) {
-      double a = 0.0, b = 0.0;
-#pragma unroll
-      for (int q = 0; q < 6; ++q) {
-        const int x = SI(q), y = SJ(q);
-        const double w = (x == y) ? 1.0 : 2.0;
-        b += w * gi[q] * dgt[q][l];
-        a += gi[q] * (x == y ? dgt[S(l, y)][x] : dgt[S(l, y)][x] + dgt[S(l, x)][y]);
-      }
-      A[l] = a - 0.5 * b;
-    }
-#pragma unroll
-    for (int k = 0; k < 3; ++k) Gd[k] = gi[S(k, 0)] * A[0] + gi[S(k, 1)] * A[1] + gi[S(k, 2)] * A[2];
-  }
+  // the evolved connection functions (equal to gt^ij Gt^k_ij where the Gt constraint holds)
+  const double Gt[3] = {ldq(U + (F_GAM + 0) * fs, c), ldq(U + (F_GAM + 1) * fs, c), ldq(U + (F_GAM + 2) * fs, c)};
   double dchi[3], dal[3];
   {
     FieldDerivs d;
@@ -103,7 +78,7 @@ __global__ __launch_bounds__(256) void k_scalar_stage(const double* __restrict__
   double lap = contract_sym(gi, dphi.d2);
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const double gk = Gd[a] + (gi[S(a, 0)] * dchi[0] + gi[S(a, 1)] * dchi[1] + gi[S(a, 2)] * dchi[2]) * (0.5 * ichi);
+    const double gk = Gt[a] + (gi[S(a, 0)] * dchi[0] + gi[S(a, 1)] * dchi[1] + gi[S(a, 2)] * dchi[2]) * (0.5 * ichi);
     lap -= gk * dphi.d1[a];
   }
   double dad = 0.0;
