@@ -1,9 +1,11 @@
 """MI355X (gfx950) implementation of the COSMOS evolution hot path.
 
 The 3+1 Einstein equations in a BSSN (chi) form coupled to a radiation fluid
-(P = w rho), on a periodic Cartesian grid, in FP64 HIP kernels behind the C ABI
-of include/cosmos.h. This package is the thin Python side: ctypes marshalling
-(``_lib``) and small drivers that own device buffers (``solver``).
+(P = w rho; centred or Kurganov-Tadmor fluxes) and optionally a massless scalar
+field, on a periodic Cartesian grid, in FP64 HIP kernels behind the C ABI of
+include/cosmos.h. This package is the thin Python side: ctypes marshalling
+(``_lib``) and small drivers that own device buffers (``solver``, ``batch``,
+``adjoint``, ``threshold``, ``autotune``).
 """
 from ._lib import (COSMOS_EINVAL, COSMOS_EHIP, COSMOS_OK, NFIELDS, CosmosError, cosmos_abi_version,  # noqa: F401
                    cosmos_adjoint_step, cosmos_adjoint_step_stages, cosmos_adjoint_workspace_bytes, cosmos_rhs_vjp,
