@@ -146,23 +146,31 @@ def flops_per_point_step():
     return op_counts()["step_per_point"]
 
 
-def cpu_baseline(n_steps: int):
+def cpu_baseline(n_steps: int, form: str = "plain"):
     """The oracle (serial FP64 C++, OpenMP over z-planes) on a bounded sample of
     the workload: RK4 steps on a 64^3 periodic grid with the benchmark's grid
     spacing h = 1/16 and perturbation parameters; its cost per point is the
-    same as on the full grid."""
+    same as on the full grid. form: "plain", "kt" (fluid_scheme 1) or "scalar"
+    (with the scalar field's iso-curvature mode 0.1 x Gaussian of width 2)."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    s = oracle.Setup(n=(64, 64, 64), L=(4.0, 4.0, 4.0))
-    u = oracle.init_fields(s, oracle.Init(mu=0.6, sigma=2.0))
+    s = oracle.Setup(n=(64, 64, 64), L=(4.0, 4.0, 4.0), fluid_scheme=1 if form == "kt" else 0)
+    ini = oracle.Init(mu=0.6, sigma=2.0)
     dt = 0.25 * s.h[0]
-    oracle.rk4(s, u, 0.0, dt, 1, parallel=True)  # warm-up
+    if form == "scalar":
+        u, sc = oracle.init_fields_sc(s, ini, 0.1, 2.0)
+        run = lambda k: oracle.rk4_sc(s, u, sc, 0.0, dt, k, parallel=True)  # noqa: E731
+    else:
+        u = oracle.init_fields(s, ini)
+        run = lambda k: oracle.rk4(s, u, 0.0, dt, k, parallel=True)  # noqa: E731
+    run(1)  # warm-up
     t0 = time.perf_counter()
-    oracle.rk4(s, u, 0.0, dt, n_steps, parallel=True)
+    run(n_steps)
     el = time.perf_counter() - t0
+    what = {"plain": "", "kt": ", Kurganov-Tadmor fluxes", "scalar": ", with the scalar field"}[form]
     return {"value": 64 ** 3 * n_steps / el, "unit": "point-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"{n_steps} RK4 steps of the CPU oracle on a 64^3 periodic grid (h = 1/16, mu = 0.6, "
-                      f"sigma = 2.0), OpenMP over z-planes, {el:.1f} s"}
+                      f"sigma = 2.0{what}), OpenMP over z-planes, {el:.1f} s"}
 
 
 def batched_bench(a):
@@ -270,6 +278,7 @@ def kt_bench(a, kv=0, tile=(16, 4, 4), order=2):
     return {"metric": "grid-point RK4 updates/sec FP64 at 256^3, Kurganov-Tadmor fluid fluxes",
             "value": n ** 3 / (ms[1] / 1e3), "unit": "point-updates/s", "ms_per_step": ms[1],
             "centred_ms_per_step": ms[0], "cost_vs_centred": ms[1] / ms[0], "steps": a.steps, "roofline": roof,
+            **({} if a.no_cpu else {"cpu_baseline": cpu_baseline(5, "kt")}),
             "higher_is_better": True, "dtype": "f64", "data": "synthetic",
             "config": {"workload": f"as the headline ({n}^3, L = 16/H0, mu = 0.6, sigma = 2.0, CFL 0.25) with "
                                    "fluid_scheme 1 (minmod reconstruction, characteristic-speed bound, no KO on "
@@ -313,6 +322,7 @@ def scalar_bench(a, kv=0, tile=(16, 4, 4), order=2):
     return {"metric": "grid-point RK4 updates/sec FP64 at 256^3 with the massless scalar field",
             "value": n ** 3 / (ms[True] / 1e3), "unit": "point-updates/s", "ms_per_step": ms[True],
             "plain_ms_per_step": ms[False], "cost_vs_plain": ms[True] / ms[False], "steps": a.steps,
+            **({} if a.no_cpu else {"cpu_baseline": cpu_baseline(5, "scalar")}),
             "higher_is_better": True, "dtype": "f64", "data": "synthetic",
             "config": {"workload": f"as the headline ({n}^3, L = 16/H0, zeta mu = 0.6, sigma = 2.0, CFL 0.25) with "
                                    "the massless scalar field, iso-curvature Upsilon mu = 0.1, sigma = 2.0",
