@@ -185,7 +185,8 @@ int cosmos_kt_divergence(const cosmos_grid* grid, const cosmos_params* params, c
  * sws: device workspace of cosmos_scalar_workspace_bytes(grid) bytes, 256-byte aligned (the
  * 11 source arrays and the scalar's RK4 buffers), used besides ws. With variant 0 the stage kernel
  * runs the 16x4x4 brick only (other bricks: COSMOS_EUNSUPPORTED); fluid_scheme 0 and 1 are both
- * supported. The status counters do not look at s (cosmos_constraints_scalar flags non-finite
+ * supported; the batched form carries the field too (cosmos_rk4_step_batched_scalar), the adjoint
+ * does not. The status counters do not look at s (cosmos_constraints_scalar flags non-finite
  * scalar energies). */
 size_t cosmos_scalar_workspace_bytes(const cosmos_grid* grid);
 
@@ -290,6 +291,19 @@ int cosmos_batch_setup(const cosmos_batch* batch, const cosmos_params* params, v
  * kernels and must be that same scheme. */
 int cosmos_rk4_step_batched(const cosmos_batch* batch, const cosmos_params* params, double* arena,
                             double* t_dev, const double* dt_dev, void* bws, void* stream);
+
+/* Bytes of the batch's scalar-field workspace (256-byte aligned device memory, used besides bws by
+ * cosmos_rk4_step_batched_scalar): the field's RK4 buffers and source arrays of every run, laid out
+ * like the state arena. 0 for an invalid batch. */
+size_t cosmos_batch_scalar_workspace_bytes(const cosmos_batch* batch);
+
+/* cosmos_rk4_step_batched with the massless scalar field (see cosmos_rk4_step_scalar) in every run:
+ * sarena is laid out like the state arena, run r's (phi, Pi) (2 n^3 doubles) at sarena +
+ * state_off[r]; both advance together; sbws holds cosmos_batch_scalar_workspace_bytes(batch)
+ * bytes. Each run equals cosmos_rk4_step_scalar on its grid with a 16x4x4 brick. */
+int cosmos_rk4_step_batched_scalar(const cosmos_batch* batch, const cosmos_params* params, double* arena,
+                                   double* sarena, double* t_dev, const double* dt_dev, void* bws, void* sbws,
+                                   void* stream);
 
 /* Synchronise and copy the per-run counters to host out[nruns][4] (as cosmos_status). */
 int cosmos_batch_status(const cosmos_batch* batch, void* bws, void* stream, int64_t* out);

@@ -75,6 +75,8 @@ def _load():
         "cosmos_batch_setup": ([B, Pr, P, P], i32),
         "cosmos_rk4_step_batched": ([B, Pr, P, P, P, P, P], i32),
         "cosmos_batch_status": ([B, P, P, ctypes.POINTER(ctypes.c_int64)], i32),
+        "cosmos_batch_scalar_workspace_bytes": ([B], sz),
+        "cosmos_rk4_step_batched_scalar": ([B, Pr, P, P, P, P, P, P, P], i32),
         "cosmos_scalar_workspace_bytes": ([G], sz),
         "cosmos_init_fields_scalar": ([G, Pr, In, f64, f64, P, P, P], i32),
         "cosmos_rhs_scalar": ([G, Pr, f64, P, P, P, P, P, P, P], i32),
@@ -315,6 +317,19 @@ def cosmos_rk4_step_batched(batch, params, arena, t_dev, dt_dev, bws, stream=Non
                                        _dev(t_dev, "t_dev", batch.nruns), _dev(dt_dev, "dt_dev", batch.nruns),
                                        _dev(bws, "bws", cosmos_batch_workspace_bytes(batch), dtype=torch.uint8),
                                        _stream(stream)))
+
+
+def cosmos_batch_scalar_workspace_bytes(batch) -> int:
+    return int(lib.cosmos_batch_scalar_workspace_bytes(ctypes.byref(batch)))
+
+
+def cosmos_rk4_step_batched_scalar(batch, params, arena, sarena, t_dev, dt_dev, bws, sbws, stream=None):
+    _check(lib.cosmos_rk4_step_batched_scalar(ctypes.byref(batch), ctypes.byref(params), _dev(arena, "arena"),
+                                              _dev(sarena, "sarena"), _dev(t_dev, "t_dev", batch.nruns),
+                                              _dev(dt_dev, "dt_dev", batch.nruns),
+                                              _dev(bws, "bws", cosmos_batch_workspace_bytes(batch), dtype=torch.uint8),
+                                              _dev(sbws, "sbws", cosmos_batch_scalar_workspace_bytes(batch),
+                                                   dtype=torch.uint8), _stream(stream)))
 
 
 def cosmos_batch_status(batch, bws, stream=None):

@@ -23,6 +23,8 @@ class RunSpec:
     mu: float
     sigma: float
     L: float = 12.0
+    sc_mu: float = 0.0     # iso-curvature mode of the scalar field (Batch(..., scalar=True))
+    sc_sigma: float = 1.0
 
 
 def draw_scan(nruns: int = 64, seed: int = 2606, sizes=(48, 64, 80, 96), mu=(0.3, 0.8), sigma=(0.8, 1.6),
@@ -37,7 +39,11 @@ def draw_scan(nruns: int = 64, seed: int = 2606, sizes=(48, 64, 80, 96), mu=(0.3
 
 
 class Batch:
-    def __init__(self, runs, params: C.cosmos_params | None = None, cfl: float = 0.25, device="cuda"):
+    """With scalar=True every run also carries the massless scalar field (RunSpec.sc_mu,
+    sc_sigma give its iso-curvature initial data); ``scalar_state(r)`` is run r's (phi, Pi)."""
+
+    def __init__(self, runs, params: C.cosmos_params | None = None, cfl: float = 0.25, device="cuda",
+                 scalar: bool = False):
         self.runs = list(runs)
         self.params = params if params is not None else C.make_params()
         self.device = torch.device(device)
@@ -52,20 +58,41 @@ class Batch:
         self.t = torch.zeros(len(self.runs), dtype=torch.float64, device=self.device)
         self.dt = torch.tensor([cfl * r.L / r.n for r in self.runs], dtype=torch.float64, device=self.device)
         self.graph = None
+        self.scalar = scalar
+        if scalar:  # laid out like the state arena: run r's (phi, Pi) at its state offset
+            self.sarena = torch.zeros(o, dtype=torch.float64, device=self.device)
+            self.sbws = torch.empty(C.cosmos_batch_scalar_workspace_bytes(self.batch), dtype=torch.uint8,
+                                    device=self.device)
 
     def state(self, r: int) -> torch.Tensor:
         n = self.runs[r].n
         return self.arena[self.offsets[r]:self.offsets[r] + C.NFIELDS * n ** 3].view(C.NFIELDS, n, n, n)
 
+    def scalar_state(self, r: int) -> torch.Tensor:
+        n = self.runs[r].n
+        return self.sarena[self.offsets[r]:self.offsets[r] + 2 * n ** 3].view(2, n, n, n)
+
     def init(self):
         for r, spec in enumerate(self.runs):
             g = C.make_grid(spec.n, spec.L)
-            C.cosmos_init_fields(g, self.params, C.make_init(mu=spec.mu, sigma=spec.sigma), self.state(r))
+            ini = C.make_init(mu=spec.mu, sigma=spec.sigma)
+            if self.scalar:
+                C.cosmos_init_fields_scalar(g, self.params, ini, spec.sc_mu, spec.sc_sigma, self.state(r),
+                                            self.scalar_state(r))
+            else:
+                C.cosmos_init_fields(g, self.params, ini, self.state(r))
         self.t.zero_()
         C.cosmos_batch_setup(self.batch, self.params, self.bws)
 
+    def _step(self, stream=None):
+        if self.scalar:
+            C.cosmos_rk4_step_batched_scalar(self.batch, self.params, self.arena, self.sarena, self.t, self.dt,
+                                             self.bws, self.sbws, stream=stream)
+        else:
+            C.cosmos_rk4_step_batched(self.batch, self.params, self.arena, self.t, self.dt, self.bws, stream=stream)
+
     def step(self):
-        C.cosmos_rk4_step_batched(self.batch, self.params, self.arena, self.t, self.dt, self.bws)
+        self._step()
 
     def capture(self):
         """Capture one batched RK4 step in a graph (after init)."""
@@ -73,8 +100,7 @@ class Batch:
         s.wait_stream(torch.cuda.current_stream())
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph, stream=s):
-            C.cosmos_rk4_step_batched(self.batch, self.params, self.arena, self.t, self.dt, self.bws,
-                                      stream=torch.cuda.current_stream())
+            self._step(stream=torch.cuda.current_stream())
         torch.cuda.current_stream().wait_stream(s)
         return self.graph
 

@@ -224,7 +224,10 @@ __device__ __forceinline__ void lds_carry_fill(LdsCarry<B, Pre>& cy, const doubl
 // whose point lies inside the grid. On entry `cy` holds this brick's ring,
 // epilogue operands and point values; if nx.valid, on return it holds those of
 // the next brick (loaded during the last phases of this one).
-template <class B, bool KT, bool SC, class Sink, class Pre>
+// SC: the scalar field's source arrays (P.xsrc) are added in the K, At and Gt
+// equations: 0 none, 1 read through buffer descriptors (P.xsrc uniform in scalar
+// registers, a kernel argument), 2 read with plain loads (P.xsrc formed per work item).
+template <class B, bool KT, int SC, class Sink, class Pre>
 __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, size_t fs, const DevParams& P, double t,
                                              int c, bool active, LdsCarry<B, Pre>& cy, const NextBrick<B>& nx,
                                              double* buf0, double* buf1, Sink& sink, bool& prim_fail) {
@@ -238,6 +241,10 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
   HaloCopy<B>& hc = cy.hc;
   auto& ep = cy.ep;
   const uint32_t nbytes = (uint32_t)(fs * 8);
+  auto xsrc = [&](int q) -> double {  // source array q at this point (SC != 0)
+    if constexpr (SC == 1) return bld(field_ptr(P.xsrc, q, fs), nbytes, (uint32_t)c * 8u);
+    return P.xsrc[(size_t)q * fs + c];
+  };
 
   // centre values (registers); inactive threads hold a valid point's values and never store
   const double chi = cy.cen[F_CHI];
@@ -466,7 +473,7 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
       double Sij = R[R3_S + SI(s)] * R[R3_S + SJ(s)] * ix + pr * gt[s] * ichi;
-      if constexpr (SC) Sij += bld(field_ptr(P.xsrc, SRC_SIJ + s, fs), nbytes, (uint32_t)c * 8u);
+      if constexpr (SC != 0) Sij += xsrc(SRC_SIJ + s);
       R[R3_RX + s] = -DDa[s] + alpha * (R[R3_RX + s] - 8.0 * PI_D * Sij);
     }
 #pragma unroll
@@ -503,7 +510,7 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
     const double AA = contract_sym(At, Aup);
     const double Str = (Sup[0] * R[R3_S + 0] + Sup[1] * R[R3_S + 1] + Sup[2] * R[R3_S + 2]) * R[R3_IX] + 3.0 * R[R3_P];
     double EpS = R[R3_E] + Str;
-    if constexpr (SC) EpS += bld(field_ptr(P.xsrc, SRC_EPS, fs), nbytes, (uint32_t)c * 8u);
+    if constexpr (SC != 0) EpS += xsrc(SRC_EPS);
     sink.put(F_K, d.advko + (-R[R3_D2A] + alpha * (AA + K * K * (1.0 / 3.0)) + 4.0 * PI_D * alpha * EpS), ep[0][0]);
     // Gt^i: every remaining term
     const double divb = R[R3_DB + 0] + R[R3_DB + 4] + R[R3_DB + 8];
@@ -528,10 +535,10 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
       double inner = contract_sym(Gu, Aup);
       inner -= (1.5 * ichi) * (Aup[S(i, 0)] * R[R3_DCHI + 0] + Aup[S(i, 1)] * R[R3_DCHI + 1] + Aup[S(i, 2)] * R[R3_DCHI + 2]);
       r += 2.0 * alpha * inner;
-      if constexpr (SC) {
+      if constexpr (SC != 0) {
         double Sj[3];
 #pragma unroll
-        for (int j = 0; j < 3; ++j) Sj[j] = R[R3_S + j] + bld(field_ptr(P.xsrc, SRC_S + j, fs), nbytes, (uint32_t)c * 8u);
+        for (int j = 0; j < 3; ++j) Sj[j] = R[R3_S + j] + xsrc(SRC_S + j);
         r -= 16.0 * PI_D * alpha * (gi[S(i, 0)] * Sj[0] + gi[S(i, 1)] * Sj[1] + gi[S(i, 2)] * Sj[2]);
       } else {
         r -= 16.0 * PI_D * alpha * (gi[S(i, 0)] * R[R3_S + 0] + gi[S(i, 1)] * R[R3_S + 1] + gi[S(i, 2)] * R[R3_S + 2]);

@@ -316,7 +316,7 @@ __global__ __launch_bounds__(kBlock) void k_bssn_stage_lds(const double* U, cons
     if (nx.valid) HaloCopy<B>::offsets(ni0, nj0, nk0, P.n, nx.goffb);
     Sink sink{un, acc, out, fs, c, ca, cn, P.alpha_collapse};
     bool fail = false;
-    bssn_rhs_lds<B, KT, SC>(U, F, fs, P, t, c, active, cy, nx, smem, smem + B::NP, sink, fail);
+    bssn_rhs_lds<B, KT, SC ? 1 : 0>(U, F, fs, P, t, c, active, cy, nx, smem, smem + B::NP, sink, fail);
     if (active) {
       nfail += fail;
       if constexpr (MODE == 3) {

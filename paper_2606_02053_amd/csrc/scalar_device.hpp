@@ -14,20 +14,16 @@
 
 namespace cosmos {
 
-// One RK4 stage of the scalar field from the stage state (U, Sc), one thread per
-// point of a 16x4x4 brick (bricks in XCD slabs, so the stencil halos of
-// neighbouring bricks meet in one L2) with direct loads; also writes the geometry's source arrays `src`
+// One RK4 stage of the scalar field at grid point (i, j, k) from the stage state
+// (U, Sc), with direct loads; also writes the geometry's source arrays `src`
 // (kScalarSrc x fs doubles, layout of DevParams::xsrc) for the stage kernel that
 // follows. MODE as the stage kernel's epilogue: 0 sout = f; 1 sacc = Sc + ca f,
 // sout = Sc + cn f; 2 sacc += ca f, sout = sun + cn f; 3 sout = sacc + ca f.
-// (4 waves per SIMD: the register budget the kernel fits without spilling)
 template <int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_scalar_stage(const double* __restrict__ U, const double* __restrict__ Sc,
-                                                      double* __restrict__ src, const double* __restrict__ sun,
-                                                      double* __restrict__ sacc, double* __restrict__ sout, size_t fs,
-                                                      DevParams P, Tile T, double ca, double cn) {
-  int i, j, k;
-  if (!tile_point(T, P.n, i, j, k)) return;
+__device__ __forceinline__ void scalar_point(const double* __restrict__ U, const double* __restrict__ Sc,
+                                             double* __restrict__ src, const double* __restrict__ sun,
+                                             double* __restrict__ sacc, double* __restrict__ sout, size_t fs,
+                                             const DevParams& P, int i, int j, int k, double ca, double cn) {
   const size_t p = (size_t)i + (size_t)P.n[0] * ((size_t)j + (size_t)P.n[1] * k);
   Nbr nb;
   make_nbr(nb, i, j, k, P.n);
@@ -102,6 +98,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
       sout[q] = sacc[q] + ca * r[f];
     }
   }
+}
+
+// The scalar stage of one grid: one thread per point of a 16x4x4 brick (bricks in XCD
+// slabs, so the stencil halos of neighbouring bricks meet in one L2); 4 waves per SIMD,
+// the register budget the point evaluation fits without spilling.
+template <int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_scalar_stage(
+    const double* __restrict__ U, const double* __restrict__ Sc, double* __restrict__ src,
+    const double* __restrict__ sun, double* __restrict__ sacc, double* __restrict__ sout, size_t fs, DevParams P,
+    Tile T, double ca, double cn) {
+  int i, j, k;
+  if (!tile_point(T, P.n, i, j, k)) return;
+  scalar_point<MODE>(U, Sc, src, sun, sacc, sout, fs, P, i, j, k, ca, cn);
 }
 
 }  // namespace cosmos
