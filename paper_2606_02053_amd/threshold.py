@@ -43,9 +43,16 @@ class ThresholdResult:
     history: list = field(default_factory=list)  # (stage, mu, J) per evaluation
 
 
-def centre_lapse_batch(mus, sigma: float, n: int, L: float, nsteps: int, params=None) -> list:
-    """alpha at the box centre after nsteps for each mu, all runs in one batch (n a multiple of 16)."""
-    b = Batch([RunSpec(n=n, mu=float(m), sigma=sigma, L=L) for m in mus], params)
+def centre_lapse_batch(mus, sigma: float, n: int, L: float, nsteps: int, params=None, isocurvature=None) -> list:
+    """alpha at the box centre after nsteps for each mu, all runs in one batch (n a multiple of 16).
+    With isocurvature = (zeta_mu, zeta_sigma) the scanned amplitude is that of the scalar field's
+    iso-curvature mode (width sigma) on the curvature perturbation (zeta_mu, zeta_sigma)."""
+    if isocurvature is None:
+        b = Batch([RunSpec(n=n, mu=float(m), sigma=sigma, L=L) for m in mus], params)
+    else:
+        zmu, zsg = isocurvature
+        b = Batch([RunSpec(n=n, mu=zmu, sigma=zsg, L=L, sc_mu=float(m), sc_sigma=sigma) for m in mus], params,
+                  scalar=True)
     b.init()
     b.capture()
     b.run(nsteps)
@@ -58,15 +65,16 @@ def centre_lapse_batch(mus, sigma: float, n: int, L: float, nsteps: int, params=
 
 
 def multisection(sigma: float, lo: float, hi: float, alpha_target: float, n: int, L: float, nsteps: int,
-                 K: int = 16, rounds: int = 2, params=None, history=None):
+                 K: int = 16, rounds: int = 2, params=None, history=None, isocurvature=None):
     """Shrink [lo, hi] around the first sign change of J with K batched runs per round
-    (the first round also runs lo itself). Returns (lo, hi, J(lo), runs)."""
+    (the first round also runs lo itself). Returns (lo, hi, J(lo), runs). isocurvature: see
+    centre_lapse_batch."""
     J_lo = None
     runs = 0
     for _ in range(rounds):
         mus = [lo + (hi - lo) * (k + 1) / (K + 1) for k in range(K)]
         first = J_lo is None
-        a = centre_lapse_batch(([lo] if first else []) + mus, sigma, n, L, nsteps, params)
+        a = centre_lapse_batch(([lo] if first else []) + mus, sigma, n, L, nsteps, params, isocurvature)
         runs += len(a)
         if first:
             J_lo = a[0] - alpha_target
@@ -117,3 +125,18 @@ def find_threshold(sigma: float, lo: float, hi: float, alpha_target: float, n: i
         mu = new
     return ThresholdResult(mu=best[0], J=best[1], dJ_dmu=best[2], bracket=(lo, hi), batched_runs=runs,
                            newton_steps=steps, history=history)
+
+
+def find_threshold_isocurvature(sigma: float, lo: float, hi: float, alpha_target: float, zeta=(0.0, 1.0),
+                                n: int = 32, L: float = 12.0, nsteps: int = 50, K: int = 16, rounds: int = 6,
+                                params=None) -> ThresholdResult:
+    """The same search over the amplitude of the scalar field's iso-curvature mode (width sigma,
+    on the curvature perturbation zeta = (mu, sigma)), by batched multisection alone (the
+    adjoint does not carry the scalar field): the bracket shrinks by K + 1 per round."""
+    params = params if params is not None else C.make_params()
+    history = []
+    lo, hi, J_lo, runs = multisection(sigma, lo, hi, alpha_target, n, L, nsteps, K, rounds, params, history,
+                                      isocurvature=tuple(zeta))
+    mu = 0.5 * (lo + hi)
+    return ThresholdResult(mu=mu, J=float("nan"), dJ_dmu=float("nan"), bracket=(lo, hi), batched_runs=runs,
+                           newton_steps=0, history=history)

@@ -30,3 +30,22 @@ def test_threshold_search_recovers_oracle_amplitude(orc):
     for m in range(nsteps):
         u, v = orc.jvp(s, u, v, "step", t=m * dt, dt=dt)
     assert res.dJ_dmu == pytest.approx(float(v[17, c, c, c]), rel=1e-8)
+
+
+def test_isocurvature_threshold_by_multisection(orc):
+    """The iso-curvature amplitude whose centre lapse matches the oracle's at a known amplitude:
+    the multisection bracket (K + 1 = 9 times narrower per round) closes on it."""
+    from paper_2606_02053_amd.threshold import find_threshold_isocurvature
+    n, L, nsteps, sigma, mu_star = 16, 6.0, 10, 1.0, 0.2763
+    s = orc.Setup(n=(n, n, n), L=(L, L, L))
+    dt = 0.25 * L / n
+    c = n // 2
+    u0, sc0 = orc.init_fields_sc(s, orc.Init(mu=0.05, sigma=1.2), mu_star, sigma)
+    u, _, _ = orc.rk4_sc(s, u0, sc0, 0.0, dt, nsteps, parallel=True)
+    target = float(u[17, c, c, c])
+    res = find_threshold_isocurvature(sigma, 0.1, 0.4, target, zeta=(0.05, 1.2), n=n, L=L, nsteps=nsteps, K=8,
+                                      rounds=4)
+    lo, hi = res.bracket
+    assert abs(hi - lo) < 0.3 / 9 ** 4 * 1.01
+    assert min(lo, hi) - 1e-9 <= mu_star <= max(lo, hi) + 1e-9, res.bracket
+    assert res.batched_runs == 1 + 4 * 8
