@@ -153,3 +153,35 @@ def test_scalar_bench_configuration_sampled(P, orc):
     assert (np.abs(g - qu).max(axis=0) / np.maximum(np.abs(qu).max(axis=0), 1e-3)).max() < 1e-11
     g = sol.s.reshape(2, -1)[:, idx[:4]].T.cpu().numpy()
     assert (np.abs(g - qs).max(axis=0) / np.maximum(np.abs(qs).max(axis=0), 1e-3)).max() < 1e-11
+
+
+def test_scalar_rhs_options(P, orc):
+    n, L = (12, 10, 14), (2.5, 2.0, 3.0)
+    u, sc = fuzz_state(n, seed=17), fuzz_scalar(n, seed=18)
+    for kw in (dict(evolve_shift=0), dict(ko_eps=0.0), dict(lapse_bg=0), dict(w=0.2, eta=2.0, H0=0.5)):
+        s, sol = mk(P, orc, n, L, **kw)
+        sol.set_state(to_dev(u), s=to_dev(sc))
+        du, ds = sol.rhs(t=0.2)
+        ru, rs, _ = orc.rhs_sc(s, u, sc, t=0.2)
+        assert err_fields(du.cpu().numpy(), ru)[0] < 1e-11, kw
+        assert err2(ds.cpu().numpy(), rs)[0] < 1e-11, kw
+
+
+def test_scalar_direct_variant_any_brick(P, orc):
+    """The LDS-staged kernel takes the scalar sources with its 16x4x4 brick only; the direct
+    variant takes any brick and agrees with it to round-off."""
+    n, L = (20, 12, 18), (4.0, 2.5, 3.5)
+    u, sc = fuzz_state(n, seed=19), fuzz_scalar(n, seed=20)
+    ref = None
+    for variant, tile in ((0, (16, 4, 4)), (1, (8, 8, 4)), (1, (16, 4, 4))):
+        sol = P.Solver(n, L, P.make_params(variant=variant, tile=tile, tile_order=1), scalar=True)
+        sol.set_state(to_dev(u), s=to_dev(sc))
+        du, ds = sol.rhs(t=0.1)
+        if ref is None:
+            ref = (du, ds)
+            continue
+        assert err_fields(du.cpu().numpy(), ref[0].cpu().numpy())[0] < 1e-13, (variant, tile)
+        assert torch.equal(ds, ref[1]), (variant, tile)  # the scalar kernel is the same
+    bad = P.Solver(n, L, P.make_params(variant=0, tile=(8, 8, 4)), scalar=True)
+    with pytest.raises(P.CosmosError):
+        bad.rhs(t=0.0)
