@@ -277,3 +277,57 @@ def test_blocked_order_bitwise(P, orc, n, L):
     got = outs[2][0].reshape(25, -1)[:, torch.from_numpy(pts).cuda()].T.cpu().numpy()
     scale = np.maximum(np.abs(ref).max(axis=0), 1e-3)
     assert (np.abs(got - ref).max(axis=0) / scale).max() < 1e-11
+
+
+
+def test_c2_128cubed_500_steps(P, orc):
+    """128^3, L = 12, Gaussian zeta mu = 0.5, sigma = 1.5, CFL 0.25, KO 0.1: initial data and
+    the first RK4 step against the oracle at sampled points (the centre, where the perturbation
+    peaks, included), then the configuration's 500 steps with the constraint norms every 10
+    steps. At step 499 one more GPU step is checked against the oracle's step from the GPU's own
+    state at sampled points (a property that holds at any step count), and the norms at step 500
+    against the oracle's norms of the GPU's state."""
+    n, L = (128, 128, 128), (12.0, 12.0, 12.0)
+    s, sol = mk(P, orc, n, L)
+    ini = dict(mu=0.5, sigma=1.5)
+    sol.init(**ini)
+    u0 = orc.init_fields(s, orc.Init(**ini))
+    assert err_fields(sol.u.cpu().numpy(), u0)[0] < 1e-13
+    c = 64 + 128 * (64 + 128 * 64)
+    pts = np.unique(np.concatenate([sample_points(n, 16, seed=5), [c, c + 1, c + 3 * 128, c + 5 * 128 * 128]]))
+    idx = torch.from_numpy(pts).cuda()
+    dt = 0.25 * s.h[0]
+
+    def check_step(u_before, t):
+        g = sol.u.reshape(25, -1)[:, idx].T.cpu().numpy()
+        r = orc.rk4_at_points(s, u_before, pts, t, dt)
+        scale = np.maximum(np.abs(r).max(axis=0), 1e-3)
+        return (np.abs(g - r).max(axis=0) / scale).max()
+
+    sol.step(dt)
+    e1 = check_step(u0, 0.0)
+    assert e1 < 1e-11
+    history = [orc.constraints(s, u0, parallel=True)[:5]]
+    for _ in range(49):
+        sol.run(10 if len(history) > 1 else 9, dt)
+        history.append(sol.constraints().numpy()[:5])
+    assert sol.status()["steps"] == 490
+    sol.run(9, dt)
+    u499, t499 = sol.u.cpu().numpy(), sol.t
+    sol.step(dt)
+    e500 = check_step(u499, t499)
+    g = sol.constraints().numpy()
+    rn = orc.constraints(s, sol.u.cpu().numpy(), parallel=True)
+    hh = np.array(history + [g[:5]])
+    print(f"C2: step 1 {e1:.3e}, step 500 {e500:.3e}; H_L2 {hh[0, 0]:.3e} max {hh[:, 0].max():.3e}, "
+          f"M_L2 max {hh[:, 2].max():.3e}")
+    assert e500 < 1e-11
+    np.testing.assert_allclose(g[:5], rn[:5], rtol=1e-11)
+    assert g[5] == 0 and g[6] == rn[6] and g[7] == rn[7]
+    history.append(g[:5])
+    h = np.array(history)
+    st = sol.status()
+    assert st["steps"] == 500 and st["nonfinite"] == 0 and st["prim_fail"] == 0
+    assert np.isfinite(h).all()
+    # the constraint violation stays at the discretisation level of the data
+    assert h[:, 0].max() < 20 * h[0, 0] and h[:, 2].max() < 20 * h[0, 0]
