@@ -9,11 +9,11 @@ average stage time, measured with HIP events on the launch stream around the
 timed steps), the CPU oracle timed on a bounded sample of the same workload, and
 the other forms of the metric as sub-objects: "batched" (runs/s of the 64-run
 scan), "adjoint" (cost of the gradient relative to the forward run), "kt" (the
-headline workload with the Kurganov-Tadmor fluid scheme) and "scalar" (with the
-massless scalar field).
+headline workload with the Kurganov-Tadmor fluid scheme), "scalar" (with the
+massless scalar field) and "c2" (the 128^3 run with constraint norms every 10 steps).
 
 Extra modes:
-  --headline-only  skip the batched, adjoint, kt and scalar sub-objects
+  --headline-only  skip the batched, adjoint, kt, scalar and c2 sub-objects
   --batched      only the 64-run threshold-scan workload (grid sizes drawn from
                  {48, 64, 80, 96}^3, mu in [0.3, 0.8], sigma in [0.8, 1.6], box 12/H0,
                  300 RK4 steps per run): runs/s of the batched, hipGraph-replayed form
@@ -29,6 +29,9 @@ Extra modes:
                  (fluid_scheme 1), against the centred scheme on the same configuration
   --scalar       only the headline workload with the massless scalar field (iso-curvature mode
                  0.1 x Gaussian of width 2), against the plain run on the same configuration
+  --c2           only the 128^3 evolution (box 12/H0, mu = 0.5, sigma = 1.5, 500 RK4 steps) with
+                 the constraint norms every 10 steps, timed with and without the norms, and the
+                 HBM roofline of one constraint evaluation
   --copy-probe   only a plain device-to-device copy of known size (calibrates
                  rocprofv3 FETCH_SIZE / WRITE_SIZE counters)
   --no-cpu       skip the CPU baseline leg
@@ -74,12 +77,13 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-tune", action="store_true", help="use the default tile instead of the autotuned one")
     ap.add_argument("--batched", action="store_true")
-    ap.add_argument("--headline-only", action="store_true", help="no batched / adjoint / kt / scalar sub-objects")
+    ap.add_argument("--headline-only", action="store_true", help="no batched / adjoint / kt / scalar / c2 sub-objects")
     ap.add_argument("--batched-steps", type=int, default=30, help="timed steps (runs/s is scaled to 300 steps)")
     ap.add_argument("--adjoint", action="store_true")
     ap.add_argument("--threshold", action="store_true")
     ap.add_argument("--kt", action="store_true", help="only the Kurganov-Tadmor fluid-scheme leg")
     ap.add_argument("--scalar", action="store_true", help="only the massless-scalar-field leg")
+    ap.add_argument("--c2", action="store_true", help="only the 128^3 run with constraint norms every 10 steps")
     ap.add_argument("--adjoint-steps", type=int, default=200, help="RK4 steps of the differentiated run")
     ap.add_argument("--no-fd", action="store_true", help="skip the finite-difference check of the adjoint")
     ap.add_argument("--config", default=None,
@@ -329,6 +333,93 @@ def scalar_bench(a, kv=0, tile=(16, 4, 4), order=2):
                        "kernel_config": config_name(kv, tile, order)}}
 
 
+def c2_bench(a):
+    """The 128^3 evolution (box 12/H0, Gaussian zeta mu = 0.5, sigma = 1.5, CFL 0.25, KO 0.1,
+    500 RK4 steps) with the Hamiltonian/momentum constraint norms every 10 steps (51
+    evaluations, t = 0 included, kept on the device until the end), timed with HIP events on
+    the launch stream, and the same 500 steps without the norms; plus the roofline of one
+    constraint evaluation (k_constraints + k_reduce_partials: every field read once, 200 B per
+    point) timed over repeated evaluations of the final state."""
+    import paper_2606_02053_amd as P
+    n, L, nsteps, every = 128, 12.0, 500, 10
+    npts = n ** 3
+    ms = {}
+    for with_norms in (True, False):
+        sol = P.Solver(n, L)
+        sol.init(mu=0.5, sigma=1.5)
+        dt = sol.default_dt()
+        hist = torch.empty((nsteps // every + 1, 8), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        if with_norms:
+            P.cosmos_constraints(sol.grid, sol.params, sol.u, hist[0], ws=sol.ws)
+        for i in range(nsteps // every):
+            for _ in range(every):
+                P.cosmos_rk4_step(sol.grid, sol.params, sol.t, dt, sol.u, sol.ws)
+                sol.t += dt
+            if with_norms:
+                P.cosmos_constraints(sol.grid, sol.params, sol.u, hist[i + 1], ws=sol.ws)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms[with_norms] = e0.elapsed_time(e1)
+        st = sol.status()
+        if st["nonfinite"] or st["prim_fail"]:
+            raise RuntimeError(f"128^3 run (norms: {with_norms}) went bad: {st}")
+        if with_norms:
+            h = hist.cpu().numpy()
+            norms = {"H_rms_first": float(h[0, 0]), "H_rms_last": float(h[-1, 0]),
+                     "H_rms_max": float(h[:, 0].max()), "M_rms_max": float(h[:, 2].max()),
+                     "alpha_min_last": float(h[-1, 6])}
+            # one constraint evaluation alone, repeated on the final state
+            reps = 50
+            P.cosmos_constraints(sol.grid, sol.params, sol.u, hist[0], ws=sol.ws)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for _ in range(reps):
+                P.cosmos_constraints(sol.grid, sol.params, sol.u, hist[0], ws=sol.ws)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            cons_s = e0.elapsed_time(e1) / 1e3 / reps
+        del sol
+    byts = 25 * 8 * npts
+    roof = {"bound": "hbm", "achieved": round(byts / cons_s / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(byts / cons_s / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "k_constraints + k_reduce_partials (one constraint evaluation)",
+            "avg_launch_ms": round(cons_s * 1e3, 4), "algorithmic_bytes_per_launch": byts}
+    out = {"metric": "grid-point RK4 updates/sec FP64 at 128^3, constraint norms every 10 steps",
+           "value": npts * nsteps / (ms[True] / 1e3), "unit": "point-updates/s",
+           "value_without_norms": npts * nsteps / (ms[False] / 1e3),
+           "ms_total": ms[True], "ms_total_without_norms": ms[False], "steps": nsteps,
+           "norm_evaluations": nsteps // every + 1, "norms": norms, "roofline": roof,
+           "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "BSSN + radiation fluid classic RK4, 128^3 periodic grid, L = 12/H0, Gaussian "
+                                  "zeta mu = 0.5 sigma = 1.5, CFL 0.25, KO eps 0.1, 500 steps, constraint "
+                                  "norms every 10 steps"}}
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_c2()
+    return out
+
+
+def cpu_baseline_c2():
+    """The oracle on a bounded sample of the 128^3 cadence: 10 RK4 steps and one constraint
+    evaluation on a 64^3 grid with the same spacing (h = 0.09375) and perturbation parameters."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    s = oracle.Setup(n=(64, 64, 64), L=(6.0, 6.0, 6.0))
+    u = oracle.init_fields(s, oracle.Init(mu=0.5, sigma=1.5))
+    dt = 0.25 * s.h[0]
+    oracle.rk4(s, u, 0.0, dt, 1, parallel=True)  # warm-up
+    t0 = time.perf_counter()
+    u1, _ = oracle.rk4(s, u, 0.0, dt, 10, parallel=True)
+    oracle.constraints(s, u1, parallel=True)
+    el = time.perf_counter() - t0
+    return {"value": 64 ** 3 * 10 / el, "unit": "point-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"10 RK4 steps + 1 constraint evaluation of the CPU oracle on a 64^3 periodic grid "
+                      f"(h = 0.09375, mu = 0.5, sigma = 1.5), OpenMP over z-planes, {el:.1f} s"}
+
+
 def adjoint_bench(a):
     from paper_2606_02053_amd.adjoint import RunConfig, central_lapse
     import paper_2606_02053_amd as P
@@ -431,6 +522,9 @@ def main():
     if a.threshold:
         print(json.dumps(threshold_bench(a)), flush=True)
         return
+    if a.c2:
+        print(json.dumps(c2_bench(a)), flush=True)
+        return
     if a.kt:
         kv, tile, order = parse_config(a.config) if a.config else (0, (16, 4, 4), 2)
         print(json.dumps(kt_bench(a, kv, tile, order)), flush=True)
@@ -496,6 +590,7 @@ def main():
         out["kt"] = kt_bench(a, kv, tile, order)
         # the LDS-staged kernel takes the scalar sources with the 16x4x4 brick only
         out["scalar"] = scalar_bench(a, kv, (16, 4, 4) if kv == 0 else tile, order)
+        out["c2"] = c2_bench(a)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(a.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -16,10 +16,26 @@ namespace cosmos {
 // partial record: sum H^2, sum |M|^2, sum Hn^2, max |H|, max |M|, #non-finite, min alpha, argmin alpha
 constexpr int kRedRecord = 8;
 
-__device__ __forceinline__ void constraint_point(const double* __restrict__ U, size_t fs, const Nbr& nb,
+// Derivatives from global memory: the centred stencils at the point, periodic wrap in the offsets.
+struct DirectDerivs {
+  const double* U;
+  size_t fs;
+  const Nbr& nb;
+  const DevParams& P;
+  template <bool SECOND>
+  __device__ __forceinline__ void get(int f, FieldDerivs& d) {
+    const double nob[3] = {0.0, 0.0, 0.0};
+    field_derivs<SECOND, false, false>(U + (size_t)f * fs, nb, P, nob, d);
+  }
+};
+
+// H, M_i and the normalised H at the point with linear index c. Der supplies the
+// first (and, with SECOND, second) centred derivatives of a field; it is asked for
+// them in a fixed order: gt_ij (6, with second), Gt^i (3), chi (with second), K, At_ij (6).
+template <class Der>
+__device__ __forceinline__ void constraint_point(const double* __restrict__ U, size_t fs, int c, Der& der,
                                                  const DevParams& P, double& H, double M[3], double& Hn,
                                                  bool& nonfinite) {
-  const int c = nb.base;
   nonfinite = false;
   for (int f = 0; f < NF; ++f) nonfinite = nonfinite || !isfinite(ldq(U + (size_t)f * fs, c));
   const double chi = ldq(U + F_CHI * fs, c);
@@ -41,13 +57,11 @@ __device__ __forceinline__ void constraint_point(const double* __restrict__ U, s
     for (int i = 0; i < 3; ++i) fl.S[i] += ldq(P.xsrc + (SRC_S + i) * fs, c);
     nonfinite = nonfinite || !isfinite(fl.E);
   }
-  const double nob[3] = {0.0, 0.0, 0.0};
-
   double dgt[6][3], Ric[6];
 #pragma unroll
   for (int s = 0; s < 6; ++s) {
     FieldDerivs d;
-    field_derivs<true, false, false>(U + (F_GT + s) * fs, nb, P, nob, d);
+    der.template get<true>(F_GT + s, d);
 #pragma unroll
     for (int a = 0; a < 3; ++a) dgt[s][a] = d.d1[a];
     Ric[s] = -0.5 * contract_sym(gi, d.d2);
@@ -57,7 +71,7 @@ __device__ __forceinline__ void constraint_point(const double* __restrict__ U, s
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     FieldDerivs d;
-    field_derivs<false, false, false>(U + (F_GAM + k) * fs, nb, P, nob, d);
+    der.template get<false>(F_GAM + k, d);
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
       const int i = SI(s), j = SJ(s);
@@ -67,7 +81,7 @@ __device__ __forceinline__ void constraint_point(const double* __restrict__ U, s
   double dchi[3];
   {
     FieldDerivs d;
-    field_derivs<true, false, false>(U + F_CHI * fs, nb, P, nob, d);
+    der.template get<true>(F_CHI, d);
 #pragma unroll
     for (int a = 0; a < 3; ++a) dchi[a] = d.d1[a];
     ricci_conformal_factor(1.0 / chi, dchi, d.d2, gt, gi, Gu, Ric);
@@ -89,7 +103,7 @@ __device__ __forceinline__ void constraint_point(const double* __restrict__ U, s
   double dK[3];
   {
     FieldDerivs d;
-    field_derivs<false, false, false>(U + F_K * fs, nb, P, nob, d);
+    der.template get<false>(F_K, d);
 #pragma unroll
     for (int a = 0; a < 3; ++a) dK[a] = d.d1[a];
   }
@@ -97,7 +111,7 @@ __device__ __forceinline__ void constraint_point(const double* __restrict__ U, s
 #pragma unroll
   for (int s = 0; s < 6; ++s) {
     FieldDerivs d;
-    field_derivs<false, false, false>(U + (F_AT + s) * fs, nb, P, nob, d);
+    der.template get<false>(F_AT + s, d);
 #pragma unroll
     for (int a = 0; a < 3; ++a) dAt[s][a] = d.d1[a];
   }
@@ -170,6 +184,35 @@ __device__ __forceinline__ Red block_tree(Red mine, Red* sh) {
   return red_combine(red_combine(sh[0], sh[1]), red_combine(sh[2], sh[3]));
 }
 
+// H and M_i of point p into the optional output fields.
+__device__ __forceinline__ void store_hm(size_t fs, int p, double H, const double M[3], double* __restrict__ Hout,
+                                         double* __restrict__ Mout) {
+  if (Hout) Hout[p] = H;
+  if (Mout)
+    for (int q = 0; q < 3; ++q) Mout[(size_t)q * fs + p] = M[q];
+}
+
+// The reduction record of one point.
+__device__ __forceinline__ Red point_record(const double* __restrict__ U, size_t fs, int p, double H, const double M[3],
+                                            double Hn, bool bad) {
+  Red mine = red_neutral();
+  const double Mn = sqrt(M[0] * M[0] + M[1] * M[1] + M[2] * M[2]);
+  const double aH = fabs(H);
+  mine.sH2 = H * H;
+  mine.sM2 = Mn * Mn;
+  mine.sHn2 = Hn * Hn;
+  mine.mH = (0.0 < aH) ? aH : 0.0;  // NaN never wins
+  mine.mM = (0.0 < Mn) ? Mn : 0.0;
+  mine.nbad = bad ? 1.0 : 0.0;
+  const double a = ldq(U + F_ALP * fs, p);
+  if (a < INFINITY) {
+    mine.minA = a;
+    mine.arg = (double)p;
+  }
+  return mine;
+}
+
+// Direct variant: one thread per point in linear order, stencils from global memory.
 __global__ __launch_bounds__(256) void k_constraints(const double* __restrict__ U, size_t fs, DevParams P,
                                                       double* __restrict__ Hout, double* __restrict__ Mout,
                                                       double* __restrict__ part) {
@@ -183,25 +226,12 @@ __global__ __launch_bounds__(256) void k_constraints(const double* __restrict__ 
     const int k = jk / P.n[1];
     Nbr nb;
     make_nbr(nb, i, j, k, P.n);
+    DirectDerivs der{U, fs, nb, P};
     double H, M[3], Hn;
     bool bad;
-    constraint_point(U, fs, nb, P, H, M, Hn, bad);
-    const double Mn = sqrt(M[0] * M[0] + M[1] * M[1] + M[2] * M[2]);
-    if (Hout) Hout[p] = H;
-    if (Mout)
-      for (int q = 0; q < 3; ++q) Mout[(size_t)q * fs + p] = M[q];
-    const double aH = fabs(H);
-    mine.sH2 = H * H;
-    mine.sM2 = Mn * Mn;
-    mine.sHn2 = Hn * Hn;
-    mine.mH = (0.0 < aH) ? aH : 0.0;  // NaN never wins
-    mine.mM = (0.0 < Mn) ? Mn : 0.0;
-    mine.nbad = bad ? 1.0 : 0.0;
-    const double a = ldq(U + F_ALP * fs, p);
-    if (a < INFINITY) {
-      mine.minA = a;
-      mine.arg = (double)p;
-    }
+    constraint_point(U, fs, p, der, P, H, M, Hn, bad);
+    store_hm(fs, p, H, M, Hout, Mout);
+    mine = point_record(U, fs, p, H, M, Hn, bad);
   }
   const Red r = block_tree(mine, sh);
   if (threadIdx.x == 0) red_store(part + (size_t)blockIdx.x * kRedRecord, r);

@@ -17,6 +17,7 @@
 #include "init_device.hpp"
 #include "constraints_device.hpp"
 #include "bssn_lds.hpp"
+#include "constraints_lds.hpp"
 #include "kt_device.hpp"
 #include "scalar_device.hpp"
 #include "adjoint_point.hpp"
@@ -606,6 +607,35 @@ int cosmos_rk4_step_stages(const cosmos_grid* grid, const cosmos_params* params,
   return rk4_step(grid, params, t, dt, u, stages, stages + n, stages + 2 * n, ws, stream);
 }
 
+}  // extern "C"
+
+namespace {
+
+// Constraint norms of u: the LDS-staged kernel (variant 0; 16x4x4 bricks in XCD slabs where
+// one workgroup per brick fits the workspace's partial records, else a linear stride) or the
+// direct one (variant 1), then the fixed-order fold of the per-workgroup partials.
+void launch_constraints(const cosmos_grid* grid, const cosmos_params* params, const DevParams& P, const double* u,
+                        double* H_out, double* M_out, double* part, double* norms_dev, hipStream_t s) {
+  const size_t nb = nblocks(grid);  // partial records the workspace holds
+  unsigned nparts = (unsigned)nb;
+  if (params->variant == 0) {
+    cosmos_params bp{};
+    bp.tile_x = 16, bp.tile_y = 4, bp.tile_z = 4, bp.tile_order = 0;
+    Tile T;
+    make_tile(grid, &bp, T);
+    if (tile_blocks(T) > nb) T.xcd_order = 0;
+    nparts = (unsigned)std::min<size_t>(T.xcd_order ? tile_blocks(T) : (size_t)T.nbricks, nb);
+    hipLaunchKernelGGL(k_constraints_lds, dim3(nparts), dim3(kBlock), 0, s, u, npts(grid), P, T, H_out, M_out, part);
+  } else {
+    hipLaunchKernelGGL(k_constraints, dim3(nparts), dim3(kBlock), 0, s, u, npts(grid), P, H_out, M_out, part);
+  }
+  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kBlock), 0, s, part, (int)nparts, npts(grid), norms_dev);
+}
+
+}  // namespace
+
+extern "C" {
+
 int cosmos_constraints(const cosmos_grid* grid, const cosmos_params* params, const double* u, double* norms_dev,
                        double* H_out, double* M_out, void* ws, void* stream) {
   int rc;
@@ -617,10 +647,7 @@ int cosmos_constraints(const cosmos_grid* grid, const cosmos_params* params, con
   const Layout L = layout(grid);
   double* part = (double*)((char*)ws + L.partials);
   const DevParams P = dev_params(grid, params);
-  const size_t nb = nblocks(grid);
-  hipStream_t s = (hipStream_t)stream;
-  hipLaunchKernelGGL(k_constraints, dim3(nb), dim3(kBlock), 0, s, u, npts(grid), P, H_out, M_out, part);
-  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kBlock), 0, s, part, (int)nb, npts(grid), norms_dev);
+  launch_constraints(grid, params, P, u, H_out, M_out, part, norms_dev, (hipStream_t)stream);
   HIP_TRY(hipGetLastError());
   return COSMOS_OK;
 }

@@ -152,6 +152,32 @@ def test_constraints_parity(P, orc):
     assert g[7] == r[7] and g[6] == r[6]
 
 
+@pytest.mark.parametrize("n", [(32, 32, 32), (20, 20, 12), (9, 13, 11), (16, 20, 12)])
+def test_constraints_lds_equals_direct(P, orc, n):
+    """The LDS-staged constraint kernel (variant 0) against the direct one (variant 1): the
+    same point arithmetic, so H and M_i agree bitwise; the norms differ only in the order of
+    their sums. Grids: one workgroup per brick in XCD slabs (32^3), more bricks than partial
+    records so that workgroups stride over several bricks (20x20x12), ragged bricks (9x13x11,
+    16x20x12). The LDS variant is also checked against the oracle's fields."""
+    L = tuple(0.25 * x for x in n)
+    s = orc.Setup(n=n, L=L)
+    u = to_dev(fuzz_state(n, seed=21))
+    out = {}
+    for variant in (0, 1):
+        sol = P.Solver(n, L, P.make_params(variant=variant))
+        sol.set_state(u)
+        norms, H, M = sol.constraints(want_fields=True)
+        out[variant] = (norms.numpy(), H.cpu().numpy(), M.cpu().numpy())
+    (n0, H0, M0), (n1, H1, M1) = out[0], out[1]
+    assert np.array_equal(H0, H1) and np.array_equal(M0, M1)
+    np.testing.assert_allclose(n0[[0, 2, 4]], n1[[0, 2, 4]], rtol=1e-13)
+    assert np.array_equal(n0[[1, 3, 5, 6, 7]], n1[[1, 3, 5, 6, 7]])
+    rn, rH, rM = orc.constraints(s, u.cpu().numpy(), want_fields=True)
+    assert np.abs(H0 - rH).max() < 1e-12 * np.abs(rH).max()
+    assert np.abs(M0 - rM).max() < 1e-12 * np.abs(rM).max()
+    np.testing.assert_allclose(n0[:5], rn[:5], rtol=1e-12)
+
+
 def test_determinism_bitwise(P, orc):
     s, sol, ini = c1_setup(P, orc)
     outs = []
