@@ -37,6 +37,8 @@ Extra modes:
   --no-cpu       skip the CPU baseline leg
   --config K     fixed configuration (lds|direct:BXxBYxBZ:xcd|linear|blocked) instead of the autotuner
 
+roofline.achievable holds this device's measured peaks (STREAM triad bandwidth and FP64 FMA
+rate, libcosmos_probe.so) beside the published ones that roofline.frac uses.
 roofline.traffic is the HBM bytes per stage launch from committed rocprofv3 counters
 (profiles/k_bssn_stage_lds_256cubed_traffic.txt), reported only while the stage-kernel
 sources, the configuration and the grid are the ones those counters were taken on.
@@ -126,6 +128,61 @@ def measured_traffic(cfg, npts):
         return round((fetch + write) * 1024.0)
     except (OSError, KeyError, ValueError):
         return None
+
+
+def machine_probes():
+    """Achievable peaks of this device, beside the published ones the fractions use:
+    STREAM triad a = b + s c over three 2 GiB FP64 arrays (24 B per element) and FP64
+    FMA throughput (16 independent chains per thread, 1 M threads), each timed with HIP
+    events over 20 launches on the launch stream (libcosmos_probe.so, cosmos_probe.h)."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(HERE, "paper_2606_02053_amd", "libcosmos_probe.so"))
+    lib.cosmos_probe_triad.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                       ctypes.c_size_t, ctypes.c_void_p]
+    lib.cosmos_probe_fma64.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p]
+    lib.cosmos_probe_fma64_flops.argtypes = [ctypes.c_size_t, ctypes.c_int]
+    lib.cosmos_probe_fma64_flops.restype = ctypes.c_double
+    stream = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(stream.cuda_stream)
+
+    def timed(call, reps=20):
+        for _ in range(3):
+            call()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            call()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3 / reps
+
+    n = 1 << 28
+    a = torch.empty(n, dtype=torch.float64, device="cuda")
+    b = torch.full((n,), 1.0, dtype=torch.float64, device="cuda")
+    c = torch.full((n,), 2.0, dtype=torch.float64, device="cuda")
+
+    def triad():
+        if lib.cosmos_probe_triad(a.data_ptr(), b.data_ptr(), c.data_ptr(), 3.0, n, sp) != 0:
+            raise RuntimeError("cosmos_probe_triad failed")
+    t_triad = timed(triad)
+    if not bool((a == 7.0).all()):
+        raise RuntimeError("triad probe produced wrong values")
+    del a, b, c
+    nthreads, iters = 1 << 20, 4096
+    out = torch.empty(nthreads, dtype=torch.float64, device="cuda")
+
+    def fma():
+        if lib.cosmos_probe_fma64(out.data_ptr(), nthreads, iters, sp) != 0:
+            raise RuntimeError("cosmos_probe_fma64 failed")
+    t_fma = timed(fma)
+    if not bool(torch.isfinite(out).all()):
+        raise RuntimeError("FMA probe produced non-finite values")
+    gbs = 24.0 * n / t_triad / 1e9
+    tfl = lib.cosmos_probe_fma64_flops(nthreads, iters) / t_fma / 1e12
+    return {"hbm_triad_gbs": round(gbs, 1), "hbm_triad_frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+            "fp64_fma_tflops": round(tfl, 2), "fp64_fma_frac_of_peak": round(tfl / FP64_PEAK_TFLOPS, 4),
+            "triad_ms": round(t_triad * 1e3, 4), "fma_ms": round(t_fma * 1e3, 4)}
 
 
 def copy_probe():
@@ -574,6 +631,9 @@ def main():
             "avg_launch_ms": round(launch_s * 1e3, 4),
             "fp64_tflops_algorithmic": round(fl * npts * a.steps / (ms / 1e3) / 1e12, 2),
             "fp64_frac": round(fl * npts * a.steps / (ms / 1e3) / 1e12 / FP64_PEAK_TFLOPS, 4)}
+    ach = machine_probes()
+    roof["achievable"] = ach
+    roof["frac_of_achievable_hbm"] = round(achieved / ach["hbm_triad_gbs"], 4)
     out = {"metric": METRIC, "value": value, "unit": "point-updates/s", "n_gpus": 1, "steps": a.steps,
            "warmup": a.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",

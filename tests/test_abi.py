@@ -138,3 +138,27 @@ def test_scalar_entry_points_validate_on_host(C):
     ini = C.make_init()
     rc = lib.cosmos_init_fields_scalar(ctypes.byref(g), ctypes.byref(p), ctypes.byref(ini), 0.1, 0.0, u, s, None)
     assert rc == C.COSMOS_EINVAL
+
+
+def test_probe_library_exports_and_rejects_bad_arguments():
+    """libcosmos_probe.so (machine probes for the benchmark's achievable peaks) exports every
+    function include/cosmos_probe.h declares and rejects invalid arguments on the host."""
+    src = open(os.path.join(ROOT, "include", "cosmos_probe.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = sorted(set(re.findall(r"\b(cosmos_probe_[a-z0-9_]+)\s*\(", src)))
+    assert len(names) == 3
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2606_02053_amd", "libcosmos_probe.so"))
+    assert all(hasattr(lib, n) for n in names)
+    lib.cosmos_probe_triad.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_double, ctypes.c_size_t, ctypes.c_void_p]
+    lib.cosmos_probe_fma64.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p]
+    lib.cosmos_probe_fma64_flops.argtypes = [ctypes.c_size_t, ctypes.c_int]
+    lib.cosmos_probe_fma64_flops.restype = ctypes.c_double
+    fake = 1 << 20  # never dereferenced: every call below fails its host-side checks
+    assert lib.cosmos_probe_triad(None, fake, fake, 1.0, 16, None) == -1
+    assert lib.cosmos_probe_triad(fake, fake + 4096, fake + 8192, 1.0, 15, None) == -1  # odd n
+    assert lib.cosmos_probe_triad(fake + 8, fake + 4096, fake + 8192, 1.0, 16, None) == -1  # misaligned
+    assert lib.cosmos_probe_triad(fake, fake + 64, fake + 8192, 1.0, 16, None) == -1  # a overlaps b
+    assert lib.cosmos_probe_fma64(fake, 255, 10, None) == -1
+    assert lib.cosmos_probe_fma64(fake, 256, 0, None) == -1
+    assert lib.cosmos_probe_fma64(None, 256, 10, None) == -1
+    assert lib.cosmos_probe_fma64_flops(512, 100) == 2.0 * 16 * 100 * 512
