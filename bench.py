@@ -229,9 +229,39 @@ def cpu_baseline(n_steps: int, form: str = "plain"):
     run(n_steps)
     el = time.perf_counter() - t0
     what = {"plain": "", "kt": ", Kurganov-Tadmor fluxes", "scalar": ", with the scalar field"}[form]
-    return {"value": 64 ** 3 * n_steps / el, "unit": "point-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n_steps} RK4 steps of the CPU oracle on a 64^3 periodic grid (h = 1/16, mu = 0.6, "
-                      f"sigma = 2.0{what}), OpenMP over z-planes, {el:.1f} s"}
+    out = {"value": 64 ** 3 * n_steps / el, "unit": "point-updates/s", "cores": threads, "kind": "oracle",
+           "sample": f"{n_steps} RK4 steps of the CPU oracle on a 64^3 periodic grid (h = 1/16, mu = 0.6, "
+                     f"sigma = 2.0{what}), OpenMP over z-planes, {el:.1f} s"}
+    if form == "plain":
+        # one core: 2 steps of a 32^3 grid with the same spacing (the cost per point does not depend on N)
+        s1 = oracle.Setup(n=(32, 32, 32), L=(2.0, 2.0, 2.0))
+        u1 = oracle.init_fields(s1, ini)
+        t0 = time.perf_counter()
+        oracle.rk4(s1, u1, 0.0, dt, 2, parallel=False)
+        out["serial_value"] = 32 ** 3 * 2 / (time.perf_counter() - t0)
+        out["host"] = host_cpu()
+    return out
+
+
+def host_cpu():
+    """The host the CPU legs ran on: model name, logical CPUs, physical cores."""
+    model, phys = None, set()
+    try:
+        cur = {}
+        for line in open("/proc/cpuinfo"):
+            k, _, v = line.partition(":")
+            k, v = k.strip(), v.strip()
+            if k == "model name" and model is None:
+                model = v
+            if k in ("physical id", "core id"):
+                cur[k] = v
+            if not line.strip() and cur:
+                phys.add((cur.get("physical id"), cur.get("core id")))
+                cur = {}
+    except OSError:
+        pass
+    return {"cpu_model": model, "os_cpu_count": os.cpu_count(), "physical_cores": len(phys) or None,
+            "affinity_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
 
 
 def batched_bench(a):
