@@ -62,6 +62,19 @@ FP64_PEAK_TFLOPS = 78.6
 #  stage 4 reads U4, acc and writes u): 16 * 25 * 8
 BYTES_PER_POINT_STEP = 3200.0
 LAUNCHES_PER_STEP = 4
+# with the scalar field, per point and RK4 step: the plain 3200 B; k_scalar_stage reads the 15
+# geometry fields and (phi, Pi) in every stage (136 B), acc and u_n of (phi, Pi) as its mode needs
+# (0 / 32 / 32 / 16 B), and writes the 11 source arrays and the field's acc and next state
+# (120 / 120 / 120 / 104 B): 1088 B; the stage kernel reads 10 source arrays per stage (320 B)
+SCALAR_BYTES_PER_POINT_STEP = 3200.0 + 1088.0 + 320.0
+
+
+def step_roofline(point_updates_per_s, bytes_per_point_step, kernels):
+    """HBM roofline of whole RK4 steps from algorithmic bytes per point and step."""
+    gbs = point_updates_per_s * bytes_per_point_step / 1e9
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kernels,
+            "algorithmic_bytes_per_point_step": bytes_per_point_step}
 HERE = os.path.dirname(os.path.abspath(__file__))
 # sources that define the stage kernel; the committed counters apply only while they are unchanged
 STAGE_SOURCES = ["bssn_device.hpp", "bssn_lds.hpp", "cosmos.hip"]
@@ -304,6 +317,8 @@ def batched_bench(a):
            "serial_plain_value": len(runs) / (plain_ms * total_steps / 1e3), "speedup_vs_serial": plain_ms / ms_step,
            "ms_per_batched_step": ms_step, "ms_per_serial_step_sum": plain_ms, "points_per_step": pts,
            "point_updates_per_s": pts / (ms_step / 1e3), "timed_steps": a.batched_steps,
+           "roofline": step_roofline(pts / (ms_step / 1e3), BYTES_PER_POINT_STEP,
+                                     "k_batch_stage over the (run, brick) work list + flux pre-pass, whole RK4 steps"),
            "higher_is_better": True, "dtype": "f64", "data": "synthetic",
            "config": {"workload": "64 runs, n from {48,64,80,96} (numpy default_rng(2606)), mu U[0.3,0.8], "
                                   "sigma U[0.8,1.6], L = 12/H0, CFL 0.25, hipGraph-replayed RK4 steps"}}
@@ -413,6 +428,9 @@ def scalar_bench(a, kv=0, tile=(16, 4, 4), order=2):
     return {"metric": "grid-point RK4 updates/sec FP64 at 256^3 with the massless scalar field",
             "value": n ** 3 / (ms[True] / 1e3), "unit": "point-updates/s", "ms_per_step": ms[True],
             "plain_ms_per_step": ms[False], "cost_vs_plain": ms[True] / ms[False], "steps": a.steps,
+            "roofline": step_roofline(n ** 3 / (ms[True] / 1e3), SCALAR_BYTES_PER_POINT_STEP,
+                                      "k_scalar_stage + flux pre-pass + stage kernel with the sources, whole RK4 "
+                                      "steps"),
             **({} if a.no_cpu else {"cpu_baseline": cpu_baseline(5, "scalar")}),
             "higher_is_better": True, "dtype": "f64", "data": "synthetic",
             "config": {"workload": f"as the headline ({n}^3, L = 16/H0, zeta mu = 0.6, sigma = 2.0, CFL 0.25) with "
