@@ -22,6 +22,7 @@ struct DirectDerivs {
   size_t fs;
   const Nbr& nb;
   const DevParams& P;
+  __device__ __forceinline__ void pin(double&) {}  // no barriers here: nothing to anchor
   template <bool SECOND>
   __device__ __forceinline__ void get(int f, FieldDerivs& d) {
     const double nob[3] = {0.0, 0.0, 0.0};
@@ -32,6 +33,9 @@ struct DirectDerivs {
 // H, M_i and the normalised H at the point with linear index c. Der supplies the
 // first (and, with SECOND, second) centred derivatives of a field; it is asked for
 // them in a fixed order: gt_ij (6, with second), Gt^i (3), chi (with second), K, At_ij (6).
+// der.pin(x) marks a running value as final for the current field (a source with barriers
+// between fields keeps it in a register there instead of recomputing it later from every
+// field's derivatives); it changes no value.
 template <class Der>
 __device__ __forceinline__ void constraint_point(const double* __restrict__ U, size_t fs, int c, Der& der,
                                                  const DevParams& P, double& H, double M[3], double& Hn,
@@ -65,9 +69,16 @@ __device__ __forceinline__ void constraint_point(const double* __restrict__ U, s
 #pragma unroll
     for (int a = 0; a < 3; ++a) dgt[s][a] = d.d1[a];
     Ric[s] = -0.5 * contract_sym(gi, d.d2);
+    der.pin(Ric[s]);
   }
   double Gu[3][6], Gd[3];
   connection_and_quadratic_ricci(dgt, gi, Gu, Gd, Ric);
+#pragma unroll
+  for (int q = 0; q < 6; ++q) der.pin(Ric[q]);
+#pragma unroll
+  for (int l = 0; l < 3; ++l)
+#pragma unroll
+    for (int q = 0; q < 6; ++q) der.pin(Gu[l][q]);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     FieldDerivs d;
@@ -76,6 +87,7 @@ __device__ __forceinline__ void constraint_point(const double* __restrict__ U, s
     for (int s = 0; s < 6; ++s) {
       const int i = SI(s), j = SJ(s);
       Ric[s] += 0.5 * (gt[S(k, i)] * d.d1[j] + gt[S(k, j)] * d.d1[i]);
+      der.pin(Ric[s]);
     }
   }
   double dchi[3];
@@ -85,6 +97,8 @@ __device__ __forceinline__ void constraint_point(const double* __restrict__ U, s
 #pragma unroll
     for (int a = 0; a < 3; ++a) dchi[a] = d.d1[a];
     ricci_conformal_factor(1.0 / chi, dchi, d.d2, gt, gi, Gu, Ric);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) der.pin(Ric[q]);
   }
   const double R = chi * contract_sym(gi, Ric);
 
@@ -99,6 +113,7 @@ __device__ __forceinline__ void constraint_point(const double* __restrict__ U, s
 #pragma unroll
     for (int j = 0; j < 3; ++j) AA += Amix[i][j] * Amix[j][i];
   H = R + (2.0 / 3.0) * K * K - AA - 16.0 * PI_D * fl.E;
+  der.pin(H);
 
   double dK[3];
   {

@@ -37,6 +37,9 @@ struct LdsDerivs {
   const DevParams& P;
   bool& odd;
   int phase;
+  // an empty register constraint: the value must exist here, so the algebra that forms it
+  // stays in this field's phase
+  __device__ __forceinline__ void pin(double& x) { asm volatile("" : "+v"(x)); }
   template <bool SECOND>
   __device__ __forceinline__ void get(int /*f: equals kConsOrder[phase]*/, FieldDerivs& d) {
     double* buf = odd ? buf1 : buf0;
@@ -63,10 +66,12 @@ struct LdsDerivs {
 // T: 16x4x4 bricks; with T.xcd_order, workgroup w takes brick (w mod 8) * T.per + w / 8,
 // so each XCD walks its own slab of brick layers (launched with one workgroup per
 // brick); otherwise workgroups stride over the bricks in linear order. One partial
-// record per workgroup (its bricks folded in walk order).
-__global__ __launch_bounds__(256) void k_constraints_lds(const double* __restrict__ U, size_t fs, DevParams P, Tile T,
-                                                          double* __restrict__ Hout, double* __restrict__ Mout,
-                                                          double* __restrict__ part) {
+// record per workgroup (its bricks folded in walk order). Two waves per SIMD (two
+// workgroups per CU, so one works while the other waits at a field barrier): 256
+// registers with about 100 spilled, faster than one wave per SIMD without spills.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_constraints_lds(
+    const double* __restrict__ U, size_t fs, DevParams P, Tile T, double* __restrict__ Hout,
+    double* __restrict__ Mout, double* __restrict__ part) {
   __shared__ double lds[ConsBrick::LDS_DOUBLES];
   __shared__ Red sh[4];
   double* buf0 = lds;
