@@ -448,9 +448,11 @@ void fluid_flux(const Params& p, const T u[NF], T out[12]) {
 //   d_t phi = alpha Pi + beta^k d_k phi,
 //   d_t Pi  = beta^k d_k Pi + alpha K Pi + alpha gamma^ij (d_i d_j phi - Gamma^k_ij d_k phi)
 //             + gamma^ij d_i alpha d_j phi,
-// with gamma^ij = chi gt^ij and gamma^ij Gamma^k_ij = chi Gt^k + 1/2 gt^kl d_l chi, Gt^k the
-// evolved connection functions (the usual BSSN choice for second derivatives of a
-// matter field; they equal gt^ij Gt^k_ij where the Gt constraint holds).
+// with gamma^ij = chi gt^ij and gamma^ij Gamma^k_ij = chi Gd^k + 1/2 gt^kl d_l chi, where
+// Gd^k = gt^ij Gt^k_ij is formed from the conformal metric's first derivatives (the same
+// rule as in the geometry: the evolved Gt^k enter only through their own derivatives, their
+// advection and the shift condition). This makes the operator the covariant Laplacian of
+// the physical metric gt_ij / chi whatever the evolved Gt^k hold.
 // Projections of T^SC on the normal frame (the sources of the geometry):
 //   E = 1/2 (Pi^2 + |D phi|^2),  S_i = -Pi d_i phi,
 //   S_ij = d_i phi d_j phi - 1/2 gamma_ij (|D phi|^2 - Pi^2),  S = 3/2 Pi^2 - 1/2 |D phi|^2.
@@ -741,7 +743,7 @@ bool rhs_point(const Params& p, double t, const GeomIn<T>& in, T Et, const T St[
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) lap = lap + gi[SYM[i][j]] * sc->d2phi[SYM[i][j]];
     for (int k = 0; k < 3; ++k) {
-      T gk = in.Gam[k];  // the evolved connection functions (equal to Gd^k where the Gt constraint holds)
+      T gk = G.Gd[k];  // contracted connection of the conformal metric (not the evolved Gt^k)
       for (int l = 0; l < 3; ++l) gk = gk + gi[SYM[k][l]] * in.dchi[l] / (T(2.0) * chi);
       lap = lap - gk * sc->dphi[k];
     }

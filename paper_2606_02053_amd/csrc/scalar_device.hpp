@@ -3,8 +3,11 @@
 // equation box phi = 0), evolved as phi and Pi = n^mu d_mu phi in a separate
 // 2-field state (field-major: phi, then Pi). The 3+1 form of box phi = 0:
 //   d_t phi = alpha Pi + beta^k d_k phi,
-//   d_t Pi  = beta^k d_k Pi + alpha K Pi + alpha chi (gt^ij d_i d_j phi - (Gt^k + gt^kl d_l chi / 2 chi) d_k phi)
-//             + chi gt^ij d_i alpha d_j phi   (Gt^k the evolved connection functions),
+//   d_t Pi  = beta^k d_k Pi + alpha K Pi + alpha chi (gt^ij d_i d_j phi - (Gd^k + gt^kl d_l chi / 2 chi) d_k phi)
+//             + chi gt^ij d_i alpha d_j phi,
+// Gd^k = gt^ij Gt^k_ij the contracted connection of the conformal metric, formed from its first
+// derivatives (the evolved Gt^k enter the system only through their own derivatives, their
+// advection and the shift condition), so the operator is the covariant Laplacian of gt_ij / chi,
 // plus Kreiss-Oliger dissipation on both fields; its normal-frame densities,
 // the sources it adds to the geometry:
 //   E = 1/2 (Pi^2 + |D phi|^2), S = 3/2 Pi^2 - 1/2 |D phi|^2, S_j = -Pi d_j phi,
@@ -36,8 +39,32 @@ __device__ __forceinline__ void scalar_point(const double* __restrict__ U, const
   for (int a = 0; a < 3; ++a) beta[a] = ldq(U + (F_BET + a) * fs, c);
   inv_sym(gt, gi);
   const double nob[3] = {0.0, 0.0, 0.0};
-  // the evolved connection functions (equal to gt^ij Gt^k_ij where the Gt constraint holds)
-  const double Gt[3] = {ldq(U + (F_GAM + 0) * fs, c), ldq(U + (F_GAM + 1) * fs, c), ldq(U + (F_GAM + 2) * fs, c)};
+  // Contracted connection Gd^k = gt^ij Gt^k_ij = gt^kl (A_l - B_l / 2), A_l = gt^xy d_x gt_ly,
+  // B_l = gt^xy d_l gt_xy, accumulated one metric component at a time (the 18 first
+  // derivatives are never live together): component ab with derivative d_c adds
+  // gt^cb d_c gt_ab to A_a (and gt^ca d_c gt_ab to A_b if a != b) and w gt^ab d_c gt_ab to B_c
+  // (w = 2 off the diagonal).
+  double Gd[3];
+  {
+    double A[3] = {0.0, 0.0, 0.0}, B[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      FieldDerivs d;
+      field_derivs<false, false, false>(U + (F_GT + q) * fs, nb, P, nob, d);
+      const int a = SI(q), b = SJ(q);
+      const double w = (a == b) ? 1.0 : 2.0;
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) {
+        A[a] += gi[S(cc, b)] * d.d1[cc];
+        if (a != b) A[b] += gi[S(cc, a)] * d.d1[cc];
+        B[cc] += w * gi[q] * d.d1[cc];
+      }
+    }
+#pragma unroll
+    for (int l = 0; l < 3; ++l) A[l] -= 0.5 * B[l];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) Gd[k] = gi[S(k, 0)] * A[0] + gi[S(k, 1)] * A[1] + gi[S(k, 2)] * A[2];
+  }
   double dchi[3], dal[3];
   {
     FieldDerivs d;
@@ -74,7 +101,7 @@ __device__ __forceinline__ void scalar_point(const double* __restrict__ U, const
   double lap = contract_sym(gi, dphi.d2);
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const double gk = Gt[a] + (gi[S(a, 0)] * dchi[0] + gi[S(a, 1)] * dchi[1] + gi[S(a, 2)] * dchi[2]) * (0.5 * ichi);
+    const double gk = Gd[a] + (gi[S(a, 0)] * dchi[0] + gi[S(a, 1)] * dchi[1] + gi[S(a, 2)] * dchi[2]) * (0.5 * ichi);
     lap -= gk * dphi.d1[a];
   }
   double dad = 0.0;
@@ -101,10 +128,10 @@ __device__ __forceinline__ void scalar_point(const double* __restrict__ U, const
 }
 
 // The scalar stage of one grid: one thread per point of a 16x4x4 brick (bricks in XCD
-// slabs, so the stencil halos of neighbouring bricks meet in one L2); 4 waves per SIMD,
-// the register budget the point evaluation fits without spilling.
+// slabs, so the stencil halos of neighbouring bricks meet in one L2). The compiler's own
+// register choice (2 waves per SIMD, no spills) is kept: a cap at 3 or 4 waves spills.
 template <int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_scalar_stage(
+__global__ __launch_bounds__(256) void k_scalar_stage(
     const double* __restrict__ U, const double* __restrict__ Sc, double* __restrict__ src,
     const double* __restrict__ sun, double* __restrict__ sacc, double* __restrict__ sout, size_t fs, DevParams P,
     Tile T, double ca, double cn) {

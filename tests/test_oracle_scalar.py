@@ -144,3 +144,87 @@ def test_point_sampled_forms_match_full_grid(orc):
     qu, qs = orc.rk4_sc_at_points(s, u, sc, pts, 0.3, dt)
     assert np.allclose(qu, u1.reshape(25, -1)[:, pts].T, rtol=0, atol=1e-13)
     assert np.allclose(qs, s1.reshape(2, -1)[:, pts].T, rtol=0, atol=1e-13)
+
+
+def _modes(rng, count, mmax=2):
+    out = []
+    for _ in range(count):
+        m = rng.integers(-mmax, mmax + 1, size=3)
+        if not m.any():
+            m[0] = 1
+        out.append((m, rng.uniform(0.5, 1.0), rng.uniform(0, 2 * np.pi)))
+    return out
+
+
+def _analytic(X, L, c0, amp, modes):
+    """f = c0 + amp * sum_q a_q sin(2 pi m_q.x / L + ph_q) / sum_q a_q with its exact first and
+    second derivatives: (f, df[3], d2f[3][3]) on the coordinate arrays X = (x, y, z)."""
+    wsum = sum(a for _, a, _ in modes)
+    f = np.full(X[0].shape, c0, dtype=float)
+    df = np.zeros((3,) + X[0].shape)
+    d2f = np.zeros((3, 3) + X[0].shape)
+    for m, a, ph in modes:
+        kv = 2 * np.pi * np.asarray(m, dtype=float) / L
+        th = kv[0] * X[0] + kv[1] * X[1] + kv[2] * X[2] + ph
+        w = amp * a / wsum
+        f += w * np.sin(th)
+        for i in range(3):
+            df[i] += w * kv[i] * np.cos(th)
+            for j in range(3):
+                d2f[i, j] -= w * kv[i] * kv[j] * np.sin(th)
+    return f, df, d2f
+
+
+def test_wave_operator_is_covariant_laplacian_4th_order(orc):
+    """With alpha = 1, beta = 0, K = Pi = 0 and no dissipation, d_t Pi is the covariant Laplacian of
+    phi in the physical metric g_ij = gt_ij / chi. Reference: g^ij (d_i d_j phi - Gamma^k_ij d_k phi)
+    with the Christoffel symbols of g_ij from exact derivatives of analytic chi, gt_ij, phi (the
+    generic metric formula, not the conformal decomposition). The state's evolved connection
+    functions are set to zero, unequal to gt^ij Gt^k_ij of this metric: the operator must not
+    depend on them, so the error falls at 4th order under grid doubling. (An operator built with
+    the evolved Gt^k in place of the metric's contracted connection has an O(1) error here.)"""
+    rng = np.random.default_rng(44)
+    L = 4.0
+    spec = {"chi": (1.0, 0.15, _modes(rng, 2)), "phi": (0.0, 0.3, _modes(rng, 3))}
+    gt_spec = []
+    for q in range(6):
+        diag = q in (0, 3, 5)
+        gt_spec.append((1.0 if diag else 0.0, 0.12 if diag else 0.06, _modes(rng, 2)))
+    errs = []
+    for N in (16, 32, 64):
+        s = orc.Setup(n=(N, N, N), L=(L, L, L), ko_eps=0.0, H0=0.0)
+        x = -L / 2 + (L / N) * np.arange(N)
+        Z, Y, Xx = np.meshgrid(x, x, x, indexing="ij")
+        X = (Xx, Y, Z)
+        chi, dchi, _ = _analytic(X, L, *spec["chi"])
+        phi, dphi, d2phi = _analytic(X, L, *spec["phi"])
+        gt = np.zeros((3, 3) + chi.shape)
+        dgt = np.zeros((3, 3, 3) + chi.shape)
+        sym = [(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]
+        u = np.zeros((25,) + chi.shape)
+        u[0] = chi
+        for q, (i, j) in enumerate(sym):
+            f, df, _ = _analytic(X, L, *gt_spec[q])
+            gt[i, j] = gt[j, i] = f
+            dgt[i, j] = dgt[j, i] = df
+            u[1 + q] = f
+        u[17] = 1.0
+        u[21] = 0.1  # fluid at rest: it does not enter d_t Pi
+        # physical metric, its inverse and derivatives
+        g = gt / chi
+        dg = dgt / chi - gt[:, :, None] * dchi[None, None] / chi ** 2  # dg[i, j, k] = d_k g_ij
+        gi = np.moveaxis(np.linalg.inv(np.moveaxis(g, (0, 1), (-2, -1))), (-2, -1), (0, 1))
+        lap = np.zeros_like(chi)
+        for i in range(3):
+            for j in range(3):
+                gam = np.zeros_like(chi)  # g^ij Gamma^k_ij d_k phi for this (i, j)
+                for k in range(3):
+                    for l in range(3):
+                        gam += 0.5 * gi[k, l] * (dg[l, j, i] + dg[l, i, j] - dg[i, j, l]) * dphi[k]
+                lap += gi[i, j] * (d2phi[i, j] - gam)
+        sc = np.zeros((2,) + chi.shape)
+        sc[0] = phi
+        _, ds, _ = orc.rhs_sc(s, u, sc, parallel=True)
+        errs.append(np.abs(ds[1] - lap).max() / np.abs(lap).max())
+    assert 13.0 < errs[1] / errs[2] < 19.0 and errs[0] / errs[1] > 10.0, errs
+    assert errs[2] < 1e-4, errs
