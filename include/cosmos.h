@@ -262,6 +262,19 @@ int cosmos_adjoint_step_stages(const cosmos_grid* grid, const cosmos_params* par
                                const double* u_n, const double* stages, const double* lam_np1, double* lam_n,
                                void* ws, void* stream);
 
+/* Gradient of an objective J(u_0) with respect to the initial-data parameters theta = (mu, sigma)
+ * of cosmos_init, given its adjoint lam0 = dJ/du_0 (25 * N3 device values, e.g. the result of the
+ * reverse sweep of cosmos_adjoint_step down to step 0): the last step of the discrete adjoint,
+ * dJ/dtheta_w = < lam0, d u_0 / d theta_w > = sum over points and fields of lam0 times the tangent of
+ * cosmos_init_fields that cosmos_init_tangent(which = w) writes. The tangent is formed at each point
+ * and contracted at once (never stored); the sums use a fixed order (a butterfly within each
+ * wavefront, then workgroup partials folded in workgroup order), so the result is bitwise
+ * reproducible. grad_dev: 2 device doubles (dJ/dmu, dJ/dsigma). ws: an adjoint workspace
+ * (cosmos_adjoint_workspace_bytes); its contents are overwritten. Errors: COSMOS_EINVAL (invalid
+ * grid or init, NULL or misaligned pointers, lam0 overlapping ws). */
+int cosmos_adjoint_gradient(const cosmos_grid* grid, const cosmos_params* params, const cosmos_init* init,
+                            const double* lam0, double* grad_dev, void* ws, void* stream);
+
 /* Batched form: many independent runs advanced together, one persistent launch per RK4 stage
  * for all of them (work items = (run, 16x4x4 brick)). Run r has a cubic periodic grid of n[r]^3
  * points (n[r] divisible by 16) and box L[r]; its state (25 * n[r]^3 doubles, layout as above)
@@ -304,6 +317,12 @@ size_t cosmos_batch_scalar_workspace_bytes(const cosmos_batch* batch);
 int cosmos_rk4_step_batched_scalar(const cosmos_batch* batch, const cosmos_params* params, double* arena,
                                    double* sarena, double* t_dev, const double* dt_dev, void* bws, void* sbws,
                                    void* stream);
+
+/* Per-run outcome of a scan, on the device: out_dev[2 r] = alpha at run r's centre point
+ * (n/2, n/2, n/2), out_dev[2 r + 1] = the minimum of alpha over run r's grid (order independent, so
+ * exact and reproducible). arena: the batch's state arena; bws: the workspace given to
+ * cosmos_batch_setup (its descriptor table); out_dev: 2 * nruns device doubles. Asynchronous. */
+int cosmos_batch_outcomes(const cosmos_batch* batch, const double* arena, void* bws, double* out_dev, void* stream);
 
 /* Synchronise and copy the per-run counters to host out[nruns][4] (as cosmos_status). */
 int cosmos_batch_status(const cosmos_batch* batch, void* bws, void* stream, int64_t* out);

@@ -71,10 +71,12 @@ def _load():
         "cosmos_adjoint_step_stages": ([G, Pr, f64, f64, P, P, P, P, P, P], i32),
         "cosmos_adjoint_workspace_bytes": ([G], sz),
         "cosmos_rhs_vjp": ([G, Pr, f64, P, P, P, P, P], i32),
+        "cosmos_adjoint_gradient": ([G, Pr, In, P, P, P, P], i32),
         "cosmos_batch_workspace_bytes": ([B], sz),
         "cosmos_batch_setup": ([B, Pr, P, P], i32),
         "cosmos_rk4_step_batched": ([B, Pr, P, P, P, P, P], i32),
         "cosmos_batch_status": ([B, P, P, ctypes.POINTER(ctypes.c_int64)], i32),
+        "cosmos_batch_outcomes": ([B, P, P, P, P], i32),
         "cosmos_batch_scalar_workspace_bytes": ([B], sz),
         "cosmos_rk4_step_batched_scalar": ([B, Pr, P, P, P, P, P, P, P], i32),
         "cosmos_scalar_workspace_bytes": ([G], sz),
@@ -178,6 +180,13 @@ def cosmos_init_fields(grid, params, init, u: torch.Tensor, stream=None):
 def cosmos_init_tangent(grid, params, init, which: int, du0: torch.Tensor, stream=None):
     _check(lib.cosmos_init_tangent(ctypes.byref(grid), ctypes.byref(params), ctypes.byref(init), int(which),
                                    _dev(du0, "du0", NFIELDS * npts(grid)), _stream(stream)))
+
+
+def cosmos_adjoint_gradient(grid, params, init, lam0: torch.Tensor, grad_dev: torch.Tensor, ws, stream=None):
+    _check(lib.cosmos_adjoint_gradient(ctypes.byref(grid), ctypes.byref(params), ctypes.byref(init),
+                                       _dev(lam0, "lam0", NFIELDS * npts(grid)), _dev(grad_dev, "grad_dev", 2),
+                                       _dev(ws, "ws", cosmos_adjoint_workspace_bytes(grid), dtype=torch.uint8),
+                                       _stream(stream)))
 
 
 def cosmos_rhs(grid, params, t: float, u, dudt, ws, stream=None):
@@ -330,6 +339,12 @@ def cosmos_rk4_step_batched_scalar(batch, params, arena, sarena, t_dev, dt_dev, 
                                               _dev(bws, "bws", cosmos_batch_workspace_bytes(batch), dtype=torch.uint8),
                                               _dev(sbws, "sbws", cosmos_batch_scalar_workspace_bytes(batch),
                                                    dtype=torch.uint8), _stream(stream)))
+
+
+def cosmos_batch_outcomes(batch, arena, bws, out_dev, stream=None):
+    _check(lib.cosmos_batch_outcomes(ctypes.byref(batch), _dev(arena, "arena"),
+                                     _dev(bws, "bws", cosmos_batch_workspace_bytes(batch), dtype=torch.uint8),
+                                     _dev(out_dev, "out_dev", 2 * batch.nruns), _stream(stream)))
 
 
 def cosmos_batch_status(batch, bws, stream=None):

@@ -6,7 +6,7 @@ forward pass stores the state every `checkpoint_every` steps; the backward
 pass recomputes each segment from its checkpoint and applies the adjoint step
 backwards through it, starting from lambda = dJ/du(T) (a unit vector on the
 centre lapse), and finally contracts lambda_0 with the derivatives of the
-initial data in mu and sigma (cosmos_init_tangent). Where device memory allows
+initial data in mu and sigma on the device (cosmos_adjoint_gradient). Where device memory allows
 (`keep_stages`), the recomputation also keeps each step's RK4 stage states
 (cosmos_rk4_step_stages) so that the adjoint step does not evaluate them again
 (cosmos_adjoint_step_stages); the result is the same bitwise.
@@ -93,12 +93,10 @@ class CosmosRun(torch.autograd.Function):
                     C.cosmos_adjoint_step(grid, params, m * dt, dt, states[m - start], lam, lam_next, ws_adj)
                 lam, lam_next = lam_next, lam
         init = C.make_init(mu=ctx.mu, sigma=ctx.sigma, **cfg.init_kw)
-        du = torch.empty_like(lam)
-        grads = []
-        for which in (0, 1):
-            C.cosmos_init_tangent(grid, params, init, which, du)
-            grads.append(torch.dot(lam.reshape(-1), du.reshape(-1)).to(gJ.device))
-        return grads[0], grads[1], None
+        grad = torch.empty(2, dtype=torch.float64, device=dev)
+        C.cosmos_adjoint_gradient(grid, params, init, lam, grad, ws_adj)
+        grad = grad.to(gJ.device)
+        return grad[0], grad[1], None
 
 
 def central_lapse(mu, sigma, cfg: RunConfig):

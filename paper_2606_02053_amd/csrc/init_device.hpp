@@ -117,15 +117,12 @@ __device__ __forceinline__ void profile_tan(const InitArgs& a, int profile, Tan 
   }
 }
 
-// which = -1: the state; 0 / 1: its derivative with respect to mu / sigma. With a
-// scalar field (sc non-null, a.sc_mu != 0) its iso-curvature mode Upsilon = sc_mu *
-// profile(sc_sigma) sets phi = Upsilon, Pi = 0, and the fluid takes the rest of the
-// Hamiltonian constraint's energy: E_fluid = E - 1/2 chi |grad Upsilon|^2.
-__global__ __launch_bounds__(256) void k_init(InitArgs a, double* __restrict__ u, int which,
-                                              double* __restrict__ sc) {
-  const size_t N3 = (size_t)a.n[0] * a.n[1] * a.n[2];
-  const size_t p = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (p >= N3) return;
+// Initial data at point p: out[NF] receives the state (which = -1) or its derivative with
+// respect to mu / sigma (which = 0 / 1), ups the scalar field's iso-curvature mode (or its
+// derivative). With a scalar field (a.sc_mu != 0) the mode Upsilon = sc_mu * profile(sc_sigma)
+// sets phi = Upsilon, Pi = 0, and the fluid takes the rest of the Hamiltonian constraint's
+// energy: E_fluid = E - 1/2 chi |grad Upsilon|^2.
+__device__ __forceinline__ void init_point(const InitArgs& a, size_t p, int which, double out[NF], double& ups_out) {
   const int i = (int)(p % a.n[0]);
   const int j = (int)((p / a.n[0]) % a.n[1]);
   const int k = (int)(p / ((size_t)a.n[0] * a.n[1]));
@@ -152,18 +149,90 @@ __global__ __launch_bounds__(256) void k_init(InitArgs a, double* __restrict__ u
   }
   const Tan Et = E / (chi * tsqrt(chi));
   const bool tangent = which >= 0;
-  double out[NF];
   for (int f = 0; f < NF; ++f) out[f] = 0.0;
   out[F_CHI] = tangent ? chi.d : chi.v;
   out[F_K] = tangent ? 0.0 : K;
   out[F_ALP] = tangent ? 0.0 : 1.0;
   if (!tangent) out[F_GT + 0] = out[F_GT + 3] = out[F_GT + 5] = 1.0;
   out[F_ET] = tangent ? Et.d : Et.v;
+  ups_out = tangent ? ups.d : ups.v;
+}
+
+// which = -1: the state; 0 / 1: its derivative with respect to mu / sigma (and the
+// scalar field's initial data when sc is non-null).
+__global__ __launch_bounds__(256) void k_init(InitArgs a, double* __restrict__ u, int which,
+                                              double* __restrict__ sc) {
+  const size_t N3 = (size_t)a.n[0] * a.n[1] * a.n[2];
+  const size_t p = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= N3) return;
+  double out[NF], ups;
+  init_point(a, p, which, out, ups);
   for (int f = 0; f < NF; ++f) u[(size_t)f * N3 + p] = out[f];
   if (sc) {
-    sc[p] = tangent ? ups.d : ups.v;
+    sc[p] = ups;
     sc[N3 + p] = 0.0;
   }
 }
 
+// Sum of (v0, v1) over the 256 threads of a workgroup in a fixed order: a butterfly
+// within each wavefront (the same partner pattern every time), then the four wave
+// results in wave order. The result is valid in thread 0. `red` holds 8 doubles of LDS.
+__device__ __forceinline__ void block_sum2(double& v0, double& v1, double* red) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    v0 += __shfl_xor(v0, o);
+    v1 += __shfl_xor(v1, o);
+  }
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[2 * wv] = v0;
+    red[2 * wv + 1] = v1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    v0 = ((red[0] + red[2]) + red[4]) + red[6];
+    v1 = ((red[1] + red[3]) + red[5]) + red[7];
+  }
+}
+
+// Gradient of an objective J(u_0(mu, sigma)) from its adjoint lam = dJ/du_0:
+// part[2 b + w] = sum over the points of workgroup b of sum_f lam[f] d u_0[f] / d theta_w,
+// theta = (mu, sigma), with the initial-data tangent formed at the point (the fields whose
+// tangent is not identically zero: chi and Et). Workgroup b takes points b*256 + t +
+// m * gridDim.x * 256; k_sum_partials2 folds the partials in workgroup order.
+__global__ __launch_bounds__(256) void k_adjoint_gradient(InitArgs a, const double* __restrict__ lam,
+                                                          double* __restrict__ part) {
+  __shared__ double red[8];
+  const size_t N3 = (size_t)a.n[0] * a.n[1] * a.n[2];
+  double g0 = 0.0, g1 = 0.0;
+  for (size_t p = (size_t)blockIdx.x * 256 + threadIdx.x; p < N3; p += (size_t)gridDim.x * 256) {
+    const double lchi = lam[(size_t)F_CHI * N3 + p], let = lam[(size_t)F_ET * N3 + p];
+    double out[NF], ups;
+    init_point(a, p, 0, out, ups);
+    g0 += lchi * out[F_CHI] + let * out[F_ET];
+    init_point(a, p, 1, out, ups);
+    g1 += lchi * out[F_CHI] + let * out[F_ET];
+  }
+  block_sum2(g0, g1, red);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = g0;
+    part[2 * blockIdx.x + 1] = g1;
+  }
+}
+
+// out[0..1] = sum over b < nparts of part[2 b + 0..1], in a fixed order (one workgroup).
+__global__ __launch_bounds__(256) void k_sum_partials2(const double* __restrict__ part, int nparts,
+                                                       double* __restrict__ out) {
+  __shared__ double red[8];
+  double v0 = 0.0, v1 = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += 256) {
+    v0 += part[2 * b];
+    v1 += part[2 * b + 1];
+  }
+  block_sum2(v0, v1, red);
+  if (threadIdx.x == 0) {
+    out[0] = v0;
+    out[1] = v1;
+  }
+}
 }  // namespace cosmos
