@@ -118,11 +118,14 @@ class Batch:
         return C.cosmos_batch_status(self.batch, self.bws)
 
     def outcomes(self):
-        """Per run: lapse at the centre point and its grid minimum."""
+        """Per run: lapse at the centre point and its grid minimum (formed on the device by
+        cosmos_batch_outcomes), with the run's status counters."""
+        dev = torch.empty(2 * len(self.runs), dtype=torch.float64, device=self.device)
+        C.cosmos_batch_outcomes(self.batch, self.arena, self.bws, dev)
+        vals = dev.cpu().tolist()
+        st = self.status()
         out = []
         for r, spec in enumerate(self.runs):
-            a = self.state(r)[17]
-            c = spec.n // 2
-            out.append({"n": spec.n, "mu": spec.mu, "sigma": spec.sigma, "alpha_centre": float(a[c, c, c]),
-                        "alpha_min": float(a.min())})
+            out.append({"n": spec.n, "mu": spec.mu, "sigma": spec.sigma, "alpha_centre": vals[2 * r],
+                        "alpha_min": vals[2 * r + 1], "collapsed": st[r]["collapsed"]})
         return out

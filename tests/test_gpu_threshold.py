@@ -1,7 +1,10 @@
-"""Threshold search (batched multisection + Newton with the adjoint derivative)
-against the oracle: the target lapse is the oracle's centre lapse at a known
-amplitude, so the threshold is that amplitude; the derivative at the root is
-checked against the oracle's exact forward-mode tangent."""
+"""Collapse-threshold search (batched multisection on the device collapse counters +
+Newton with the adjoint derivative) against the oracle: the collapse level alpha_th is
+the oracle's centre lapse at the final step for a known amplitude mu*. The centre
+lapse falls monotonically through the run and is the grid minimum (checked on the
+oracle), so the runs that push the lapse below alpha_th at some point and step are
+exactly those above mu*: the threshold is mu*. The derivative at the root is checked
+against the oracle's exact forward-mode tangent."""
 import pytest
 
 pytestmark = pytest.mark.gpu
@@ -16,9 +19,12 @@ def test_threshold_search_recovers_oracle_amplitude(orc):
     ini = orc.Init(mu=mu_star, sigma=sigma)
     u, _ = orc.rk4(s, orc.init_fields(s, ini), 0.0, dt, nsteps, parallel=True)
     target = float(u[17, c, c, c])
+    assert float(u[17].min()) == target  # the lapse is lowest at the centre
     res = find_threshold(sigma, 0.3, 0.5, target, n=n, L=L, nsteps=nsteps, K=8, rounds=2)
-    batched = [m for stage, m, _ in res.history if stage == "batched"]
-    assert len(batched) == 16 and res.batched_runs == 17
+    batched = [h for h in res.history if h[0] == "batched"]
+    assert len(batched) == 16 and res.batched_runs == 18
+    for _, m, collapsed, a_centre, a_min in batched:  # device outcomes: minimum at the centre
+        assert collapsed == (m > mu_star) and a_min == a_centre
     # the final bracket closes on the root of the GPU's J, which differs from the oracle's
     # amplitude by rounding only
     lo, hi = res.bracket
@@ -48,4 +54,4 @@ def test_isocurvature_threshold_by_multisection(orc):
     lo, hi = res.bracket
     assert abs(hi - lo) < 0.3 / 9 ** 4 * 1.01
     assert min(lo, hi) - 1e-9 <= mu_star <= max(lo, hi) + 1e-9, res.bracket
-    assert res.batched_runs == 1 + 4 * 8
+    assert res.batched_runs == 2 + 4 * 8
