@@ -612,13 +612,14 @@ int cosmos_rk4_step_stages(const cosmos_grid* grid, const cosmos_params* params,
 namespace {
 
 // Constraint norms of u: the LDS-staged kernel (variant 0; 16x4x4 bricks in XCD slabs where
-// one workgroup per brick fits the workspace's partial records, else a linear stride) or the
-// direct one (variant 1), then the fixed-order fold of the per-workgroup partials.
+// one workgroup per brick fits the `cap` partial records at `part`, else workgroups stride over
+// the bricks) or the direct one (variant 1, one workgroup per 256 points: needs cap >=
+// nblocks), then the fixed-order fold of the per-workgroup partials.
 void launch_constraints(const cosmos_grid* grid, const cosmos_params* params, const DevParams& P, const double* u,
-                        double* H_out, double* M_out, double* part, double* norms_dev, hipStream_t s) {
-  const size_t nb = nblocks(grid);  // partial records the workspace holds
+                        double* H_out, double* M_out, double* part, size_t cap, double* norms_dev, hipStream_t s) {
+  const size_t nb = std::min(nblocks(grid), cap);
   unsigned nparts = (unsigned)nb;
-  if (params->variant == 0) {
+  if (params->variant == 0 || cap < nblocks(grid)) {
     cosmos_params bp{};
     bp.tile_x = 16, bp.tile_y = 4, bp.tile_z = 4, bp.tile_order = 0;
     Tile T;
@@ -647,7 +648,7 @@ int cosmos_constraints(const cosmos_grid* grid, const cosmos_params* params, con
   const Layout L = layout(grid);
   double* part = (double*)((char*)ws + L.partials);
   const DevParams P = dev_params(grid, params);
-  launch_constraints(grid, params, P, u, H_out, M_out, part, norms_dev, (hipStream_t)stream);
+  launch_constraints(grid, params, P, u, H_out, M_out, part, nblocks(grid), norms_dev, (hipStream_t)stream);
   HIP_TRY(hipGetLastError());
   return COSMOS_OK;
 }
@@ -657,3 +658,4 @@ int cosmos_constraints(const cosmos_grid* grid, const cosmos_params* params, con
 #include "batch.hip.inc"
 #include "adjoint.hip.inc"
 #include "scalar.hip.inc"
+

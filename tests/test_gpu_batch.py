@@ -136,3 +136,98 @@ def test_batched_scalar_field_equals_plain_bitwise(P, scheme):
         assert torch.equal(b.scalar_state(r), s.s), r
         assert b.scalar_state(r)[1].abs().max() > 0  # the field moves
     assert all(x["steps"] == 3 and x["nonfinite"] == 0 for x in b.status())
+
+
+def _err_fields(gpu, ref):
+    """Parity metric per field: ||gpu_f - ref_f||_inf / max(||ref_f||_inf, 1e-3), max over fields."""
+    gpu = np.asarray(gpu).reshape(25, -1)
+    ref = np.asarray(ref).reshape(25, -1)
+    return (np.abs(gpu - ref).max(axis=1) / np.maximum(np.abs(ref).max(axis=1), 1e-3)).max()
+
+
+def test_batched_runs_match_oracle(P, orc):
+    """Every run of a small batch (16^3, 32^3, 48^3 and a second 16^3 in other boxes) after 3 RK4
+    steps (one eager, two graph replays) against the oracle's full-grid run."""
+    from paper_2606_02053_amd.batch import Batch
+    runs = small_runs()
+    b = Batch(runs)
+    b.init()
+    b.step()
+    b.capture()
+    b.run(2)
+    torch.cuda.synchronize()
+    for r, spec in enumerate(runs):
+        s = orc.Setup(n=(spec.n,) * 3, L=(spec.L,) * 3)
+        u0 = orc.init_fields(s, orc.Init(mu=spec.mu, sigma=spec.sigma))
+        dt = 0.25 * spec.L / spec.n
+        ref, _ = orc.rk4(s, u0, 0.0, dt, 3, parallel=True)
+        e = _err_fields(b.state(r).cpu().numpy(), ref)
+        assert e < 1e-10, (r, e)
+
+
+def test_c4_draw_subset_trajectories_match_oracle(P, orc):
+    """The first run of each grid size in the seeded 64-run scan (48^3, 64^3, 80^3, 96^3, box 12,
+    its drawn mu and sigma) batched together for 5 RK4 steps in graph replays, each against the
+    oracle's full-grid 5-step run."""
+    from paper_2606_02053_amd.batch import Batch, draw_scan
+    draw = draw_scan()
+    pick = []
+    for size in (48, 64, 80, 96):
+        pick.append(next(r for r in draw if r.n == size))
+    b = Batch(pick)
+    b.init()
+    b.capture()
+    b.run(5)
+    torch.cuda.synchronize()
+    for r, spec in enumerate(pick):
+        s = orc.Setup(n=(spec.n,) * 3, L=(spec.L,) * 3)
+        u0 = orc.init_fields(s, orc.Init(mu=spec.mu, sigma=spec.sigma))
+        ref, _ = orc.rk4(s, u0, 0.0, 0.25 * spec.L / spec.n, 5, parallel=True)
+        e = _err_fields(b.state(r).cpu().numpy(), ref)
+        print(f"C4 run n={spec.n} mu={spec.mu:.4f} sigma={spec.sigma:.4f}: 5 steps, error {e:.3e}")
+        assert e < 1e-10, (spec, e)
+
+
+def test_c4_full_draw_first_step_sampled(P, orc):
+    """All 64 runs of the seeded scan (grid sizes 48^3 to 96^3 drawn with numpy's generator seeded
+    2606, mu in [0.3, 0.8], sigma in [0.8, 1.6], box 12) in one batch: after one step every run
+    matches the oracle's step at 12 sampled points (the centre and corners included)."""
+    from paper_2606_02053_amd.batch import Batch, draw_scan
+    from tests.inputs import sample_points
+    runs = draw_scan()
+    assert len(runs) == 64 and {r.n for r in runs} == {48, 64, 80, 96}
+    b = Batch(runs)
+    b.init()
+    b.capture()
+    b.run(1)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for r, spec in enumerate(runs):
+        n = (spec.n,) * 3
+        s = orc.Setup(n=n, L=(spec.L,) * 3)
+        u0 = orc.init_fields(s, orc.Init(mu=spec.mu, sigma=spec.sigma))
+        pts = sample_points(n, 12, seed=r)
+        ref = orc.rk4_at_points(s, u0, pts, 0.0, 0.25 * spec.L / spec.n)
+        got = b.state(r).reshape(25, -1)[:, torch.from_numpy(pts).cuda()].T.cpu().numpy()
+        scale = np.maximum(np.abs(ref).max(axis=0), 1e-3)
+        e = (np.abs(got - ref).max(axis=0) / scale).max()
+        worst = max(worst, e)
+        assert e < 1e-11, (r, spec, e)
+    print(f"C4 draw, 64 runs, first step at sampled points: worst error {worst:.3e}")
+    assert all(x["steps"] == 1 and x["nonfinite"] == 0 for x in b.status())
+
+
+def test_batch_outcomes_on_device(P):
+    """cosmos_batch_outcomes: each run's centre lapse and grid-minimum lapse equal the values read
+    from its state."""
+    from paper_2606_02053_amd.batch import Batch
+    runs = small_runs()
+    b = Batch(runs)
+    b.init()
+    b.run(2, use_graph=False)
+    out = b.outcomes()
+    for r, spec in enumerate(runs):
+        a = b.state(r)[17]
+        c = spec.n // 2
+        assert out[r]["alpha_centre"] == float(a[c, c, c])
+        assert out[r]["alpha_min"] == float(a.min())

@@ -357,3 +357,42 @@ def test_c2_128cubed_500_steps(P, orc):
     assert np.isfinite(h).all()
     # the constraint violation stays at the discretisation level of the data
     assert h[:, 0].max() < 20 * h[0, 0] and h[:, 2].max() < 20 * h[0, 0]
+
+
+def _stored_trajectory(name):
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
+    if not os.path.exists(path):
+        pytest.skip(f"{name} not generated (tests/golden/make_c2_trajectory.py)")
+    with open(path) as f:
+        return json.load(f)
+
+
+def test_c2_trajectory_100_steps_against_stored_oracle(P):
+    """128^3, L = 12, Gaussian zeta mu = 0.5, sigma = 1.5, CFL 0.25, KO 0.1: 100 RK4 steps from the
+    GPU's own initial data, against the oracle's 100-step state stored at 64 points (the centre
+    and its axis neighbours included) by tests/golden/make_c2_trajectory.py, with the per-field
+    scale of the parity metric taken over the oracle's whole grid; bar 1e-9. The step-100
+    constraint norms against the oracle's."""
+    g = _stored_trajectory("c2_128cubed_100steps.json")
+    cfg = g["config"]
+    n, L = (cfg["n"],) * 3, (cfg["L"],) * 3
+    sol = P.Solver(n, L)
+    assert (sol.params.variant, sol.params.tile_order) == (0, 2)  # the benchmark's launch configuration
+    sol.init(mu=cfg["mu"], sigma=cfg["sigma"])
+    dt = cfg["dt"]
+    assert dt == 0.25 * cfg["L"] / cfg["n"]
+    sol.run(cfg["steps"], dt)
+    pts = np.array(g["points"], dtype=np.int64)
+    got = sol.u.reshape(25, -1)[:, torch.from_numpy(pts).cuda()].T.cpu().numpy()
+    ref = np.array(g["values"])
+    scale = np.maximum(np.array(g["field_absmax"]), 1e-3)
+    per = (np.abs(got - ref).max(axis=0) / scale)
+    print(f"C2 100-step trajectory at {len(pts)} points: max error {per.max():.3e}")
+    assert per.max() < 1e-9, per
+    norms = sol.constraints().numpy()
+    np.testing.assert_allclose(norms[:5], np.array(g["norms"][:5]), rtol=1e-9)
+    assert norms[5] == g["norms"][5] and norms[6] == pytest.approx(g["norms"][6], rel=1e-12)
+    st = sol.status()
+    assert st["steps"] == 100 and st["nonfinite"] == 0 and st["prim_fail"] == g["prim_fail"]
