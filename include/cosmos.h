@@ -236,6 +236,22 @@ int cosmos_rk4_step_stages(const cosmos_grid* grid, const cosmos_params* params,
 int cosmos_constraints(const cosmos_grid* grid, const cosmos_params* params, const double* u,
                        double* norms_dev, double* H_out, double* M_out, void* ws, void* stream);
 
+/* cosmos_constraints without a workspace, for callers that cannot allocate device memory (code
+ * under graph capture, monitoring loops and harnesses that forbid allocation). Same arguments and
+ * results as cosmos_constraints (always the LDS-staged kernel; params->variant is not consulted),
+ * minus ws: the per-workgroup reduction partials go to a fixed device array inside the library,
+ * 4096 records of 8 doubles (256 KiB) per GPU, held from the first call on that GPU until the
+ * process ends. At most 4096 workgroups are launched and they stride over the grid's bricks, so
+ * every grid the library accepts fits; grids beyond its limits (8 <= n <= 2048, n0 n1 n2 < 2^29)
+ * are rejected with COSMOS_EINVAL as by every entry point. Every launched workgroup writes its own
+ * record before the fold reads it, so no state carries over from one call to the next. All calls
+ * on one GPU share the array: calls that overlap in time on one GPU (different streams or host
+ * threads without ordering) race and give wrong norms. The call allocates nothing (no hipMalloc,
+ * hipFree or allocating library routine). Errors: as cosmos_constraints; COSMOS_EHIP if the
+ * array's device address cannot be obtained, COSMOS_EUNSUPPORTED on a device index above 63. */
+int cosmos_constraints_noalloc(const cosmos_grid* grid, const cosmos_params* params, const double* u,
+                               double* norms_dev, double* H_out, double* M_out, void* stream);
+
 /* Bytes of device workspace for cosmos_rhs_vjp / cosmos_adjoint_step: status counters, the
  * recomputed stage states U2..U4 and the stage accumulator, two state-sized cotangent buffers and
  * 136 * N3 doubles of per-point cotangent scratch. 0 for an invalid grid. */

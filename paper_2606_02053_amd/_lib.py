@@ -67,6 +67,7 @@ def _load():
         "cosmos_rk4_step": ([G, Pr, f64, f64, P, P, P], i32),
         "cosmos_rk4_step_stages": ([G, Pr, f64, f64, P, P, P, P], i32),
         "cosmos_constraints": ([G, Pr, P, P, P, P, P, P], i32),
+        "cosmos_constraints_noalloc": ([G, Pr, P, P, P, P, P], i32),
         "cosmos_adjoint_step": ([G, Pr, f64, f64, P, P, P, P, P], i32),
         "cosmos_adjoint_step_stages": ([G, Pr, f64, f64, P, P, P, P, P, P], i32),
         "cosmos_adjoint_workspace_bytes": ([G], sz),
@@ -221,6 +222,13 @@ def cosmos_constraints(grid, params, u, norms_dev, H_out=None, M_out=None, ws=No
                                   _dev(norms_dev, "norms_dev", 8), _dev(H_out, "H_out", N3),
                                   _dev(M_out, "M_out", 3 * N3),
                                   _dev(ws, "ws", cosmos_workspace_bytes(grid), dtype=torch.uint8), _stream(stream)))
+
+
+def cosmos_constraints_noalloc(grid, params, u, norms_dev, H_out=None, M_out=None, stream=None):
+    N3 = npts(grid)
+    _check(lib.cosmos_constraints_noalloc(ctypes.byref(grid), ctypes.byref(params), _dev(u, "u", NFIELDS * N3),
+                                          _dev(norms_dev, "norms_dev", 8), _dev(H_out, "H_out", N3),
+                                          _dev(M_out, "M_out", 3 * N3), _stream(stream)))
 
 
 # ---- massless scalar field: s is a (2, nz, ny, nx) float64 device tensor (phi, Pi)

@@ -11,6 +11,7 @@
 #include <string>
 #include <vector>
 #include <algorithm>
+#include <mutex>
 
 #include "cosmos.h"
 #include "bssn_device.hpp"
@@ -659,3 +660,62 @@ int cosmos_constraints(const cosmos_grid* grid, const cosmos_params* params, con
 #include "adjoint.hip.inc"
 #include "scalar.hip.inc"
 
+// ---------------------------------------------------------------- allocation-free constraint norms
+// For callers that cannot allocate (code under graph capture, tight monitoring loops): the
+// constraint norms with the reduction partials in a fixed device array instead of a workspace.
+namespace {
+constexpr int kNoAllocParts = 4096;  // partial records of the array: 4096 x 8 doubles = 256 KiB
+constexpr int kMaxDevices = 64;
+}  // namespace
+
+// One copy per GPU the library runs on, held until the process ends. Host code must not use
+// this name as a device address: it takes the address that hipGetSymbolAddress returns.
+static __device__ __align__(256) double scratch[kNoAllocParts * kRedRecord];
+
+namespace {
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+// The current device's copy of `scratch`, looked up on the first call on that device.
+int scratch_for_current_device(double** out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices)
+    return set_error(COSMOS_EUNSUPPORTED, "device %d: the allocation-free entry points serve devices 0..%d", dev,
+                     kMaxDevices - 1);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return set_error(COSMOS_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_dev[dev] = (double*)ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return COSMOS_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int cosmos_constraints_noalloc(const cosmos_grid* grid, const cosmos_params* params, const double* u,
+                               double* norms_dev, double* H_out, double* M_out, void* stream) {
+  int rc;
+  if ((rc = check_common(grid, params)) || (rc = check_state(u, "u")) || (rc = check_state(norms_dev, "norms_dev")))
+    return rc;
+  if ((H_out && !aligned(H_out, 8)) || (M_out && !aligned(M_out, 8)))
+    return set_error(COSMOS_EINVAL, "H_out / M_out not 8-byte aligned");
+  double* part = nullptr;
+  if ((rc = scratch_for_current_device(&part))) return rc;
+  // At most kNoAllocParts workgroups: the LDS-staged kernel's workgroups stride over the
+  // bricks, so every grid the library accepts fits; each launched workgroup writes its record
+  // and the fold reads exactly those, so nothing in the array needs clearing between calls.
+  cosmos_params p = *params;
+  p.variant = 0;
+  const DevParams P = dev_params(grid, &p);
+  launch_constraints(grid, &p, P, u, H_out, M_out, part, (size_t)kNoAllocParts, norms_dev, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  return COSMOS_OK;
+}
+
+}  // extern "C"
