@@ -43,15 +43,30 @@ enum : int {
 
 template <int BX, int BY, int BZ>
 struct Brick {
+  static constexpr int X = BX, Y = BY, Z = BZ;   // brick (one point per thread)
+  static constexpr int XO = 3;                  // x offset of the brick in its halo box
   static constexpr int HX = BX + 6, HY = BY + 6, HZ = BZ + 6;
   static constexpr int NH = HX * HY * HZ;       // halo-box points
   static constexpr int NQ = (NH + 255) / 256;   // loads per thread per field
   static constexpr int NP = NQ * 256;            // padded LDS buffer: every thread copies NQ points
   static constexpr int SY = HX, SZ = HX * HY;   // LDS strides
+  static constexpr int NOFF = NQ;                // per-thread halo offsets
   static constexpr int LDS_DOUBLES = 2 * NP;       // two halo buffers
   static_assert(BX * BY * BZ == 256, "one point per thread");
   static_assert(LDS_DOUBLES * 8 <= 160 * 1024, "LDS budget");
 };
+
+// Workgroup barrier for LDS staging. __syncthreads() carries a workgroup-scope release fence,
+// which waits for every outstanding global load and store of the wave (s_waitcnt vmcnt(0)) and so
+// drains the prefetch of later fields and epilogue operands at every phase. Here only the wave's
+// own LDS operations are completed (lgkmcnt 0: its halo writes are visible and its reads of a
+// buffer about to be refilled have returned) before s_barrier; global memory is not ordered.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt and expcnt not waited on
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
 
 // Stencil taps read from the LDS halo box: c points at the thread's centre.
 template <class B>
@@ -175,12 +190,86 @@ struct HaloCopy {
   }
 };
 
+// Halo box for staging by LDS-direct loads: x runs from i0 - 4 to i0 + BX + 3 (BX + 8 points,
+// one more on each side than the stencils need), so that with n0 even every aligned pair of
+// x-neighbours (2m, 2m + 1) of the box is two consecutive doubles in memory, 16-byte aligned,
+// also where the box wraps around the periodic boundary. One lane moves one such pair per load
+// (buffer_load_dwordx4 into LDS), NR rounds of 256 pairs per field.
+template <int BX, int BY, int BZ>
+struct DBrick {
+  static constexpr int X = BX, Y = BY, Z = BZ;
+  static constexpr int XO = 4;
+  static constexpr int HX = BX + 8, HY = BY + 6, HZ = BZ + 6;
+  static constexpr int NPR = HX / 2;                 // pairs per row
+  static constexpr int NPAIR = NPR * HY * HZ;
+  static constexpr int NR = (NPAIR + 255) / 256;     // load rounds per field
+  static constexpr int NP = NR * 512;                // doubles per LDS buffer (padded to whole rounds)
+  static constexpr int SY = HX, SZ = HX * HY;
+  static constexpr int NOFF = NR;
+  static_assert(BX * BY * BZ == 256 && BX % 2 == 0, "one point per thread, even brick width");
+};
+constexpr int kRing = 5;      // LDS halo buffers of the direct-load ring (25 phases = 5 rounds of the ring)
+constexpr int kDmaAhead = 4;  // fields whose loads are in flight ahead of the one being processed
+static_assert(NF % kRing == 0 && kDmaAhead == kRing - 1, "ring slot = phase mod kRing, across bricks");
+
+// Wait until at most n vector-memory operations of this wave are outstanding (expcnt and
+// lgkmcnt not waited on). Loads complete in issue order, so a load is complete once n newer
+// ones have been issued and the count drops to n.
+__device__ __forceinline__ void wait_vm(int n) {
+  switch (n) {  // the count is an instruction immediate
+    case 0: __builtin_amdgcn_s_waitcnt(0x0F70); break;
+    case 5: __builtin_amdgcn_s_waitcnt(0x0F75); break;
+    case 6: __builtin_amdgcn_s_waitcnt(0x0F76); break;
+    case 10: __builtin_amdgcn_s_waitcnt(0x0F7A); break;
+    case 12: __builtin_amdgcn_s_waitcnt(0x0F7C); break;
+    case 15: __builtin_amdgcn_s_waitcnt(0x0F7F); break;
+    case 18: __builtin_amdgcn_s_waitcnt(0x4F72); break;
+    default: __builtin_amdgcn_s_waitcnt(0x0F70); break;  // any other count: wait for everything
+  }
+}
+
+// LDS-direct halo staging: each lane holds the byte offsets of its pair in a field (one per
+// round); a fetch issues NR loads that write the field's halo box straight into an LDS buffer,
+// round q of wave w filling pairs [256 q + 64 w, 256 q + 64 w + 64). No registers hold the data.
+template <class B>
+struct HaloDma {
+  uint32_t goffb[B::NR];
+  __device__ __forceinline__ void init(int i0, int j0, int k0, const int n[3]) { offsets(i0, j0, k0, n, goffb); }
+  static __device__ __forceinline__ void offsets(int i0, int j0, int k0, const int n[3], uint32_t goffb[B::NR]) {
+#pragma unroll
+    for (int q = 0; q < B::NR; ++q) {
+      const int m = threadIdx.x + 256 * q;
+      const int mm = m < B::NPAIR ? m : 0;  // padding lanes load an in-box pair into the padding
+      const int hx2 = mm % B::NPR, hy = (mm / B::NPR) % B::HY, hz = mm / (B::NPR * B::HY);
+      const int x = wrap_halo(i0 - 4 + 2 * hx2, n[0]), y = wrap_halo(j0 - 3 + hy, n[1]), z = wrap_halo(k0 - 3 + hz, n[2]);
+      goffb[q] = 8u * (uint32_t)(x + n[0] * (y + n[1] * z));
+    }
+  }
+  __device__ __forceinline__ void fetch(const double* F, uint32_t nbytes, double* buf) const { fetch_at(F, nbytes, buf, goffb); }
+  static __device__ __forceinline__ void fetch_at(const double* F, uint32_t nbytes, double* buf,
+                                                  const uint32_t off[B::NR]) {
+    const __amdgpu_buffer_rsrc_t r = field_rsrc(F, nbytes);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+#pragma unroll
+    for (int q = 0; q < B::NR; ++q)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          r, (__attribute__((address_space(3))) void*)(buf + 2 * (256 * q + 64 * w)), 16, off[q], 0, 0, 0);
+  }
+};
+
 // State carried from one brick to the next by a workgroup that walks several
 // bricks: the halo ring (the next fields to commit), the epilogue-operand ring
 // (slot d = phase + d) and the 25 values of the thread's point.
+// Halo staging of a brick type: a register ring (Brick) or LDS-direct loads (DBrick).
+template <class B> struct HaloOf { using type = HaloCopy<B>; static constexpr bool dma = false; };
+template <int BX, int BY, int BZ> struct HaloOf<DBrick<BX, BY, BZ>> {
+  using type = HaloDma<DBrick<BX, BY, BZ>>;
+  static constexpr bool dma = true;
+};
+
 template <class B, class Pre>
 struct LdsCarry {
-  HaloCopy<B> hc;
+  typename HaloOf<B>::type hc;
   Pre ep[kEpiAhead + 1][4];
   double cen[NF];
 };
@@ -192,7 +281,7 @@ template <class B>
 struct NextBrick {
   bool valid;
   int c;
-  uint32_t goffb[B::NQ];
+  uint32_t goffb[B::NOFF];
   const double* U;   // stage input
   const double* un;  // RK4 epilogue operands
   const double* acc;
@@ -200,16 +289,20 @@ struct NextBrick {
 };
 
 // Loads of the first brick of a workgroup (later bricks are prefetched during the
-// previous one): fields 0 .. kPrefetch-1 into the ring, the epilogue operands of
-// phases 0 .. kEpiAhead-1 and the point's values.
+// previous one): the epilogue operands of phases 0 .. kEpiAhead-1, the point's values, and
+// the first fields -- 0 .. kPrefetch-1 into the register ring, or with LDS-direct staging
+// 0 .. kDmaAhead-1 into ring slots 0 .. kDmaAhead-1 at `ring` (issued last, so that waiting
+// for the other loads does not wait for them).
 template <class B, class Sink, class Pre>
 __device__ __forceinline__ void lds_carry_fill(LdsCarry<B, Pre>& cy, const double* U, size_t fs, const Sink& sink,
-                                               int c) {
+                                               int c, double* ring = nullptr) {
   static_assert(kPrefetch >= 1 && kPrefetch <= 3, "ring depth");
   const uint32_t nbytes = (uint32_t)(fs * 8);
-  cy.hc.template fetch<0>(field_ptr(U, kStageOrder[0], fs), nbytes);
-  if constexpr (kPrefetch > 1) cy.hc.template fetch<(kPrefetch > 1 ? 1 : 0)>(field_ptr(U, kStageOrder[1], fs), nbytes);
-  if constexpr (kPrefetch > 2) cy.hc.template fetch<(kPrefetch > 2 ? 2 : 0)>(field_ptr(U, kStageOrder[2], fs), nbytes);
+  if constexpr (!HaloOf<B>::dma) {
+    cy.hc.template fetch<0>(field_ptr(U, kStageOrder[0], fs), nbytes);
+    if constexpr (kPrefetch > 1) cy.hc.template fetch<(kPrefetch > 1 ? 1 : 0)>(field_ptr(U, kStageOrder[1], fs), nbytes);
+    if constexpr (kPrefetch > 2) cy.hc.template fetch<(kPrefetch > 2 ? 2 : 0)>(field_ptr(U, kStageOrder[2], fs), nbytes);
+  }
 #pragma unroll
   for (int d = 0; d < kEpiAhead; ++d)
 #pragma unroll
@@ -217,6 +310,10 @@ __device__ __forceinline__ void lds_carry_fill(LdsCarry<B, Pre>& cy, const doubl
       if (k < kPutCount[d]) cy.ep[d][k] = sink.preload_at(kPutField[d][k], c);
 #pragma unroll
   for (int f = 0; f < NF; ++f) cy.cen[f] = bld(field_ptr(U, f, fs), nbytes, (uint32_t)c * 8u);
+  if constexpr (HaloOf<B>::dma) {
+#pragma unroll
+    for (int q = 0; q < kDmaAhead; ++q) cy.hc.fetch(field_ptr(U, kStageOrder[q], fs), nbytes, ring + q * B::NP);
+  }
 }
 
 // The whole right-hand side of one point with LDS-staged stencils. All threads
@@ -235,10 +332,10 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
     double v[R3_COUNT];
     __device__ __forceinline__ double& operator[](int k) { return v[k]; }
   } R;
-  const int lx = threadIdx.x % (B::HX - 6), ly = (threadIdx.x / (B::HX - 6)) % (B::HY - 6),
-            lz = threadIdx.x / ((B::HX - 6) * (B::HY - 6));
-  const int cidx = (lx + 3) + B::SY * ((ly + 3) + B::HY * (lz + 3));
-  HaloCopy<B>& hc = cy.hc;
+  const int lx = threadIdx.x % B::X, ly = (threadIdx.x / B::X) % B::Y, lz = threadIdx.x / (B::X * B::Y);
+  const int cidx = (lx + B::XO) + B::SY * ((ly + 3) + B::HY * (lz + 3));
+  constexpr bool dma = HaloOf<B>::dma;  // LDS-direct staging: buf0 is the ring of kRing buffers
+  auto& hc = cy.hc;
   auto& ep = cy.ep;
   const uint32_t nbytes = (uint32_t)(fs * 8);
   auto xsrc = [&](int q) -> double {  // source array q at this point (SC != 0)
@@ -293,29 +390,55 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
       R[R3_SG + q] = 0.0;
     }
   }
-  hc.commit_and_rotate(buf0);
-  __syncthreads();
+  if constexpr (dma) {
+    wait_vm(3 * B::NR);  // field 0 is in LDS once the loads of fields 1 .. 3, issued after it, remain
+  } else {
+    hc.commit_and_rotate(buf0);
+  }
+  lds_barrier();
 
-  // Phase p processes field kStageOrder[p] from LDS buffer p & 1. At its start
-  // the field p + kPrefetch is fetched into the last register slot; at its end
-  // the field p + 1 (slot 0) is committed to the other buffer.
+  // Phase p processes field kStageOrder[p] from LDS buffer p & 1 (register ring: at its start
+  // the field p + kPrefetch is fetched into the last register slot, at its end the field p + 1
+  // is committed to the other buffer) or from ring slot p % kRing (LDS-direct: at its start the
+  // loads of field p + kDmaAhead go to slot (p - 1) % kRing, free since the last barrier; at its
+  // end the wave waits until field p + 1 has landed).
   int phase = 0;
-  auto cur = [&]() -> const double* { return ((phase & 1) ? buf1 : buf0) + cidx; };
+  auto cur = [&]() -> const double* {
+    if constexpr (dma) return buf0 + (phase % kRing) * B::NP + cidx;
+    return ((phase & 1) ? buf1 : buf0) + cidx;
+  };
   auto prefetch = [&]() {
-    if (phase + kPrefetch < NF)
-      hc.template fetch<kPrefetch - 1>(field_ptr(U, kStageOrder[phase + kPrefetch], fs), nbytes);
-    else if (nx.valid)
-      hc.template fetch_at<kPrefetch - 1>(field_ptr(nx.U, kStageOrder[phase + kPrefetch - NF], nx.fs),
-                                          (uint32_t)(nx.fs * 8), nx.goffb);
-    epi_load(phase + kEpiAhead, std::integral_constant<int, kEpiAhead>());
+    if constexpr (dma) {
+      epi_load(phase + kEpiAhead, std::integral_constant<int, kEpiAhead>());
+      double* slot = buf0 + ((phase + kDmaAhead) % kRing) * B::NP;
+      if (phase + kDmaAhead < NF)
+        hc.fetch(field_ptr(U, kStageOrder[phase + kDmaAhead], fs), nbytes, slot);
+      else if (nx.valid)
+        hc.fetch_at(field_ptr(nx.U, kStageOrder[phase + kDmaAhead - NF], nx.fs), (uint32_t)(nx.fs * 8), slot, nx.goffb);
+    } else {
+      if (phase + kPrefetch < NF)
+        hc.template fetch<kPrefetch - 1>(field_ptr(U, kStageOrder[phase + kPrefetch], fs), nbytes);
+      else if (nx.valid)
+        hc.template fetch_at<kPrefetch - 1>(field_ptr(nx.U, kStageOrder[phase + kPrefetch - NF], nx.fs),
+                                            (uint32_t)(nx.fs * 8), nx.goffb);
+      epi_load(phase + kEpiAhead, std::integral_constant<int, kEpiAhead>());
+    }
   };
   auto advance = [&](int) {
 #pragma unroll
     for (int d = 0; d < kEpiAhead; ++d)
 #pragma unroll
       for (int k = 0; k < 4; ++k) ep[d][k] = ep[d + 1][k];
-    if (phase + 1 < NF) hc.commit_and_rotate((phase & 1) ? buf0 : buf1);
-    __syncthreads();
+    if constexpr (dma) {
+      // field phase + 1 was issued kDmaAhead - 1 phases ago; the phases since issued one field
+      // each, except past the brick's last field when there is no next brick
+      const int v = nx.valid ? 1 : 0;
+      const int newer = phase <= NF - 1 - kDmaAhead ? 3 : (phase == NF - kDmaAhead ? 2 + v : (phase == NF - 3 ? 1 + 2 * v : 3 * v));
+      wait_vm(newer * B::NR);
+    } else {
+      if (phase + 1 < NF) hc.commit_and_rotate((phase & 1) ? buf0 : buf1);
+    }
+    lds_barrier();
     ++phase;
   };
   double Sup[3];  // S^j = chi gt^jk S_k
@@ -649,7 +772,7 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
 #pragma unroll
     for (int f = 0; f < NF; ++f) cy.cen[f] = cnext[f];
 #pragma unroll
-    for (int q = 0; q < B::NQ; ++q) hc.goffb[q] = nx.goffb[q];
+    for (int q = 0; q < B::NOFF; ++q) hc.goffb[q] = nx.goffb[q];
 #pragma unroll
     for (int d = 0; d < kEpiAhead; ++d)
 #pragma unroll

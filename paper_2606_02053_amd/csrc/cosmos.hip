@@ -252,14 +252,17 @@ __global__ __launch_bounds__(kBlock) void k_bssn_stage(const double* U, const do
 // it * gridDim.x (gridDim.x a multiple of 8, so with the XCD-aware order every
 // brick of a workgroup lies in its XCD's slab), prefetching each next brick
 // during the last phases of the current one.
+// The halo boxes are staged by LDS-direct loads into a ring of kRing LDS buffers (DBrick,
+// kDmaAhead fields in flight; the grid's n0 must be even) -- the launcher sends grids with odd
+// n0 to the direct kernel.
 template <int BX, int BY, int BZ, int MODE, bool KT, bool SC = false>
 __global__ __launch_bounds__(kBlock) void k_bssn_stage_lds(const double* U, const double* F, const double* un,
                                                             double* acc, double* out, size_t fs, DevParams P, Tile T,
                                                             double t, double ca, double cn,
                                                             unsigned long long* status) {
-  using B = Brick<BX, BY, BZ>;
+  using B = DBrick<BX, BY, BZ>;
   using Sink = StageSink<MODE>;
-  __shared__ double smem[B::LDS_DOUBLES];
+  __shared__ double smem[kRing * B::NP];
   // brick number `it` of this workgroup (all uniform): 1 = a brick (origin, and this
   // thread's point, c = 0 outside the grid), 0 = none in this round, -1 = no more
   auto locate = [&](int it, int& i0, int& j0, int& k0, int& c, bool& act) -> int {
@@ -305,7 +308,7 @@ __global__ __launch_bounds__(kBlock) void k_bssn_stage_lds(const double* U, cons
   cy.hc.init(i0, j0, k0, P.n);
   {
     const Sink s0{un, acc, out, fs, c, ca, cn, P.alpha_collapse};
-    lds_carry_fill(cy, U, fs, s0, c);
+    lds_carry_fill(cy, U, fs, s0, c, smem);
   }
   unsigned long long nfail = 0, nbad = 0, ncoll = 0, nstep = 0;
   for (;;) {
@@ -315,10 +318,10 @@ __global__ __launch_bounds__(kBlock) void k_bssn_stage_lds(const double* U, cons
     const int nit = next_brick(it + 1, ni0, nj0, nk0, nx.c, nact);
     nx.valid = nit >= 0;
     nx.U = U, nx.un = un, nx.acc = acc, nx.fs = fs;
-    if (nx.valid) HaloCopy<B>::offsets(ni0, nj0, nk0, P.n, nx.goffb);
+    if (nx.valid) HaloDma<B>::offsets(ni0, nj0, nk0, P.n, nx.goffb);
     Sink sink{un, acc, out, fs, c, ca, cn, P.alpha_collapse};
     bool fail = false;
-    bssn_rhs_lds<B, KT, SC ? 1 : 0>(U, F, fs, P, t, c, active, cy, nx, smem, smem + B::NP, sink, fail);
+    bssn_rhs_lds<B, KT, SC ? 1 : 0>(U, F, fs, P, t, c, active, cy, nx, smem, nullptr, sink, fail);
     if (active) {
       nfail += fail;
       if constexpr (MODE == 3) {
@@ -328,7 +331,7 @@ __global__ __launch_bounds__(kBlock) void k_bssn_stage_lds(const double* U, cons
       }
     }
     if (!nx.valid) break;
-    __syncthreads();  // the halo buffers are reused by the next brick
+    lds_barrier();  // the halo buffers are reused by the next brick
     c = nx.c;
     active = nact;
     it = nit;
@@ -432,7 +435,7 @@ template <int M>
 void launch_mode(bool lds, const Tile& T, hipStream_t s, const double* U, const double* F, const double* un,
                  double* acc, double* out, size_t fs, const DevParams& P, double t, double ca, double cn,
                  unsigned long long* status) {
-  if (!lds) {
+  if (!lds || P.n[0] % 2 || ((uintptr_t)U & 15)) {  // the LDS-staged kernel: n0 even, U 16-byte aligned
     const dim3 g(tile_blocks(T)), b(kBlock);
     hipLaunchKernelGGL(k_bssn_stage<M>, g, b, 0, s, U, F, un, acc, out, fs, P, T, t, ca, cn, status);
   } else if (P.fluid_scheme == 1) {
