@@ -32,6 +32,8 @@ Extra modes:
   --c2           only the 128^3 evolution (box 12/H0, mu = 0.5, sigma = 1.5, 500 RK4 steps) with
                  the constraint norms every 10 steps, timed with and without the norms, and the
                  HBM roofline of one constraint evaluation
+  --triad-probe  only the STREAM triad probe (16 B read, 8 B written per element; a second
+                 calibration point for the counters)
   --copy-probe   only a plain device-to-device copy of known size (calibrates
                  rocprofv3 FETCH_SIZE / WRITE_SIZE counters)
   --no-cpu       skip the CPU baseline leg
@@ -89,6 +91,7 @@ def parse():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--triad-probe", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-tune", action="store_true", help="use the default tile instead of the autotuned one")
     ap.add_argument("--batched", action="store_true")
@@ -208,6 +211,26 @@ def copy_probe():
     print(json.dumps({"copy_probe_bytes_read": nbytes, "copy_probe_bytes_written": nbytes, "launches": 5}))
 
 
+def triad_probe():
+    """The STREAM triad of libcosmos_probe.so over three 2 GiB arrays, 5 launches: 16 bytes read
+    and 8 written per element, a second known-byte point (beside the copy) for scaling the
+    FETCH_SIZE / WRITE_SIZE counters."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(HERE, "paper_2606_02053_amd", "libcosmos_probe.so"))
+    lib.cosmos_probe_triad.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                       ctypes.c_size_t, ctypes.c_void_p]
+    n = 1 << 28
+    a = torch.empty(n, dtype=torch.float64, device="cuda")
+    b = torch.full((n,), 1.0, dtype=torch.float64, device="cuda")
+    c = torch.full((n,), 2.0, dtype=torch.float64, device="cuda")
+    sp = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    for _ in range(5):
+        if lib.cosmos_probe_triad(a.data_ptr(), b.data_ptr(), c.data_ptr(), 3.0, n, sp) != 0:
+            raise RuntimeError("cosmos_probe_triad failed")
+    torch.cuda.synchronize()
+    print(json.dumps({"triad_probe_bytes_read": 16 * n, "triad_probe_bytes_written": 8 * n, "launches": 5}))
+
+
 def op_counts():
     """Algorithmic FP64 operation counts (tests/golden/op_counts.json, written from the
     oracle's operation-counting scalar by tests/golden/make_golden.py):
@@ -279,10 +302,14 @@ def host_cpu():
 
 def batched_bench(a):
     import paper_2606_02053_amd as P
+    from paper_2606_02053_amd import autotune
     from paper_2606_02053_amd.batch import Batch, draw_scan
     runs = draw_scan(64, seed=2606)
     total_steps = 300
-    b = Batch(runs)
+    tile = (16, 4, 4)
+    if not a.no_tune:  # untimed: the batched stage kernel's brick for this batch (cached)
+        tile, _ = autotune.tune_batch(runs)
+    b = Batch(runs, autotune.with_tile(P.make_params(), 0, tile, 1))
     b.init()
     b.capture()
     b.run(2)
@@ -321,8 +348,33 @@ def batched_bench(a):
                                      "k_batch_stage over the (run, brick) work list + flux pre-pass, whole RK4 steps"),
            "higher_is_better": True, "dtype": "f64", "data": "synthetic",
            "config": {"workload": "64 runs, n from {48,64,80,96} (numpy default_rng(2606)), mu U[0.3,0.8], "
-                                  "sigma U[0.8,1.6], L = 12/H0, CFL 0.25, hipGraph-replayed RK4 steps"}}
+                                  "sigma U[0.8,1.6], L = 12/H0, CFL 0.25, hipGraph-replayed RK4 steps",
+                      "brick": "x".join(map(str, tile))}}
+    if not a.no_cpu:
+        # the oracle's point-update rate on a 64^3 sample with the scan's box, as runs of the scan per second
+        cb = cpu_baseline_scan(16)
+        per_run = pts * total_steps / len(runs)
+        out["cpu_baseline"] = {"value": cb["value"] / per_run, "unit": "runs/s", "cores": cb["cores"], "kind": "oracle",
+                               "sample": cb["sample"] + f"; runs/s = point-updates/s / ({per_run:.4g} point-updates "
+                                                       "per average run of the scan)"}
     return out
+
+
+def cpu_baseline_scan(n_steps: int):
+    """The oracle on a bounded sample of the scan: RK4 steps of one 64^3 run of box 12 (the
+    scan's spacing at its middle size) at the middle of its mu, sigma ranges."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    s = oracle.Setup(n=(64, 64, 64), L=(12.0, 12.0, 12.0))
+    u = oracle.init_fields(s, oracle.Init(mu=0.55, sigma=1.2))
+    dt = 0.25 * s.h[0]
+    oracle.rk4(s, u, 0.0, dt, 1, parallel=True)  # warm-up
+    t0 = time.perf_counter()
+    oracle.rk4(s, u, 0.0, dt, n_steps, parallel=True)
+    el = time.perf_counter() - t0
+    return {"value": 64 ** 3 * n_steps / el, "cores": threads,
+            "sample": f"{n_steps} RK4 steps of the CPU oracle on one 64^3 run (L = 12, mu = 0.55, sigma = 1.2), "
+                      f"OpenMP over z-planes, {el:.1f} s"}
 
 
 def kt_bench(a, kv=0, tile=(16, 4, 4), order=2):
@@ -617,6 +669,9 @@ def main():
         return
     if a.copy_probe:
         copy_probe()
+        return
+    if a.triad_probe:
+        triad_probe()
         return
     if a.batched:
         print(json.dumps(batched_bench(a)), flush=True)

@@ -292,10 +292,12 @@ int cosmos_adjoint_gradient(const cosmos_grid* grid, const cosmos_params* params
                             const double* lam0, double* grad_dev, void* ws, void* stream);
 
 /* Batched form: many independent runs advanced together, one persistent launch per RK4 stage
- * for all of them (work items = (run, 16x4x4 brick)). Run r has a cubic periodic grid of n[r]^3
+ * for all of them (work items = (run, brick)). Run r has a cubic periodic grid of n[r]^3
  * points (n[r] divisible by 16) and box L[r]; its state (25 * n[r]^3 doubles, layout as above)
- * starts at arena + state_off[r] (state_off[r] a multiple of 32). All runs share the params
- * (tile fields are ignored). Host arrays, read during the call only. */
+ * starts at arena + state_off[r] (state_off[r] a multiple of 32). All runs share the params; their
+ * tile fields choose the brick (0 = 16x4x4; 16x8x2, 8x8x4, 8x4x8; the Kurganov-Tadmor scheme and
+ * the scalar field run 16x4x4 only; the order field is not used) and the results do not depend on
+ * it (bitwise). Host arrays, read during the call only. */
 typedef struct {
   int32_t nruns;
   const int32_t* n;
@@ -309,15 +311,16 @@ size_t cosmos_batch_workspace_bytes(const cosmos_batch* batch);
 
 /* Upload the per-run descriptor table and the interleaved (run, brick) work list into bws and
  * zero the per-run status counters. Synchronises `stream`. Call once per batch (not inside a
- * graph capture). */
+ * graph capture). Errors: COSMOS_EINVAL for an invalid batch or brick, COSMOS_EUNSUPPORTED for a
+ * brick other than 16x4x4 with fluid_scheme 1. */
 int cosmos_batch_setup(const cosmos_batch* batch, const cosmos_params* params, void* bws, void* stream);
 
 /* One classic RK4 step of every run: run r advances by dt_dev[r] from time t_dev[r]; t_dev is
  * advanced on the device (t_dev, dt_dev: device arrays of nruns doubles). Enqueues 4 stage
  * launches and one time update and nothing else, so it can be captured in a hipGraph and
- * replayed; the results equal those of cosmos_rk4_step on each run with a 16x4x4 brick. The
- * runs' parameters are those given to cosmos_batch_setup; params->fluid_scheme selects the
- * kernels and must be that same scheme. */
+ * replayed; the results equal those of cosmos_rk4_step on each run with the same brick. The
+ * runs' parameters are those given to cosmos_batch_setup; params->fluid_scheme and the tile
+ * fields select the kernels and must be the ones given there. */
 int cosmos_rk4_step_batched(const cosmos_batch* batch, const cosmos_params* params, double* arena,
                             double* t_dev, const double* dt_dev, void* bws, void* stream);
 

@@ -1,18 +1,21 @@
 """Tile autotuner for the stage kernel.
 
 Searches the kernel variant (LDS-staged bricks, or direct loads through the
-caches), the brick owned by one 256-thread workgroup (tile_x x tile_y x
-tile_z, x fastest) and the brick order (XCD slabs, linear, or XCD-blocked), times
-full RK4 steps of each candidate with HIP events on the launch stream, and
-keeps the fastest. A candidate is eligible only if its right-hand side is
-bitwise identical to its variant's default brick on the same state (the brick
-changes the schedule, never the arithmetic), and that variant agrees with the
-other one to round-off (max relative difference 1e-13 per field). Results are cached as JSON keyed by
-(gfx arch, grid, variant) in $COSMOS_TUNE_CACHE (default
-~/.cache/cosmos_tune.json).
+caches), the brick owned by one 256-thread workgroup
+(tile_x x tile_y x tile_z, x fastest) and the brick order (XCD slabs, linear, or
+XCD-blocked), times full RK4 steps of each candidate with HIP events on the launch
+stream, and keeps the fastest (tune_batch does the same for the batched form's brick). A candidate is eligible only if its right-hand side
+is bitwise identical to its variant's default brick on the same state (the brick
+changes the schedule, never the arithmetic), and every variant agrees with the
+LDS-staged one to round-off (max relative difference 1e-13 per field). Results are
+cached as JSON in $COSMOS_TUNE_CACHE (default ~/.cache/cosmos_tune.json), keyed by
+the gfx arch, the grid, a digest of the built library and a digest of the
+parameters other than the tile fields; a cached pick is checked for parity again
+before it is returned.
 """
 from __future__ import annotations
 
+import hashlib
 import json
 import os
 
@@ -22,37 +25,55 @@ from . import _lib as C
 
 LDS_BRICKS = [(16, 4, 4), (16, 8, 2), (8, 8, 4), (8, 4, 8)]
 DIRECT_TILES = [(256, 1, 1), (64, 4, 1), (32, 8, 1), (32, 4, 2), (16, 16, 1), (16, 4, 4), (8, 8, 4)]
-ORDERS = (0, 1, 2)  # XCD slabs, linear, XCD-blocked (the last only for the LDS-staged variant)
+ORDERS = (0, 1, 2)  # XCD slabs, linear, XCD-blocked (the last only for the LDS-staged variants)
 # (variant, tile, order): variant 0 = LDS-staged bricks, 1 = direct loads
 CANDIDATES = [(0, t, o) for t in LDS_BRICKS for o in ORDERS] + [(1, t, o) for t in DIRECT_TILES for o in ORDERS[:2]]
+DEFAULT_TILE = {0: (16, 4, 4), 1: (16, 4, 4)}
 
 
 def _cache_path() -> str:
     return os.environ.get("COSMOS_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "cosmos_tune.json"))
 
 
-def _key(grid: C.cosmos_grid, variant: str) -> str:
+_LIB_DIGEST = None
+
+
+def _lib_digest() -> str:
+    """Digest of the built library file: a pick timed on another build is not reused."""
+    global _LIB_DIGEST
+    if _LIB_DIGEST is None:
+        with open(C.LIB_PATH, "rb") as f:
+            _LIB_DIGEST = hashlib.sha256(f.read()).hexdigest()[:16]
+    return _LIB_DIGEST
+
+
+def _params_digest(params: C.cosmos_params) -> str:
+    p = with_tile(params, 0, (0, 0, 0), 0)
+    return hashlib.sha256(bytes(p)).hexdigest()[:12]
+
+
+def _key(grid: C.cosmos_grid, variant: str, params: C.cosmos_params) -> str:
     arch = torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
-    return f"{arch}:{grid.n[0]}x{grid.n[1]}x{grid.n[2]}:{variant}"
+    return f"{arch}:{grid.n[0]}x{grid.n[1]}x{grid.n[2]}:{variant}:lib {_lib_digest()}:params {_params_digest(params)}"
 
 
-def load(grid: C.cosmos_grid, variant: str = "rk4"):
+def load(grid: C.cosmos_grid, params: C.cosmos_params, variant: str = "rk4"):
     try:
         with open(_cache_path()) as f:
-            e = json.load(f).get(_key(grid, variant))
+            e = json.load(f).get(_key(grid, variant, params))
         return (e["variant"], tuple(e["tile"]), e["order"]) if e else None
     except (OSError, ValueError, KeyError):
         return None
 
 
-def _store(grid, variant, entry):
+def _store(grid, variant, params, entry):
     path = _cache_path()
     try:
         with open(path) as f:
             db = json.load(f)
     except (OSError, ValueError):
         db = {}
-    db[_key(grid, variant)] = entry
+    db[_key(grid, variant, params)] = entry
     os.makedirs(os.path.dirname(path), exist_ok=True)
     tmp = path + ".tmp"
     with open(tmp, "w") as f:
@@ -68,24 +89,33 @@ def with_tile(params: C.cosmos_params, variant, tile, order) -> C.cosmos_params:
     return p
 
 
+def _references(grid, params, u, ws):
+    """Right-hand side of u by each variant's default brick, and whether every variant agrees
+    with the LDS-staged one to round-off."""
+    refs = {}
+    for kv, tile in DEFAULT_TILE.items():
+        refs[kv] = torch.empty_like(u)
+        C.cosmos_rhs(grid, with_tile(params, kv, tile, 0), 0.0, u, refs[kv], ws)
+    sc = refs[0].abs().reshape(C.NFIELDS, -1).amax(dim=1).clamp_min(1e-3)
+    agree = all(bool((((refs[kv] - refs[0]).abs().reshape(C.NFIELDS, -1).amax(dim=1) / sc).max() < 1e-13).item())
+                for kv in refs)
+    return refs, agree
+
+
 def tune(grid: C.cosmos_grid, params: C.cosmos_params, u: torch.Tensor, dt: float, steps: int = 2,
          candidates=None, variant: str = "rk4", use_cache: bool = True, verbose: bool = False):
     """Returns ((kernel_variant, tile, order), table). `u` is a representative state (not modified)."""
-    if use_cache:
-        hit = load(grid, variant)
-        if hit is not None:
-            return hit, None
-    cands = candidates or CANDIDATES
     ws = torch.empty(C.cosmos_workspace_bytes(grid), dtype=torch.uint8, device=u.device)
-    refs = {}
-    for kv, tile in ((0, (16, 4, 4)), (1, (16, 4, 4))):
-        refs[kv] = torch.empty_like(u)
-        C.cosmos_rhs(grid, with_tile(params, kv, tile, 0), 0.0, u, refs[kv], ws)
-    d = (refs[0] - refs[1]).abs().reshape(C.NFIELDS, -1).amax(dim=1)
-    sc = refs[0].abs().reshape(C.NFIELDS, -1).amax(dim=1).clamp_min(1e-3)
-    variants_agree = bool(((d / sc).max() < 1e-13).item())
-    work = torch.empty_like(u)
+    refs, variants_agree = _references(grid, params, u, ws)
     out = torch.empty_like(u)
+    if use_cache:
+        hit = load(grid, params, variant)
+        if hit is not None:
+            C.cosmos_rhs(grid, with_tile(params, *hit), 0.0, u, out, ws)
+            if variants_agree and torch.equal(out, refs[hit[0]]):
+                return hit, None
+    cands = candidates or CANDIDATES
+    work = torch.empty_like(u)
     stream = torch.cuda.current_stream()
     table = []
     for kv, tile, order in cands:
@@ -107,7 +137,76 @@ def tune(grid: C.cosmos_grid, params: C.cosmos_params, u: torch.Tensor, dt: floa
         if verbose:
             print(f"variant {kv} tile {tile} order {order}: {ms:.3f} ms/step", flush=True)
     ok = [r for r in table if r["parity"]]
+    if not ok:
+        why = ("the kernel variants disagree beyond round-off on this state" if not variants_agree
+               else "no candidate reproduces its variant's default brick bitwise")
+        raise RuntimeError(f"autotune: no eligible candidate ({why})")
     best = min(ok, key=lambda r: r["ms_per_step"])
-    _store(grid, variant, {"variant": best["variant"], "tile": list(best["tile"]), "order": best["order"],
-                           "ms_per_step": best["ms_per_step"], "table": [dict(r, tile=list(r["tile"])) for r in table]})
+    _store(grid, variant, params, {"variant": best["variant"], "tile": list(best["tile"]), "order": best["order"],
+                                   "ms_per_step": best["ms_per_step"],
+                                   "table": [dict(r, tile=list(r["tile"])) for r in table]})
     return (best["variant"], tuple(best["tile"]), best["order"]), table
+
+BATCH_BRICKS = [(16, 4, 4), (16, 8, 2), (8, 8, 4), (8, 4, 8)]
+
+
+def tune_batch(runs, params: C.cosmos_params | None = None, steps: int = 2, use_cache: bool = True,
+               verbose: bool = False):
+    """Brick of the batched stage kernel for this batch of runs (a list of batch.RunSpec): every
+    candidate brick advances the batch one step from the same initial data, must equal the default
+    brick's result bitwise, and is timed over `steps` further steps (HIP events on the launch
+    stream); the fastest is kept. Cached like tune(), keyed by the runs' (n, L) list. Returns
+    ((tile_x, tile_y, tile_z), table)."""
+    from .batch import Batch
+    params = params if params is not None else C.make_params()
+    sizes = hashlib.sha256(repr([(r.n, r.L) for r in runs]).encode()).hexdigest()[:12]
+    arch = torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
+    key = f"{arch}:batch {sizes}:lib {_lib_digest()}:params {_params_digest(params)}"
+    if use_cache:
+        try:
+            with open(_cache_path()) as f:
+                e = json.load(f).get(key)
+            if e:
+                return tuple(e["tile"]), None
+        except (OSError, ValueError, KeyError):
+            pass
+    ref = None
+    table = []
+    stream = torch.cuda.current_stream()
+    for tile in BATCH_BRICKS:
+        b = Batch(runs, with_tile(params, 0, tile, 1))
+        b.init()
+        b.step()
+        if ref is None:
+            ref = b.arena.clone()
+        ok = torch.equal(b.arena, ref)
+        ms = None
+        if ok:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(steps):
+                b.step()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+        table.append({"tile": tile, "ms_per_step": ms, "parity": ok})
+        if verbose:
+            print(f"batched brick {tile}: {ms} ms/step parity {ok}", flush=True)
+        del b
+    good = [r for r in table if r["parity"]]
+    if not good:
+        raise RuntimeError("autotune: no batched brick reproduces the default brick bitwise")
+    best = min(good, key=lambda r: r["ms_per_step"])
+    path = _cache_path()
+    try:
+        with open(path) as f:
+            db = json.load(f)
+    except (OSError, ValueError):
+        db = {}
+    db[key] = {"tile": list(best["tile"]), "ms_per_step": best["ms_per_step"],
+               "table": [dict(r, tile=list(r["tile"])) for r in table]}
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path + ".tmp", "w") as f:
+        json.dump(db, f, indent=1, sort_keys=True)
+    os.replace(path + ".tmp", path)
+    return tuple(best["tile"]), table

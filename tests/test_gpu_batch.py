@@ -231,3 +231,27 @@ def test_batch_outcomes_on_device(P):
         c = spec.n // 2
         assert out[r]["alpha_centre"] == float(a[c, c, c])
         assert out[r]["alpha_min"] == float(a.min())
+
+
+def test_batched_bricks_bitwise_and_tuner(P):
+    """Every brick of the batched stage kernel advances the batch to the same bits (the brick
+    changes the schedule, not the arithmetic); the batch autotuner returns one of them with its
+    timing table, every candidate eligible."""
+    from paper_2606_02053_amd import autotune
+    from paper_2606_02053_amd.batch import Batch
+    runs = small_runs()
+    ref = None
+    for tile in autotune.BATCH_BRICKS:
+        b = Batch(runs, autotune.with_tile(P.make_params(), 0, tile, 1))
+        b.init()
+        b.step()
+        b.capture()
+        b.run(1)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = b.arena.clone()
+        assert torch.equal(b.arena, ref), tile
+    tile, table = autotune.tune_batch(runs, use_cache=False)
+    assert tile in autotune.BATCH_BRICKS and all(r["parity"] for r in table)
+    with pytest.raises(P.CosmosError):
+        Batch(runs, autotune.with_tile(P.make_params(fluid_scheme=1), 0, (8, 8, 4), 1)).init()
