@@ -79,7 +79,8 @@ def step_roofline(point_updates_per_s, bytes_per_point_step, kernels):
             "algorithmic_bytes_per_point_step": bytes_per_point_step}
 HERE = os.path.dirname(os.path.abspath(__file__))
 # sources that define the stage kernel; the committed counters apply only while they are unchanged
-STAGE_SOURCES = ["bssn_device.hpp", "bssn_lds.hpp", "cosmos.hip"]
+ORDER_NAMES = ("xcd", "linear", "blocked")
+STAGE_SOURCES = ["bssn_device.hpp", "bssn_lds.hpp", "stage.hip.inc"]
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "k_bssn_stage_lds_256cubed_traffic.txt")
 
 
@@ -113,11 +114,11 @@ def parse():
 def parse_config(text):
     kind, tile, order = text.split(":")
     kv = {"lds": 0, "direct": 1}[kind]
-    return kv, tuple(int(x) for x in tile.split("x")), {"xcd": 0, "linear": 1, "blocked": 2}[order]
+    return kv, tuple(int(x) for x in tile.split("x")), ORDER_NAMES.index(order)
 
 
 def config_name(kv, tile, order):
-    return f"{'lds' if kv == 0 else 'direct'}:{'x'.join(map(str, tile))}:{('xcd', 'linear', 'blocked')[order]}"
+    return f"{'lds' if kv == 0 else 'direct'}:{'x'.join(map(str, tile))}:{ORDER_NAMES[order]}"
 
 
 def stage_source_hash():
@@ -128,22 +129,28 @@ def stage_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(cfg, npts):
-    """HBM bytes per stage launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
-    counters (KiB per dispatch, averaged over the four RK4 stages), each scaled by
-    what the same counter reads for a plain device copy of known size. None when the
-    counters were taken on other kernel sources, another configuration or grid."""
+def measured_counters(cfg, npts):
+    """From the committed rocprofv3 counters of the stage kernel (TRAFFIC_FILE): HBM bytes per
+    stage launch (FETCH_SIZE / WRITE_SIZE in KiB per dispatch, averaged over the four RK4 stages,
+    each scaled by what the same counter reads for plain copy and triad kernels of known size)
+    and the FP64 operations executed per point and stage (SQ_INSTS_VALU_{FMA,ADD,MUL}_F64 x 64
+    lanes, an FMA counted as 2). (None, None) when the counters were taken on other kernel
+    sources, another configuration or grid."""
     try:
         with open(TRAFFIC_FILE) as f:
             kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith(("#", " ", "|")))
         kv = {k.strip(): v.strip() for k, v in kv.items()}
         if kv["source_hash"] != stage_source_hash() or kv["config"] != cfg or int(kv["points"]) != npts:
-            return None
+            return None, None
         fetch = float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_scale"])
         write = float(kv["write_kib_per_dispatch"]) * float(kv["write_scale"])
-        return round((fetch + write) * 1024.0)
+        return round((fetch + write) * 1024.0), float(kv["fp64_flop_per_point"])
     except (OSError, KeyError, ValueError):
-        return None
+        return None, None
+
+
+def measured_traffic(cfg, npts):
+    return measured_counters(cfg, npts)[0]
 
 
 def machine_probes():
@@ -616,7 +623,70 @@ def adjoint_bench(a):
            "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"96^3 periodic, L = 12/H0, Gaussian zeta mu = 0.55 sigma = 1.2, {cfg.nsteps} RK4 "
                                   "steps, CFL 0.25, checkpoint every 20, J = centre lapse at the final time"}}
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_adjoint()
     return out
+
+
+def c3b_bench(a, kv, tile, order):
+    """The headline workload on the 384^3 grid (same box L = 16/H0 and perturbation, h = 1/24):
+    whole RK4 steps timed with HIP events on the launch stream, in the headline's kernel
+    configuration."""
+    import paper_2606_02053_amd as P
+    from paper_2606_02053_amd import autotune
+    n, L, steps = 384, 16.0, max(1, min(a.steps, 10))
+    sol = P.Solver(n, L)
+    sol.init(mu=0.6, sigma=2.0)
+    dt = sol.default_dt()
+    sol.params = autotune.with_tile(sol.params, kv, tile, order)
+    for _ in range(max(1, a.warmup)):
+        sol.step(dt)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(steps):
+        sol.step(dt)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    if sol.status()["nonfinite"]:
+        raise RuntimeError("non-finite values in the 384^3 run")
+    value = n ** 3 * steps / (ms / 1e3)
+    out = {"metric": "grid-point RK4 updates/sec FP64 at 384^3", "value": value, "unit": "point-updates/s",
+           "ms_per_step": ms / steps, "timed_steps": steps, "higher_is_better": True, "dtype": "f64",
+           "data": "synthetic",
+           "roofline": step_roofline(value, BYTES_PER_POINT_STEP, "k_bssn_stage_lds + k_fluid_flux, whole RK4 steps"),
+           "config": {"workload": "BSSN + radiation fluid classic RK4, 384^3 periodic grid, L = 16/H0, Gaussian zeta "
+                                  "mu = 0.6 sigma = 2.0, CFL 0.25, KO eps 0.1",
+                      "kernel_config": config_name(kv, tile, order)}}
+    del sol
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline_adjoint():
+    """The oracle's discrete adjoint (taped reverse mode through one RK4 step) on a 12^3 grid with
+    the differentiated run's grid spacing and data, beside its forward step: the CPU cost ratio
+    (forward + adjoint) / forward, the unit of the adjoint leg."""
+    import numpy as np
+    import oracle
+    n = 12
+    s = oracle.Setup(n=(n, n, n), L=(1.5, 1.5, 1.5))  # h = 12/96, as in the 96^3 run
+    u = oracle.init_fields(s, oracle.Init(mu=0.55, sigma=1.2))
+    lam = np.random.default_rng(5).standard_normal(u.shape)
+    dt = 0.25 * s.h[0]
+    t0 = time.perf_counter()
+    for _ in range(20):
+        oracle.rk4(s, u.copy(), 0.0, dt, 1)
+    t_fwd = (time.perf_counter() - t0) / 20
+    t0 = time.perf_counter()
+    oracle.vjp(s, u, lam, "step", t=0.0, dt=dt)
+    t_adj = time.perf_counter() - t0
+    return {"value": (t_fwd + t_adj) / t_fwd, "unit": "x forward", "cores": 1, "kind": "oracle",
+            "sample": f"one RK4 step and its taped reverse-mode adjoint on a 12^3 grid (h = 1/8, mu = 0.55, "
+                      f"sigma = 1.2), serial: forward {t_fwd * 1e3:.1f} ms, adjoint {t_adj:.1f} s; "
+                      f"{n ** 3 / t_adj:.1f} adjoint point-steps/s"}
 
 
 def threshold_bench(a):
@@ -726,14 +796,19 @@ def main():
     bytes_launch = BYTES_PER_POINT_STEP / LAUNCHES_PER_STEP * npts
     achieved = bytes_launch / launch_s / 1e9
     fl = flops_per_point_step()
+    traffic, xfl = measured_counters(config_name(kv, tile, order), npts)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(config_name(kv, tile, order), npts),
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "traffic_unit": "bytes per launch", "algorithmic_bytes_per_launch": round(bytes_launch),
             "kernel": (f"k_bssn_stage_lds<{tile[0]},{tile[1]},{tile[2]}>" if kv == 0 else "k_bssn_stage") +
                       " + k_fluid_flux pre-pass (one RK4 stage)",
             "avg_launch_ms": round(launch_s * 1e3, 4),
             "fp64_tflops_algorithmic": round(fl * npts * a.steps / (ms / 1e3) / 1e12, 2),
             "fp64_frac": round(fl * npts * a.steps / (ms / 1e3) / 1e12 / FP64_PEAK_TFLOPS, 4)}
+    # what the stage kernel executes (counters), beside the oracle's operation count above
+    roof["fp64_flop_per_point_stage_executed"] = xfl
+    roof["fp64_tflops_executed"] = None if xfl is None else round(xfl * npts / launch_s / 1e12, 2)
+    roof["fp64_executed_frac"] = None if xfl is None else round(xfl * npts / launch_s / 1e12 / FP64_PEAK_TFLOPS, 4)
     ach = machine_probes()
     roof["achievable"] = ach
     roof["frac_of_achievable_hbm"] = round(achieved / ach["hbm_triad_gbs"], 4)
@@ -743,7 +818,7 @@ def main():
            "config": {"workload": f"BSSN + radiation fluid (P = rho/3) classic RK4, {n}^3 periodic grid, L = 16/H0, "
                                   f"Gaussian zeta mu = 0.6 sigma = 2.0, CFL 0.25, KO eps 0.1",
                       "grid": n, "dt": dt, "kernel_variant": "lds-staged" if kv == 0 else "direct",
-                      "tile": list(tile), "tile_order": ("xcd", "linear", "blocked")[order],
+                      "tile": list(tile), "tile_order": ORDER_NAMES[order],
                       "kernel_config": config_name(kv, tile, order),
                       "parallelism": "single GPU"},
            "roofline": roof}
@@ -754,6 +829,7 @@ def main():
         # the LDS-staged kernel takes the scalar sources with the 16x4x4 brick only
         out["scalar"] = scalar_bench(a, kv, (16, 4, 4) if kv == 0 else tile, order)
         out["c2"] = c2_bench(a)
+        out["c3b"] = c3b_bench(a, kv, tile, order)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(a.cpu_steps)
     print(json.dumps(out), flush=True)

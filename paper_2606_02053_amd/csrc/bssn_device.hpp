@@ -182,6 +182,15 @@ __device__ __forceinline__ double bld(const double* base, uint32_t nbytes, uint3
 __device__ __forceinline__ void bst(double* base, uint32_t nbytes, uint32_t off, double v) {
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), field_rsrc(base, nbytes), off, 0, 0);
 }
+// The same with the non-temporal hint (cache policy nt): for data used once per launch (the RK4
+// epilogue operands and results), so that it is the first to leave L2 and the halo lines that
+// neighbouring bricks share stay.
+__device__ __forceinline__ double bld_nt(const double* base, uint32_t nbytes, uint32_t off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(field_rsrc(base, nbytes), off, 0, 2));
+}
+__device__ __forceinline__ void bst_nt(double* base, uint32_t nbytes, uint32_t off, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), field_rsrc(base, nbytes), off, 0, 2);
+}
 
 // Base of field f of a field-major array. The field offset passes through an empty
 // asm statement so the compiler recomputes it (two scalar ops) at each use instead

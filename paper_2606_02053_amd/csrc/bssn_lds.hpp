@@ -114,6 +114,11 @@ constexpr int kStageOrder[NF] = {F_BET,    F_BET + 1, F_BET + 2, F_GT,     F_GT 
                                  F_GT + 4, F_GT + 5,  F_GAM,     F_GAM + 1, F_GAM + 2, F_CHI,   F_ALP,
                                  F_K,      F_AT,      F_AT + 1,  F_AT + 2, F_AT + 3, F_AT + 4, F_AT + 5,
                                  F_ET,     F_ST,      F_ST + 1,  F_ST + 2};
+// Phases whose field is differentiated twice (second and mixed derivatives: the shift, the
+// conformal metric, chi and the lapse); the others take first derivatives only.
+constexpr bool kSecondDerivs[NF] = {true,  true,  true,  true,  true,  true,  true,  true,  true,
+                                    false, false, false, true,  true,  false, false, false, false,
+                                    false, false, false, false, false, false, false};
 constexpr int kPrefetch = 2;  // fields in flight ahead of the one being processed
 
 // Fields whose right-hand side becomes final in each phase, in the order they are
@@ -205,7 +210,7 @@ struct DBrick {
   static constexpr int NR = (NPAIR + 255) / 256;     // load rounds per field
   static constexpr int NP = NR * 512;                // doubles per LDS buffer (padded to whole rounds)
   static constexpr int SY = HX, SZ = HX * HY;
-  static constexpr int NOFF = NR;
+  static constexpr int NOFF = 2 * NR;  // two offset sets: fields with and without second derivatives
   static_assert(BX * BY * BZ == 256 && BX % 2 == 0, "one point per thread, even brick width");
 };
 constexpr int kRing = 5;      // LDS halo buffers of the direct-load ring (25 phases = 5 rounds of the ring)
@@ -233,19 +238,41 @@ __device__ __forceinline__ void wait_vm(int n) {
 // round q of wave w filling pairs [256 q + 64 w, 256 q + 64 w + 64). No registers hold the data.
 template <class B>
 struct HaloDma {
-  uint32_t goffb[B::NR];
+  uint32_t goffb[B::NOFF];
   __device__ __forceinline__ void init(int i0, int j0, int k0, const int n[3]) { offsets(i0, j0, k0, n, goffb); }
-  static __device__ __forceinline__ void offsets(int i0, int j0, int k0, const int n[3], uint32_t goffb[B::NR]) {
+  // Box points that no stencil reads load a pair from a cache line the brick reads anyway, so
+  // that only the lines the stencils use are requested. Offsets [0, NR): fields with second
+  // derivatives -- x-halo reads come from rows within +-2 of the brick in y and z with the other
+  // coordinate inside (mixed xy and xz derivatives; +-3 axial ones in rows inside in both), the
+  // other rows are read only at the brick's x-range (y and z stencils, mixed yz ones within
+  // +-2 in both), and the box's corner rows not at all. Offsets [NR, 2 NR): fields with first
+  // derivatives only -- axial stencils: the x-halo in rows inside in y and z, the brick's
+  // x-range in rows inside in one of them, nothing elsewhere.
+  static __device__ __forceinline__ void offsets(int i0, int j0, int k0, const int n[3], uint32_t goffb[B::NOFF]) {
 #pragma unroll
     for (int q = 0; q < B::NR; ++q) {
       const int m = threadIdx.x + 256 * q;
       const int mm = m < B::NPAIR ? m : 0;  // padding lanes load an in-box pair into the padding
-      const int hx2 = mm % B::NPR, hy = (mm / B::NPR) % B::HY, hz = mm / (B::NPR * B::HY);
-      const int x = wrap_halo(i0 - 4 + 2 * hx2, n[0]), y = wrap_halo(j0 - 3 + hy, n[1]), z = wrap_halo(k0 - 3 + hz, n[2]);
-      goffb[q] = 8u * (uint32_t)(x + n[0] * (y + n[1] * z));
+      const int hx2 = mm % B::NPR, dy = (mm / B::NPR) % B::HY - 3, dz = mm / (B::NPR * B::HY) - 3;
+      const bool yin = dy >= 0 && dy < B::Y, zin = dz >= 0 && dz < B::Z;
+      const bool y2 = dy >= -2 && dy < B::Y + 2, z2 = dz >= -2 && dz < B::Z + 2;
+      const int hxi = min(max(hx2, 2), B::NPR - 3);  // the pair moved into the brick's x-range
+      const int x = wrap_halo(i0 - 4 + 2 * hx2, n[0]), xi = wrap_halo(i0 - 4 + 2 * hxi, n[0]);
+      const int y = wrap_halo(j0 + dy, n[1]), z = wrap_halo(k0 + dz, n[2]);
+      // a row that is read nowhere is replaced by the row with y moved inside the brick (read by
+      // the z stencils of both sets at the brick's x-range)
+      const int yc = wrap_halo(j0 + min(max(dy, 0), B::Y - 1), n[1]);
+      const bool xh2 = (y2 && zin) || (yin && z2), row2 = yin || zin || (y2 && z2);
+      goffb[q] = 8u * (uint32_t)((xh2 ? x : xi) + n[0] * ((row2 ? y : yc) + n[1] * z));
+      // first derivatives: rows inside in y or z are read, the others replaced as above
+      const bool xh1 = yin && zin, row1 = yin || zin;
+      goffb[B::NR + q] = 8u * (uint32_t)((xh1 ? x : xi) + n[0] * ((row1 ? y : yc) + n[1] * z));
     }
   }
-  __device__ __forceinline__ void fetch(const double* F, uint32_t nbytes, double* buf) const { fetch_at(F, nbytes, buf, goffb); }
+  // one field's halo box: SECOND selects the offset set of the fields with second derivatives
+  __device__ __forceinline__ void fetch(const double* F, uint32_t nbytes, double* buf, bool second = true) const {
+    fetch_at(F, nbytes, buf, second ? goffb : goffb + B::NR);
+  }
   static __device__ __forceinline__ void fetch_at(const double* F, uint32_t nbytes, double* buf,
                                                   const uint32_t off[B::NR]) {
     const __amdgpu_buffer_rsrc_t r = field_rsrc(F, nbytes);
@@ -412,7 +439,7 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
       epi_load(phase + kEpiAhead, std::integral_constant<int, kEpiAhead>());
       double* slot = buf0 + ((phase + kDmaAhead) % kRing) * B::NP;
       if (phase + kDmaAhead < NF)
-        hc.fetch(field_ptr(U, kStageOrder[phase + kDmaAhead], fs), nbytes, slot);
+        hc.fetch(field_ptr(U, kStageOrder[phase + kDmaAhead], fs), nbytes, slot, kSecondDerivs[phase + kDmaAhead]);
       else if (nx.valid)
         hc.fetch_at(field_ptr(nx.U, kStageOrder[phase + kDmaAhead - NF], nx.fs), (uint32_t)(nx.fs * 8), slot, nx.goffb);
     } else {

@@ -165,313 +165,9 @@ DevParams dev_params(const cosmos_grid* g, const cosmos_params* p) {
 }
 }  // namespace
 
-// ---------------------------------------------------------------- stage kernel
-// One kernel for every use of the right-hand side; MODE (a template parameter, so
-// the epilogue has no run-time branches) selects what is done with f(U):
-// 0: dudt = f(U)
-// 1: first RK4 stage   acc = U + ca k,  out = U + cn k          (U = u_n)
-// 2: middle stages     acc += ca k,     out = u_n + cn k
-// 3: last stage        out = acc + ca k (out = u_n's buffer), non-finite / collapse counts
-template <int MODE>
-struct StageSink {
-  const double* un;
-  double* acc;
-  double* out;
-  size_t fs;
-  int c;
-  double ca, cn, acol;
-  bool bad = false, coll = false;
-  // Epilogue operands of field f at this point (u_n and/or acc by mode), loaded
-  // ahead of the point's arithmetic so that their latency overlaps it.
-  struct Pre {
-    double u0, a0;
-  };
-  __device__ __forceinline__ Pre preload(int f) const { return preload_at(f, c); }
-  __device__ __forceinline__ Pre preload_at(int f, int cp) const { return preload_from(f, cp, un, acc, fs); }
-  // the same for point cp of another grid (arrays un_, acc_ with field size fs_)
-  __device__ __forceinline__ Pre preload_from(int f, int cp, const double* un_, const double* acc_,
-                                              size_t fs_) const {
-    const uint32_t nb = (uint32_t)(fs_ * 8), cb = (uint32_t)cp * 8u;
-    const size_t o = field_off(f, fs_);
-    Pre p{0.0, 0.0};
-    if constexpr (MODE == 1 || MODE == 2) p.u0 = bld(un_ + o, nb, cb);
-    if constexpr (MODE >= 2) p.a0 = bld(acc_ + o, nb, cb);
-    return p;
-  }
-  __device__ __forceinline__ void put(int f, double r, const Pre& p) {
-    const uint32_t nb = (uint32_t)(fs * 8), cb = (uint32_t)c * 8u;
-    const size_t o = field_off(f, fs);
-    if constexpr (MODE == 0) {
-      bst(out + o, nb, cb, r);
-    } else if constexpr (MODE == 1) {
-      bst(acc + o, nb, cb, p.u0 + ca * r);
-      bst(out + o, nb, cb, p.u0 + cn * r);
-    } else if constexpr (MODE == 2) {
-      bst(acc + o, nb, cb, p.a0 + ca * r);
-      bst(out + o, nb, cb, p.u0 + cn * r);
-    } else {
-      const double v = p.a0 + ca * r;
-      bst(out + o, nb, cb, v);
-      bad = bad || !isfinite(v);
-      if (f == F_ALP) coll = v < acol;
-    }
-  }
-  __device__ __forceinline__ void put(int f, double r) { put(f, r, preload(f)); }
-};
-
-// Pointwise pre-pass of every stage: the fluid fluxes of U at all points.
-__global__ __launch_bounds__(kBlock) void k_fluid_flux(const double* U, size_t fs, double w, double* F) {
-  const size_t c = (size_t)blockIdx.x * kBlock + threadIdx.x;
-  if (c >= fs) return;
-  fluid_flux_point(U, fs, (int)c, w, F);
-}
-
-template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_bssn_stage(const double* U, const double* F, const double* un, double* acc,
-                                                        double* out, size_t fs, DevParams P, Tile T, double t,
-                                                        double ca, double cn, unsigned long long* status) {
-  int i, j, k;
-  if (!tile_point(T, P.n, i, j, k)) return;
-  const int p = i + P.n[0] * (j + P.n[1] * k);
-  Nbr nb;
-  make_nbr(nb, i, j, k, P.n);
-  __shared__ double lds_rec[R_COUNT * kBlock];
-  const Rec rec{lds_rec + threadIdx.x, kBlock};
-  StageSink<MODE> sink{un, acc, out, fs, p, ca, cn, P.alpha_collapse};
-  bool fail = false;
-  bssn_rhs_stream(U, F, fs, nb, P, t, rec, sink, fail);
-  if (fail) atomicAdd(&status[1], 1ull);
-  if constexpr (MODE == 3) {
-    if (sink.bad) atomicAdd(&status[0], 1ull);
-    if (sink.coll) atomicAdd(&status[2], 1ull);
-    if (p == 0) atomicAdd(&status[3], 1ull);
-  }
-}
-
-// LDS-staged stage kernel: a persistent workgroup walks bricks v = blockIdx.x +
-// it * gridDim.x (gridDim.x a multiple of 8, so with the XCD-aware order every
-// brick of a workgroup lies in its XCD's slab), prefetching each next brick
-// during the last phases of the current one.
-// The halo boxes are staged by LDS-direct loads into a ring of kRing LDS buffers (DBrick,
-// kDmaAhead fields in flight; the grid's n0 must be even) -- the launcher sends grids with odd
-// n0 to the direct kernel.
-template <int BX, int BY, int BZ, int MODE, bool KT, bool SC = false>
-__global__ __launch_bounds__(kBlock) void k_bssn_stage_lds(const double* U, const double* F, const double* un,
-                                                            double* acc, double* out, size_t fs, DevParams P, Tile T,
-                                                            double t, double ca, double cn,
-                                                            unsigned long long* status) {
-  using B = DBrick<BX, BY, BZ>;
-  using Sink = StageSink<MODE>;
-  __shared__ double smem[kRing * B::NP];
-  // brick number `it` of this workgroup (all uniform): 1 = a brick (origin, and this
-  // thread's point, c = 0 outside the grid), 0 = none in this round, -1 = no more
-  auto locate = [&](int it, int& i0, int& j0, int& k0, int& c, bool& act) -> int {
-    int bxi, byi, bzi;
-    if (T.order == 2) {
-      if (it >= T.ngroups) return -1;
-      const int l = blockIdx.x >> 3, gxy = T.ngx * T.ngy;
-      bxi = (it % T.ngx) * T.gx + l % T.gx;
-      byi = ((it / T.ngx) % T.ngy) * T.gy + (l / T.gx) % T.gy;
-      const int bzl = (it / gxy) * T.gz + l / (T.gx * T.gy);
-      bzi = (blockIdx.x & 7) * T.zr + bzl;
-      if (bxi >= T.nbx || byi >= T.nby || bzl >= T.zr || bzi >= T.nbz) return 0;
-    } else {
-      const int v = blockIdx.x + it * gridDim.x;
-      int brick = v;
-      if (T.order == 0) {
-        if ((v >> 3) >= T.per) return -1;
-        brick = (v & 7) * T.per + (v >> 3);
-      }
-      if (brick >= T.nbricks) return -1;  // bricks increase with `it`: none after this one
-      bxi = brick % T.nbx;
-      byi = (brick / T.nbx) % T.nby;
-      bzi = brick / (T.nbx * T.nby);
-    }
-    i0 = bxi * BX, j0 = byi * BY, k0 = bzi * BZ;
-    const int i = i0 + threadIdx.x % BX, j = j0 + (threadIdx.x / BX) % BY, k = k0 + threadIdx.x / (BX * BY);
-    act = i < P.n[0] && j < P.n[1] && k < P.n[2];
-    c = act ? i + P.n[0] * (j + P.n[1] * k) : 0;
-    return 1;
-  };
-  // the first brick at or after round `it`; -1 when there is none
-  auto next_brick = [&](int it, int& i0, int& j0, int& k0, int& c, bool& act) -> int {
-    for (;; ++it) {
-      const int r = locate(it, i0, j0, k0, c, act);
-      if (r != 0) return r > 0 ? it : -1;
-    }
-  };
-  int i0, j0, k0, c;
-  bool active;
-  int it = next_brick(0, i0, j0, k0, c, active);
-  if (it < 0) return;  // uniform over the workgroup
-  LdsCarry<B, typename Sink::Pre> cy;
-  cy.hc.init(i0, j0, k0, P.n);
-  {
-    const Sink s0{un, acc, out, fs, c, ca, cn, P.alpha_collapse};
-    lds_carry_fill(cy, U, fs, s0, c, smem);
-  }
-  unsigned long long nfail = 0, nbad = 0, ncoll = 0, nstep = 0;
-  for (;;) {
-    NextBrick<B> nx;
-    int ni0, nj0, nk0;
-    bool nact = false;
-    const int nit = next_brick(it + 1, ni0, nj0, nk0, nx.c, nact);
-    nx.valid = nit >= 0;
-    nx.U = U, nx.un = un, nx.acc = acc, nx.fs = fs;
-    if (nx.valid) HaloDma<B>::offsets(ni0, nj0, nk0, P.n, nx.goffb);
-    Sink sink{un, acc, out, fs, c, ca, cn, P.alpha_collapse};
-    bool fail = false;
-    bssn_rhs_lds<B, KT, SC ? 1 : 0>(U, F, fs, P, t, c, active, cy, nx, smem, nullptr, sink, fail);
-    if (active) {
-      nfail += fail;
-      if constexpr (MODE == 3) {
-        nbad += sink.bad;
-        ncoll += sink.coll;
-        nstep += c == 0;
-      }
-    }
-    if (!nx.valid) break;
-    lds_barrier();  // the halo buffers are reused by the next brick
-    c = nx.c;
-    active = nact;
-    it = nit;
-  }
-  if (nfail) atomicAdd(&status[1], nfail);
-  if constexpr (MODE == 3) {
-    if (nbad) atomicAdd(&status[0], nbad);
-    if (ncoll) atomicAdd(&status[2], ncoll);
-    if (nstep) atomicAdd(&status[3], nstep);
-  }
-}
+#include "stage.hip.inc"
 
 namespace {
-// Workgroups of `kernel` resident on the whole device at once, rounded down to a
-// multiple of 8 (one slot per XCD per round), cached per device and kernel (per host
-// thread, so that concurrent callers share no mutable state).
-template <class K>
-unsigned resident_groups(K kernel) {
-  struct Entry {
-    const void* k;
-    int dev;
-    unsigned n;
-  };
-  static thread_local Entry cache[64];
-  static thread_local int used = 0;
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 8;
-  for (int e = 0; e < used; ++e)
-    if (cache[e].k == (const void*)kernel && cache[e].dev == dev) return cache[e].n;
-  int ncu = 0, per = 0;
-  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) ncu = 8;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kBlock, 0) != hipSuccess || per < 1) per = 1;
-  const unsigned n = std::max(8u, (unsigned)(ncu * per) / 8u * 8u);
-  if (used < 64) cache[used++] = Entry{(const void*)kernel, dev, n};
-  return n;
-}
-
-// Block of bricks processed together by the W resident workgroups of one XCD in the
-// XCD-blocked order: gx gy gz = W bricks that tile the XCD's slab of the brick grid
-// exactly (every XCD holds nbz / 8 brick layers and the blocks divide the slab), with
-// the smallest halo-to-interior ratio. False when there is no such block: an uneven
-// split would leave some XCDs idle or with half-filled blocks while others work, and
-// the launch then takes the linear order.
-bool blocked_order(Tile& T, unsigned W) {
-  if (T.nbz % 8) return false;
-  T.zr = T.nbz / 8;
-  double best = 1e300;
-  for (int gx = 1; gx <= (int)W; ++gx) {
-    if (W % gx || T.nbx % gx) continue;
-    for (int gy = 1; gy <= (int)W / gx; ++gy) {
-      if ((W / gx) % gy || T.nby % gy) continue;
-      const int gz = (int)W / (gx * gy);
-      if (T.zr % gz) continue;
-      const double ex = gx * T.bx + 6.0, ey = gy * T.by + 6.0, ez = gz * T.bz + 6.0;
-      const double ratio = ex * ey * ez / (double(W) * kBlock);
-      if (ratio < best) best = ratio, T.gx = gx, T.gy = gy, T.gz = gz;
-    }
-  }
-  if (!(best < 1e300)) return false;
-  T.ngx = T.nbx / T.gx;
-  T.ngy = T.nby / T.gy;
-  T.ngroups = T.ngx * T.ngy * (T.zr / T.gz);
-  return true;
-}
-
-template <class K>
-void launch_persistent(K kernel, const Tile& T0, hipStream_t s, const double* U, const double* F, const double* un,
-                       double* acc, double* out, size_t fs, const DevParams& P, double t, double ca, double cn,
-                       unsigned long long* status) {
-  Tile T = T0;
-  const unsigned G = resident_groups(kernel);
-  unsigned grid = std::min(tile_blocks(T), G);
-  if (T.order == 2) {
-    // needs every XCD busy with whole blocks; other grids fall back to the linear order
-    if (T.nbricks >= (int)G && blocked_order(T, G / 8)) grid = G;
-    else T.order = 1;
-  }
-  hipLaunchKernelGGL(kernel, dim3(grid), dim3(kBlock), 0, s, U, F, un, acc, out, fs, P, T, t, ca, cn, status);
-}
-
-// KT: the LDS-staged kernel is instantiated per fluid scheme, so the centred
-// scheme's code carries no trace of the other; the direct kernel tests it at run time.
-template <int M, bool KT>
-void launch_lds(const Tile& T, hipStream_t s, const double* U, const double* F, const double* un, double* acc,
-                double* out, size_t fs, const DevParams& P, double t, double ca, double cn,
-                unsigned long long* status) {
-  if (P.xsrc) {  // with the scalar field's sources: the 16x4x4 brick only (checked by launch_stage)
-    launch_persistent(k_bssn_stage_lds<16, 4, 4, M, KT, true>, T, s, U, F, un, acc, out, fs, P, t, ca, cn, status);
-  } else if (T.bx == 16 && T.by == 4) {
-    launch_persistent(k_bssn_stage_lds<16, 4, 4, M, KT>, T, s, U, F, un, acc, out, fs, P, t, ca, cn, status);
-  } else if (T.bx == 16) {
-    launch_persistent(k_bssn_stage_lds<16, 8, 2, M, KT>, T, s, U, F, un, acc, out, fs, P, t, ca, cn, status);
-  } else if (T.by == 8) {
-    launch_persistent(k_bssn_stage_lds<8, 8, 4, M, KT>, T, s, U, F, un, acc, out, fs, P, t, ca, cn, status);
-  } else {
-    launch_persistent(k_bssn_stage_lds<8, 4, 8, M, KT>, T, s, U, F, un, acc, out, fs, P, t, ca, cn, status);
-  }
-}
-
-template <int M>
-void launch_mode(bool lds, const Tile& T, hipStream_t s, const double* U, const double* F, const double* un,
-                 double* acc, double* out, size_t fs, const DevParams& P, double t, double ca, double cn,
-                 unsigned long long* status) {
-  if (!lds || P.n[0] % 2 || ((uintptr_t)U & 15)) {  // the LDS-staged kernel: n0 even, U 16-byte aligned
-    const dim3 g(tile_blocks(T)), b(kBlock);
-    hipLaunchKernelGGL(k_bssn_stage<M>, g, b, 0, s, U, F, un, acc, out, fs, P, T, t, ca, cn, status);
-  } else if (P.fluid_scheme == 1) {
-    launch_lds<M, true>(T, s, U, F, un, acc, out, fs, P, t, ca, cn, status);
-  } else {
-    launch_lds<M, false>(T, s, U, F, un, acc, out, fs, P, t, ca, cn, status);
-  }
-}
-
-// Launch one stage: the flux pre-pass into F (kFluxFields x fs doubles: the point
-// fluxes, or with the Kurganov-Tadmor scheme the flux divergence in the first 4
-// arrays), then the stage kernel with the variant and brick chosen in the params.
-int launch_stage(const cosmos_params* p, const Tile& T, hipStream_t s, const double* U, double* F, const double* un,
-                 double* acc, double* out, size_t fs, const DevParams& P, double t, double ca, double cn, int mode,
-                 unsigned long long* status) {
-  const bool lds = p->variant == 0;
-  if (lds && !((T.bx == 16 && T.by == 4 && T.bz == 4) || (T.bx == 16 && T.by == 8 && T.bz == 2) ||
-               (T.bx == 8 && T.by == 8 && T.bz == 4) || (T.bx == 8 && T.by == 4 && T.bz == 8)))
-    return set_error(COSMOS_EINVAL, "LDS-staged variant has no %dx%dx%d brick (16x4x4, 16x8x2, 8x8x4, 8x4x8)", T.bx,
-                     T.by, T.bz);
-  if (lds && P.xsrc && !(T.bx == 16 && T.by == 4 && T.bz == 4))
-    return set_error(COSMOS_EUNSUPPORTED, "with the scalar field the LDS-staged variant runs the 16x4x4 brick only");
-  if (P.fluid_scheme == 1) {
-    hipLaunchKernelGGL(k_fluid_kt, dim3(kt_bricks(P)), dim3(kKtThreads), 0, s, U, fs, P, F);
-  } else {
-    hipLaunchKernelGGL(k_fluid_flux, dim3((unsigned)((fs + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, U, fs, P.w,
-                       F);
-  }
-  switch (mode) {
-    case 0: launch_mode<0>(lds, T, s, U, F, un, acc, out, fs, P, t, ca, cn, status); break;
-    case 1: launch_mode<1>(lds, T, s, U, F, un, acc, out, fs, P, t, ca, cn, status); break;
-    case 2: launch_mode<2>(lds, T, s, U, F, un, acc, out, fs, P, t, ca, cn, status); break;
-    default: launch_mode<3>(lds, T, s, U, F, un, acc, out, fs, P, t, ca, cn, status); break;
-  }
-  return COSMOS_OK;
-}
 // One RK4 step in place on u; the stage states go to U2, U3, U4 (U4 may be U2: it is
 // written after U2 has been read for the last time).
 int rk4_step(const cosmos_grid* grid, const cosmos_params* params, double t, double dt, double* u, double* U2,

@@ -28,12 +28,14 @@ def test_source_hash_gates_the_committed_counters(tmp_path, monkeypatch):
     import bench
     assert bench.stage_source_hash() == h
     body = ("source_hash: {h}\nconfig: lds:16x4x4:blocked\npoints: 4096\nfetch_kib_per_dispatch: 100\n"
-            "write_kib_per_dispatch: 50\nfetch_scale: 2.0\nwrite_scale: 1.0\n")
+            "write_kib_per_dispatch: 50\nfetch_scale: 2.0\nwrite_scale: 1.0\nfp64_flop_per_point: 4789\n")
     f = tmp_path / "traffic.txt"
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
     f.write_text(body.format(h=h))
     assert bench.measured_traffic("lds:16x4x4:blocked", 4096) == (100 * 2.0 + 50) * 1024
+    assert bench.measured_counters("lds:16x4x4:blocked", 4096) == ((100 * 2.0 + 50) * 1024, 4789.0)
     assert bench.measured_traffic("lds:16x4x4:blocked", 8192) is None  # another grid
     assert bench.measured_traffic("lds:16x8x2:blocked", 4096) is None  # another configuration
     f.write_text(body.format(h="0" * 16))
     assert bench.measured_traffic("lds:16x4x4:blocked", 4096) is None  # counters of other sources
+    assert bench.measured_counters("lds:16x4x4:blocked", 4096) == (None, None)
