@@ -32,6 +32,8 @@ Extra modes:
   --c2           only the 128^3 evolution (box 12/H0, mu = 0.5, sigma = 1.5, 500 RK4 steps) with
                  the constraint norms every 10 steps, timed with and without the norms, and the
                  HBM roofline of one constraint evaluation
+  --fmr          only the three-layer refined run (128^3 layer 0, two nested children at h/2 and
+                 h/4 over central 64^3 cell boxes), against the same RK4 steps without refinement
   --triad-probe  only the STREAM triad probe (16 B read, 8 B written per element; a second
                  calibration point for the counters)
   --copy-probe   only a plain device-to-device copy of known size (calibrates
@@ -103,6 +105,7 @@ def parse():
     ap.add_argument("--kt", action="store_true", help="only the Kurganov-Tadmor fluid-scheme leg")
     ap.add_argument("--scalar", action="store_true", help="only the massless-scalar-field leg")
     ap.add_argument("--c2", action="store_true", help="only the 128^3 run with constraint norms every 10 steps")
+    ap.add_argument("--fmr", action="store_true", help="only the three-layer refined run")
     ap.add_argument("--adjoint-steps", type=int, default=200, help="RK4 steps of the differentiated run")
     ap.add_argument("--no-fd", action="store_true", help="skip the finite-difference check of the adjoint")
     ap.add_argument("--config", default=None,
@@ -665,6 +668,84 @@ def c3b_bench(a, kv, tile, order):
     return out
 
 
+def fmr_bench(a):
+    """Three refinement layers on the headline data (zeta Gaussian mu 0.6, sigma 2.0, box 16/H0):
+    layer 0 a 128^3 periodic grid, layer 1 over its central 64^3 cells (h/2), layer 2 over the
+    central 64^3 cells of layer 1 (h/4); Berger-Oliger sub-cycling (1, 2, 4 steps per layer-0
+    step). Timed with HIP events on the launch stream; beside it the same RK4 steps of the three
+    padded grids run alone, whose difference is the cost of the refinement (interpolation,
+    injection, the parents' right-hand sides for the time interpolant)."""
+    import paper_2606_02053_amd as P
+    n, L = 128, 16.0
+    boxes = [((32, 32, 32), (64, 64, 64)), ((44, 44, 44), (64, 64, 64))]
+    steps = max(1, min(a.steps, 5))
+    run = P.RefinedRun((n, n, n), (L, L, L), boxes)
+    run.init(mu=0.6, sigma=2.0)
+    dt = run.default_dt()
+    run.step(dt)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(steps):
+        run.step(dt)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    st = run.status(0)
+    if st["nonfinite"]:
+        raise RuntimeError(f"non-finite values in the refined run: {st}")
+    # the same RK4 steps of the three padded grids alone
+    ev0.record(stream)
+    for _ in range(steps):
+        for k, reps in ((0, 1), (1, 2), (2, 4)):
+            for _ in range(reps):
+                P.cosmos_rk4_step(run.grids[k], run.params, 0.0, dt / reps, run.u0[k] if k < 2 else run.u[k],
+                                  run.ws[k])
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_plain = ev0.elapsed_time(ev1) / steps
+    interior = n ** 3 + 2 * 128 ** 3 + 4 * 128 ** 3
+    padded = n ** 3 + 2 * 152 ** 3 + 4 * 152 ** 3
+    value = interior / (ms / 1e3)
+    out = {"metric": "refined-run point-updates/sec (interior points of all layers)", "value": value,
+           "unit": "point-updates/s", "higher_is_better": True, "ms_per_layer0_step": ms,
+           "ms_plain_rk4_steps": ms_plain, "refinement_overhead_frac": (ms - ms_plain) / ms,
+           "uniform_equivalent_point_updates_per_s": (4 * n) ** 3 * 4 / (ms / 1e3),
+           "timed_steps": steps, "dtype": "f64", "data": "synthetic",
+           "roofline": step_roofline(padded / (ms / 1e3), BYTES_PER_POINT_STEP,
+                                     "k_bssn_stage_lds + k_fluid_flux on the padded layers, k_fmr_pass_*, "
+                                     "k_fmr_restrict, right-hand sides of layers 0 and 1"),
+           "config": {"workload": "3 layers: 128^3 periodic, L = 16/H0, Gaussian zeta mu = 0.6 sigma = 2.0; layer 1 "
+                                  "= central 64^3 cells at h/2 (152^3 padded), layer 2 = central 64^3 cells of layer 1 "
+                                  "at h/4 (152^3 padded); buffer 12; CFL 0.25 on every layer"}}
+    del run
+    torch.cuda.empty_cache()
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_fmr()
+    return out
+
+
+def cpu_baseline_fmr():
+    """The oracle's refined run (oracle/fmr.py) on a bounded sample: a 24^3 periodic grid with one
+    child over its central 16^3 cells (56^3 padded), two layer-0 steps, OpenMP inside each step."""
+    import oracle
+    from oracle import fmr
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    s = oracle.Setup(n=(24, 24, 24), L=(3.0, 3.0, 3.0))  # h = 1/8 as layer 0 of the GPU run
+    H = fmr.Hierarchy(s, [fmr.Box((4, 4, 4), (16, 16, 16))])
+    st = H.init(oracle.init_fields(s, oracle.Init(mu=0.6, sigma=2.0)))
+    dt = 0.25 * s.h[0]
+    t0 = time.perf_counter()
+    for m in range(2):
+        H.step(st, m * dt, dt)
+    sec = time.perf_counter() - t0
+    interior = 2 * (24 ** 3 + 2 * 32 ** 3)
+    return {"value": interior / sec, "unit": "point-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"2 layer-0 steps of a 24^3 grid with one child over its central 16^3 cells (56^3 padded), "
+                      f"{sec:.1f} s; interior points of both layers"}
+
+
 def cpu_baseline_adjoint():
     """The oracle's discrete adjoint (taped reverse mode through one RK4 step) on a 12^3 grid with
     the differentiated run's grid spacing and data, beside its forward step: the CPU cost ratio
@@ -755,6 +836,9 @@ def main():
     if a.c2:
         print(json.dumps(c2_bench(a)), flush=True)
         return
+    if a.fmr:
+        print(json.dumps(fmr_bench(a)), flush=True)
+        return
     if a.kt:
         kv, tile, order = parse_config(a.config) if a.config else (0, (16, 4, 4), 2)
         print(json.dumps(kt_bench(a, kv, tile, order)), flush=True)
@@ -830,6 +914,7 @@ def main():
         out["scalar"] = scalar_bench(a, kv, (16, 4, 4) if kv == 0 else tile, order)
         out["c2"] = c2_bench(a)
         out["c3b"] = c3b_bench(a, kv, tile, order)
+        out["fmr"] = fmr_bench(a)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(a.cpu_steps)
     print(json.dumps(out), flush=True)

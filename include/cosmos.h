@@ -346,6 +346,60 @@ int cosmos_batch_outcomes(const cosmos_batch* batch, const double* arena, void* 
 /* Synchronise and copy the per-run counters to host out[nruns][4] (as cosmos_status). */
 int cosmos_batch_status(const cosmos_batch* batch, void* bws, void* stream, int64_t* out);
 
+/* ---------------------------------------------------------------- fixed mesh refinement
+ * Nested refinement layers ("Statement of need": the code resolves collapse with fixed mesh
+ * refinement; the adiabatic-fluctuation example shows the lowest, 1st and 2nd layers). The paper
+ * leaves the scheme to its references; this library's is Berger-Oliger sub-cycling with buffer
+ * zones:
+ *   - a layer ("child") refines a box of its parent ("parent": the periodic grid, or a child
+ *     itself) by 2 per axis, vertex-aligned: the child's interior point i (per axis,
+ *     0 <= i < 2 m) lies at parent index origin + i / 2;
+ *   - the child's state is a 25-field SoA array on its padded grid (cosmos_fmr_child_grid:
+ *     n = 2 m + 2 COSMOS_FMR_BUFFER per axis, spacing half the parent's) and is advanced with
+ *     cosmos_rk4_step on that grid as if periodic: what the wrap-around spoils reaches at most 3
+ *     points further inwards per RK4 stage, so the outer COSMOS_FMR_BUFFER layers go stale within
+ *     a step and the interior stays exact;
+ *   - per parent step dt the child takes two steps dt/2; before each, cosmos_fmr_prolong refills
+ *     the buffer from the parent (6-point Lagrange in space, cubic Hermite in time over the
+ *     parent step), and after both cosmos_fmr_restrict copies the child's interior onto the
+ *     parent points it covers.
+ * The driver (paper_2606_02053_amd/fmr.py) sequences these calls; every value is computed here. */
+#define COSMOS_FMR_BUFFER 12
+
+typedef struct cosmos_box {
+  int32_t origin[3]; /* parent array index (x, y, z) of the child's interior point 0; any integer:
+                        indices wrap periodically on the parent */
+  int32_t m[3];      /* parent cells covered per axis (>= 4); the child interior has 2 m points */
+} cosmos_box;
+
+/* The child's padded grid: n[a] = 2 m[a] + 2 COSMOS_FMR_BUFFER, L[a] = n[a] * h_parent[a] / 2.
+ * Errors: COSMOS_EINVAL for an invalid parent grid or box, or a child beyond the grid limits. */
+int cosmos_fmr_child_grid(const cosmos_grid* parent, const cosmos_box* box, cosmos_grid* child);
+
+/* Device bytes of the workspace cosmos_fmr_prolong needs for this parent and box (its two
+ * partially interpolated intermediates); 0 for invalid arguments. */
+size_t cosmos_fmr_workspace_bytes(const cosmos_grid* parent, const cosmos_box* box);
+
+/* Child values interpolated from the parent. The parent's values in time: theta == 0 takes u0
+ * (f0, u1, f1 may be NULL); 0 < theta <= 1 takes the cubic Hermite interpolant at t0 + theta dt
+ * of the parent's trajectory with values u0, u1 and right-hand sides f0, f1 (cosmos_rhs) at t0 and
+ * t0 + dt. In space, per axis: a child point that coincides with a parent point copies it, a
+ * midpoint takes (3, -25, 150, 150, -25, 3)/256 of the 6 parent points around it (exact for
+ * quintics), applied along x, then y, then z. buffer_only != 0 writes only the child points within
+ * COSMOS_FMR_BUFFER of a face; 0 writes the whole padded child (initial data). Parent arrays:
+ * device, 25 x N3(parent) doubles; child_u: device, 25 x N3(child) doubles, not overlapping them;
+ * ws: cosmos_fmr_workspace_bytes, 256-byte aligned. Asynchronous on `stream`. Errors: COSMOS_EINVAL
+ * (invalid grid/box/pointers, theta outside [0, 1], theta > 0 without u1/f0/f1 or with dt <= 0). */
+int cosmos_fmr_prolong(const cosmos_grid* parent, const cosmos_box* box, const double* u0, const double* f0,
+                       const double* u1, const double* f1, double dt, double theta, int32_t buffer_only,
+                       double* child_u, void* ws, void* stream);
+
+/* Injection: parent points origin + j (0 <= j < m per axis, wrapped) take the child's values at
+ * its interior points 2 j (padded index COSMOS_FMR_BUFFER + 2 j). child_u and parent_u: device,
+ * 25-field SoA on their grids, not overlapping. Asynchronous. Errors: COSMOS_EINVAL. */
+int cosmos_fmr_restrict(const cosmos_grid* parent, const cosmos_box* box, const double* child_u, double* parent_u,
+                        void* stream);
+
 /* Human-readable reason for the last error on this thread ("" if none). */
 const char* cosmos_last_error(void);
 

@@ -17,3 +17,4 @@ for _name in dir(_lib):
         globals()[_name] = getattr(_lib, _name)
 del _name
 from .solver import Solver  # noqa: F401
+from .fmr import RefinedRun  # noqa: F401

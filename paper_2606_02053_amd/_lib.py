@@ -48,6 +48,13 @@ class cosmos_batch(ctypes.Structure):
                 ("L", ctypes.POINTER(ctypes.c_double)), ("state_off", ctypes.POINTER(ctypes.c_int64))]
 
 
+class cosmos_box(ctypes.Structure):
+    _fields_ = [("origin", ctypes.c_int32 * 3), ("m", ctypes.c_int32 * 3)]
+
+
+COSMOS_FMR_BUFFER = 12
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built: run __graft_entry__.build() (or python "
@@ -85,6 +92,10 @@ def _load():
         "cosmos_rhs_scalar": ([G, Pr, f64, P, P, P, P, P, P, P], i32),
         "cosmos_rk4_step_scalar": ([G, Pr, f64, f64, P, P, P, P, P], i32),
         "cosmos_constraints_scalar": ([G, Pr, P, P, P, P, P, P, P, P], i32),
+        "cosmos_fmr_child_grid": ([G, ctypes.POINTER(cosmos_box), G], i32),
+        "cosmos_fmr_workspace_bytes": ([G, ctypes.POINTER(cosmos_box)], sz),
+        "cosmos_fmr_prolong": ([G, ctypes.POINTER(cosmos_box), P, P, P, P, f64, f64, ctypes.c_int32, P, P, P], i32),
+        "cosmos_fmr_restrict": ([G, ctypes.POINTER(cosmos_box), P, P, P], i32),
         "cosmos_last_error": ([], ctypes.c_char_p),
         "cosmos_abi_version": ([], i32),
     }
@@ -360,3 +371,39 @@ def cosmos_batch_status(batch, bws, stream=None):
     _check(lib.cosmos_batch_status(ctypes.byref(batch), _dev(bws, "bws", dtype=torch.uint8), _stream(stream), out))
     return [{"nonfinite": out[4 * r], "prim_fail": out[4 * r + 1], "collapsed": out[4 * r + 2],
              "steps": out[4 * r + 3]} for r in range(batch.nruns)]
+
+
+# ---------------------------------------------------------------- fixed mesh refinement
+def make_box(origin, m) -> cosmos_box:
+    b = cosmos_box()
+    b.origin[:] = [int(x) for x in origin]
+    b.m[:] = [int(x) for x in m]
+    return b
+
+
+def cosmos_fmr_child_grid(parent: cosmos_grid, box: cosmos_box) -> cosmos_grid:
+    child = cosmos_grid()
+    _check(lib.cosmos_fmr_child_grid(ctypes.byref(parent), ctypes.byref(box), ctypes.byref(child)))
+    return child
+
+
+def cosmos_fmr_workspace_bytes(parent: cosmos_grid, box: cosmos_box) -> int:
+    return int(lib.cosmos_fmr_workspace_bytes(ctypes.byref(parent), ctypes.byref(box)))
+
+
+def cosmos_fmr_prolong(parent, box, u0, f0, u1, f1, dt: float, theta: float, buffer_only: bool, child_u, ws,
+                       stream=None):
+    Np = NFIELDS * npts(parent)
+    child = cosmos_fmr_child_grid(parent, box)
+    _check(lib.cosmos_fmr_prolong(ctypes.byref(parent), ctypes.byref(box), _dev(u0, "u0", Np), _dev(f0, "f0", Np),
+                                  _dev(u1, "u1", Np), _dev(f1, "f1", Np), float(dt), float(theta),
+                                  int(bool(buffer_only)), _dev(child_u, "child_u", NFIELDS * npts(child)),
+                                  _dev(ws, "ws", cosmos_fmr_workspace_bytes(parent, box), dtype=torch.uint8),
+                                  _stream(stream)))
+
+
+def cosmos_fmr_restrict(parent, box, child_u, parent_u, stream=None):
+    child = cosmos_fmr_child_grid(parent, box)
+    _check(lib.cosmos_fmr_restrict(ctypes.byref(parent), ctypes.byref(box),
+                                   _dev(child_u, "child_u", NFIELDS * npts(child)),
+                                   _dev(parent_u, "parent_u", NFIELDS * npts(parent)), _stream(stream)))

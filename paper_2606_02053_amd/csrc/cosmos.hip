@@ -358,6 +358,7 @@ int cosmos_constraints(const cosmos_grid* grid, const cosmos_params* params, con
 #include "batch.hip.inc"
 #include "adjoint.hip.inc"
 #include "scalar.hip.inc"
+#include "fmr.hip.inc"
 
 // ---------------------------------------------------------------- allocation-free constraint norms
 // For callers that cannot allocate (code under graph capture, tight monitoring loops): the

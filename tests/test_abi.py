@@ -162,3 +162,29 @@ def test_probe_library_exports_and_rejects_bad_arguments():
     assert lib.cosmos_probe_fma64(fake, 256, 0, None) == -1
     assert lib.cosmos_probe_fma64(None, 256, 10, None) == -1
     assert lib.cosmos_probe_fma64_flops(512, 100) == 2.0 * 16 * 100 * 512
+
+
+def test_fmr_geometry_on_host(C):
+    """The refinement entry points' host-side geometry: the padded child grid, the workspace size
+    and the argument checks that run before any launch."""
+    g = C.make_grid((24, 20, 16), (6.0, 5.0, 4.0))
+    b = C.make_box((3, -2, 5), (8, 6, 5))
+    child = C.cosmos_fmr_child_grid(g, b)
+    assert tuple(child.n) == (2 * 8 + 24, 2 * 6 + 24, 2 * 5 + 24)
+    assert [child.L[a] for a in range(3)] == pytest.approx([child.n[a] * 0.25 / 2 for a in range(3)])
+    ws = C.cosmos_fmr_workspace_bytes(g, b)
+    # two intermediates: x interpolated (40 x 23 x 22), then y (40 x 36 x 22), 25 fields each,
+    # each rounded up to 256 bytes
+    up = lambda x: (x + 255) // 256 * 256  # noqa: E731
+    assert ws == up(25 * 8 * (40 * 23 * 22)) + up(25 * 8 * (40 * 36 * 22))
+    assert C.cosmos_fmr_workspace_bytes(g, C.make_box((0, 0, 0), (3, 6, 6))) == 0
+    lib = C.lib
+    fake = ctypes.c_void_p(0x100000)
+    rc = lib.cosmos_fmr_prolong(ctypes.byref(g), ctypes.byref(b), fake, None, None, None, 0.1, 0.5, 1, fake, fake,
+                                None)
+    assert rc == C.COSMOS_EINVAL and "f0" in C.last_error()
+    rc = lib.cosmos_fmr_prolong(ctypes.byref(g), ctypes.byref(b), fake, fake, fake, fake, 0.1, -0.5, 1, fake, fake,
+                                None)
+    assert rc == C.COSMOS_EINVAL and "theta" in C.last_error()
+    rc = lib.cosmos_fmr_restrict(ctypes.byref(g), ctypes.byref(b), None, fake, None)
+    assert rc == C.COSMOS_EINVAL and "child_u" in C.last_error()

@@ -1,0 +1,112 @@
+"""Fixed mesh refinement on the GPU against the oracle (oracle/fmr.py): the prolongation entry point
+(whole child and buffer only, parent values at the step start and the Hermite midpoint, a box
+that wraps around the periodic parent), the injection, and a three-layer refined run (layer 0
+periodic, two nested children, Berger-Oliger sub-cycling) layer by layer after several steps."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import fmr
+from tests.inputs import fuzz_direction, fuzz_state
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2606_02053_amd as P
+    return P
+
+
+def rel(a, b, floor=1e-6):
+    """Largest per-field max-norm difference relative to the field's max-norm (floored)."""
+    a = np.asarray(a).reshape(25, -1)
+    b = np.asarray(b).reshape(25, -1)
+    return (np.abs(a - b).max(axis=1) / np.maximum(np.abs(b).max(axis=1), floor)).max()
+
+
+@pytest.mark.parametrize("theta", [0.0, 0.5])
+@pytest.mark.parametrize("buffer_only", [False, True])
+def test_prolong_matches_oracle(P, theta, buffer_only):
+    n, L = (20, 16, 24), (5.0, 4.0, 6.0)
+    box = fmr.Box(origin=(15, -3, 5), m=(6, 5, 8))  # wraps in x and y
+    u0 = fuzz_state(n, seed=71)
+    f0 = fuzz_direction(n, seed=72)
+    u1 = fuzz_state(n, seed=73)
+    f1 = fuzz_direction(n, seed=74)
+    dt = 0.13
+    src = u0 if theta == 0.0 else fmr.hermite(u0, f0, u1, f1, dt, theta)
+    ref = fmr.prolong(src, box)
+    grid = P.make_grid(n, L)
+    b = P._lib.make_box(box.origin, box.m)
+    cg = P.cosmos_fmr_child_grid(grid, b)
+    assert tuple(cg.n) == tuple(2 * box.m[a] + 2 * fmr.W for a in range(3))
+    start = fuzz_state(tuple(cg.n), seed=75)
+    child = torch.from_numpy(start).cuda()
+    ws = torch.empty(P.cosmos_fmr_workspace_bytes(grid, b), dtype=torch.uint8, device="cuda")
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    P.cosmos_fmr_prolong(grid, b, dev(u0), dev(f0) if theta else None, dev(u1) if theta else None,
+                         dev(f1) if theta else None, dt, theta, buffer_only, child, ws)
+    got = child.cpu().numpy()
+    if buffer_only:
+        mask = fmr.shell_mask(box)
+        assert np.array_equal(got[:, ~mask], start[:, ~mask])  # the interior is left alone
+        expect = start.copy()
+        expect[:, mask] = ref[:, mask]
+        ref = expect
+    assert rel(got, ref) < 1e-13
+
+
+def test_restrict_matches_oracle_bitwise(P):
+    n, L = (16, 12, 20), (4.0, 3.0, 5.0)
+    box = fmr.Box(origin=(13, 8, -2), m=(5, 6, 4))
+    grid = P.make_grid(n, L)
+    b = P._lib.make_box(box.origin, box.m)
+    cg = P.cosmos_fmr_child_grid(grid, b)
+    child = fuzz_state(tuple(cg.n), seed=81)
+    parent = fuzz_state(n, seed=82)
+    ref = fmr.restrict(child, parent, box)
+    pd = torch.from_numpy(parent).cuda()
+    P.cosmos_fmr_restrict(grid, b, torch.from_numpy(child).cuda(), pd)
+    assert np.array_equal(pd.cpu().numpy(), ref)
+
+
+def test_fmr_argument_checks(P):
+    grid = P.make_grid((16, 16, 16), (4.0, 4.0, 4.0))
+    with pytest.raises(P.CosmosError):
+        P.cosmos_fmr_child_grid(grid, P._lib.make_box((0, 0, 0), (3, 8, 8)))  # m < 4
+    b = P._lib.make_box((2, 2, 2), (6, 6, 6))
+    cg = P.cosmos_fmr_child_grid(grid, b)
+    u = torch.zeros((25, 16, 16, 16), dtype=torch.float64, device="cuda")
+    child = torch.zeros((25, cg.n[2], cg.n[1], cg.n[0]), dtype=torch.float64, device="cuda")
+    ws = torch.empty(P.cosmos_fmr_workspace_bytes(grid, b), dtype=torch.uint8, device="cuda")
+    with pytest.raises(P.CosmosError):  # theta > 0 needs u1, f0, f1
+        P.cosmos_fmr_prolong(grid, b, u, None, None, None, 0.1, 0.5, True, child, ws)
+    with pytest.raises(P.CosmosError):
+        P.cosmos_fmr_prolong(grid, b, u, u, u, u, 0.1, 1.5, True, child, ws)
+
+
+def test_three_layer_run_matches_oracle(P, orc):
+    """Layer 0: 24^3 periodic box of side 10; layer 1 over its central 16^3 cells; layer 2 over the
+    central 8^3 cells of layer 1 (dt, dt/2, dt/4); PGAUSS data; 3 steps of layer 0."""
+    n, L = 24, 10.0
+    boxes = [((4, 4, 4), (16, 16, 16)), ((24, 24, 24), (8, 8, 8))]
+    ini = dict(mu=0.1, sigma=2.5, profile=orc.PGAUSS)
+    run = P.RefinedRun((n, n, n), (L, L, L), boxes)
+    run.init(**ini)
+    s = orc.Setup(n=(n,) * 3, L=(L,) * 3)
+    H = fmr.Hierarchy(s, [fmr.Box(o, m) for o, m in boxes])
+    st = H.init(orc.init_fields(s, orc.Init(**ini)))
+    for k in range(3):
+        assert rel(run.u[k].cpu().numpy(), st[k]) < 1e-13, k
+    dt = run.default_dt()
+    t = 0.0
+    for _ in range(3):
+        run.step(dt)
+        H.step(st, t, dt)
+        t += dt
+    for k in range(3):
+        e = rel(run.interior(k).cpu().numpy(), st[k][:, fmr.W:-fmr.W, fmr.W:-fmr.W, fmr.W:-fmr.W] if k else st[k])
+        print(f"layer {k}: {e:.3e}")
+        assert e < 1e-10, (k, e)
+    assert run.status(0)["nonfinite"] == 0
