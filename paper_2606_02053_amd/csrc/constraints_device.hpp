@@ -22,9 +22,13 @@ struct DirectDerivs {
   size_t fs;
   const Nbr& nb;
   const DevParams& P;
-  __device__ __forceinline__ void pin(double&) {}  // no barriers here: nothing to anchor
+  // a value final for this field stays in a register here (as with the LDS source)
+  __device__ __forceinline__ void pin(double& x) { asm volatile("" : "+v"(x)); }
   template <bool SECOND>
   __device__ __forceinline__ void get(int f, FieldDerivs& d) {
+    // a compiler-level fence per field: the stencil loads of later fields stay after it, so they
+    // are not all hoisted to the start and kept live (no instruction is emitted)
+    asm volatile("" ::: "memory");
     const double nob[3] = {0.0, 0.0, 0.0};
     field_derivs<SECOND, false, false>(U + (size_t)f * fs, nb, P, nob, d);
   }
@@ -32,7 +36,9 @@ struct DirectDerivs {
 
 // H, M_i and the normalised H at the point with linear index c. Der supplies the
 // first (and, with SECOND, second) centred derivatives of a field; it is asked for
-// them in a fixed order: gt_ij (6, with second), Gt^i (3), chi (with second), K, At_ij (6).
+// them in a fixed order: gt_ij (6, with second), chi (with second), Gt^i (3), K, At_ij (6).
+// Every field's derivatives are folded into running sums as they arrive (the Ricci tensor,
+// then H; M_i term by term), so that few of them stay live at once.
 // der.pin(x) marks a running value as final for the current field (a source with barriers
 // between fields keeps it in a register there instead of recomputing it later from every
 // field's derivatives); it changes no value.
@@ -42,25 +48,16 @@ __device__ __forceinline__ void constraint_point(const double* __restrict__ U, s
                                                  bool& nonfinite) {
   nonfinite = false;
   for (int f = 0; f < NF; ++f) nonfinite = nonfinite || !isfinite(ldq(U + (size_t)f * fs, c));
-  const double chi = ldq(U + F_CHI * fs, c);
-  const double K = ldq(U + F_K * fs, c);
-  double gt[6], gi[6], At[6], St[3];
+  // point values are loaded where they are needed (gt_ij twice: for its inverse, then for the
+  // chi and Gt^i terms), so that they are not live across the connection
+  double gi[6];
+  {
+    double gt[6];
 #pragma unroll
-  for (int s = 0; s < 6; ++s) {
-    gt[s] = ldq(U + (F_GT + s) * fs, c);
-    At[s] = ldq(U + (F_AT + s) * fs, c);
+    for (int s = 0; s < 6; ++s) gt[s] = ldq(U + (F_GT + s) * fs, c);
+    inv_sym(gt, gi);
   }
-#pragma unroll
-  for (int i = 0; i < 3; ++i) St[i] = ldq(U + (F_ST + i) * fs, c);
-  inv_sym(gt, gi);
-  Fluid fl;
-  recover(P.w, chi, gi, ldq(U + F_ET * fs, c), St, fl);
-  if (P.xsrc) {  // scalar field: its energy and momentum densities join the fluid's
-    fl.E += ldq(P.xsrc + SRC_E * fs, c);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) fl.S[i] += ldq(P.xsrc + (SRC_S + i) * fs, c);
-    nonfinite = nonfinite || !isfinite(fl.E);
-  }
+  // ---- conformal metric: second derivatives into the Ricci tensor, first into the connection
   double dgt[6][3], Ric[6];
 #pragma unroll
   for (int s = 0; s < 6; ++s) {
@@ -73,12 +70,53 @@ __device__ __forceinline__ void constraint_point(const double* __restrict__ U, s
   }
   double Gu[3][6], Gd[3];
   connection_and_quadratic_ricci(dgt, gi, Gu, Gd, Ric);
+  double At[6];
 #pragma unroll
-  for (int q = 0; q < 6; ++q) der.pin(Ric[q]);
+  for (int s = 0; s < 6; ++s) At[s] = ldq(U + (F_AT + s) * fs, c);
+  // the connection's part of M_i: -gt^jk (Gt^l_jk At_li + Gt^l_ji At_kl)
+  double Mc[3];
 #pragma unroll
-  for (int l = 0; l < 3; ++l)
+  for (int i = 0; i < 3; ++i) {
+    double acc = 0.0;
 #pragma unroll
-    for (int q = 0; q < 6; ++q) der.pin(Gu[l][q]);
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        double term = 0.0;
+#pragma unroll
+        for (int l = 0; l < 3; ++l) term -= Gu[l][S(j, k)] * At[S(l, i)] + Gu[l][S(j, i)] * At[S(k, l)];
+        acc += gi[S(j, k)] * term;
+      }
+    Mc[i] = acc;
+  }
+  // ---- chi: its terms of the Ricci tensor (they need the connection, free after this) and of M_i
+  double Amix[3][3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) Amix[k][j] = gi[S(k, 0)] * At[S(0, j)] + gi[S(k, 1)] * At[S(1, j)] + gi[S(k, 2)] * At[S(2, j)];
+  double AA = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) AA += Amix[i][j] * Amix[j][i];
+  const double chi = ldq(U + F_CHI * fs, c);
+  double gt[6];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) gt[s] = ldq(U + (F_GT + s) * fs, c);
+  {
+    FieldDerivs d;
+    der.template get<true>(F_CHI, d);
+    ricci_conformal_factor(1.0 / chi, d.d1, d.d2, gt, gi, Gu, Ric);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      Mc[i] -= (1.5 / chi) * (Amix[0][i] * d.d1[0] + Amix[1][i] * d.d1[1] + Amix[2][i] * d.d1[2]);
+      der.pin(Mc[i]);
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) der.pin(Ric[q]);
+  }
+  // ---- evolved connection functions: gt_k(i d_j) Gt^k
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     FieldDerivs d;
@@ -90,64 +128,47 @@ __device__ __forceinline__ void constraint_point(const double* __restrict__ U, s
       der.pin(Ric[s]);
     }
   }
-  double dchi[3];
-  {
-    FieldDerivs d;
-    der.template get<true>(F_CHI, d);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) dchi[a] = d.d1[a];
-    ricci_conformal_factor(1.0 / chi, dchi, d.d2, gt, gi, Gu, Ric);
-#pragma unroll
-    for (int q = 0; q < 6; ++q) der.pin(Ric[q]);
-  }
   const double R = chi * contract_sym(gi, Ric);
-
-  double Amix[3][3];
+  const double K = ldq(U + F_K * fs, c);
+  double St[3];
 #pragma unroll
-  for (int k = 0; k < 3; ++k)
+  for (int i = 0; i < 3; ++i) St[i] = ldq(U + (F_ST + i) * fs, c);
+  Fluid fl;
+  recover(P.w, chi, gi, ldq(U + F_ET * fs, c), St, fl);
+  if (P.xsrc) {  // scalar field: its energy and momentum densities join the fluid's
+    fl.E += ldq(P.xsrc + SRC_E * fs, c);
 #pragma unroll
-    for (int j = 0; j < 3; ++j) Amix[k][j] = gi[S(k, 0)] * At[S(0, j)] + gi[S(k, 1)] * At[S(1, j)] + gi[S(k, 2)] * At[S(2, j)];
-  double AA = 0.0;
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j) AA += Amix[i][j] * Amix[j][i];
+    for (int i = 0; i < 3; ++i) fl.S[i] += ldq(P.xsrc + (SRC_S + i) * fs, c);
+    nonfinite = nonfinite || !isfinite(fl.E);
+  }
   H = R + (2.0 / 3.0) * K * K - AA - 16.0 * PI_D * fl.E;
   der.pin(H);
-
-  double dK[3];
+  const double den = fabs(R) + (2.0 / 3.0) * K * K + AA + 16.0 * PI_D * fabs(fl.E);
+  Hn = (den > 0.0) ? H / den : 0.0;
+  der.pin(Hn);
+  // ---- trace K
   {
     FieldDerivs d;
     der.template get<false>(F_K, d);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) dK[a] = d.d1[a];
+    for (int i = 0; i < 3; ++i) {
+      Mc[i] -= (2.0 / 3.0) * d.d1[i];
+      der.pin(Mc[i]);
+    }
   }
-  double dAt[6][3];
+  // ---- At_ab: d_j At_ab enters M_b with gt^ja and, off the diagonal, M_a with gt^jb
 #pragma unroll
   for (int s = 0; s < 6; ++s) {
     FieldDerivs d;
     der.template get<false>(F_AT + s, d);
+    const int a = SI(s), b = SJ(s);
+    Mc[b] += gi[S(0, a)] * d.d1[0] + gi[S(1, a)] * d.d1[1] + gi[S(2, a)] * d.d1[2];
+    if (a != b) Mc[a] += gi[S(0, b)] * d.d1[0] + gi[S(1, b)] * d.d1[1] + gi[S(2, b)] * d.d1[2];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) dAt[s][a] = d.d1[a];
+    for (int i = 0; i < 3; ++i) der.pin(Mc[i]);
   }
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    double acc = 0.0;
-#pragma unroll
-    for (int j = 0; j < 3; ++j)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        double term = dAt[S(k, i)][j];
-#pragma unroll
-        for (int l = 0; l < 3; ++l) term -= Gu[l][S(j, k)] * At[S(l, i)] + Gu[l][S(j, i)] * At[S(k, l)];
-        acc += gi[S(j, k)] * term;
-      }
-    acc -= (1.5 / chi) * (Amix[0][i] * dchi[0] + Amix[1][i] * dchi[1] + Amix[2][i] * dchi[2]);
-    acc -= (2.0 / 3.0) * dK[i] + 8.0 * PI_D * fl.S[i];
-    M[i] = acc;
-  }
-  const double den = fabs(R) + (2.0 / 3.0) * K * K + AA + 16.0 * PI_D * fabs(fl.E);
-  Hn = (den > 0.0) ? H / den : 0.0;
+  for (int i = 0; i < 3; ++i) M[i] = Mc[i] - 8.0 * PI_D * fl.S[i];
   nonfinite = nonfinite || !isfinite(H) || !isfinite(M[0]) || !isfinite(M[1]) || !isfinite(M[2]);
 }
 
@@ -227,26 +248,31 @@ __device__ __forceinline__ Red point_record(const double* __restrict__ U, size_t
   return mine;
 }
 
-// Direct variant: one thread per point in linear order, stencils from global memory.
+// Direct variant: one thread per point in linear order, stencils from global memory. Workgroup
+// b takes the 256-point blocks b, b + gridDim.x, ... (one block each when launched with one
+// workgroup per block) and folds them in that order into its partial record.
 __global__ __launch_bounds__(256) void k_constraints(const double* __restrict__ U, size_t fs, DevParams P,
                                                       double* __restrict__ Hout, double* __restrict__ Mout,
                                                       double* __restrict__ part) {
   __shared__ Red sh[4];  // one entry per wave
-  const int p = blockIdx.x * 256 + threadIdx.x;
   Red mine = red_neutral();
-  if (p < (int)fs) {
-    const int i = p % P.n[0];
-    const int jk = p / P.n[0];
-    const int j = jk % P.n[1];
-    const int k = jk / P.n[1];
-    Nbr nb;
-    make_nbr(nb, i, j, k, P.n);
-    DirectDerivs der{U, fs, nb, P};
-    double H, M[3], Hn;
-    bool bad;
-    constraint_point(U, fs, p, der, P, H, M, Hn, bad);
-    store_hm(fs, p, H, M, Hout, Mout);
-    mine = point_record(U, fs, p, H, M, Hn, bad);
+  const size_t nblk = (fs + 255) / 256;
+  for (size_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    const int p = (int)(blk * 256 + threadIdx.x);
+    if (p < (int)fs) {
+      const int i = p % P.n[0];
+      const int jk = p / P.n[0];
+      const int j = jk % P.n[1];
+      const int k = jk / P.n[1];
+      Nbr nb;
+      make_nbr(nb, i, j, k, P.n);
+      DirectDerivs der{U, fs, nb, P};
+      double H, M[3], Hn;
+      bool bad;
+      constraint_point(U, fs, p, der, P, H, M, Hn, bad);
+      store_hm(fs, p, H, M, Hout, Mout);
+      mine = red_combine(mine, point_record(U, fs, p, H, M, Hn, bad));
+    }
   }
   const Red r = block_tree(mine, sh);
   if (threadIdx.x == 0) red_store(part + (size_t)blockIdx.x * kRedRecord, r);

@@ -311,15 +311,17 @@ int cosmos_rk4_step_stages(const cosmos_grid* grid, const cosmos_params* params,
 
 namespace {
 
-// Constraint norms of u: the LDS-staged kernel (variant 0; 16x4x4 bricks in XCD slabs where
-// one workgroup per brick fits the `cap` partial records at `part`, else workgroups stride over
-// the bricks) or the direct one (variant 1, one workgroup per 256 points: needs cap >=
-// nblocks), then the fixed-order fold of the per-workgroup partials.
+// Constraint norms of u: the LDS-staged kernel (variant 0 with n0 even; 16x4x4 bricks in XCD
+// slabs where one workgroup per brick fits the `cap` partial records at `part`, else workgroups
+// stride over the bricks) or the direct one (variant 1, and grids with odd n0: one workgroup per
+// 256 points, or at most `cap` of them striding over the blocks), then the fixed-order fold of
+// the per-workgroup partials.
 void launch_constraints(const cosmos_grid* grid, const cosmos_params* params, const DevParams& P, const double* u,
                         double* H_out, double* M_out, double* part, size_t cap, double* norms_dev, hipStream_t s) {
   const size_t nb = std::min(nblocks(grid), cap);
   unsigned nparts = (unsigned)nb;
-  if (params->variant == 0 || cap < nblocks(grid)) {
+  // the LDS-staged kernel loads aligned pairs of x-neighbours: n0 even, u 16-byte aligned
+  if (params->variant == 0 && grid->n[0] % 2 == 0 && aligned(u, 16)) {
     cosmos_params bp{};
     bp.tile_x = 16, bp.tile_y = 4, bp.tile_z = 4, bp.tile_order = 0;
     Tile T;

@@ -157,8 +157,9 @@ def test_constraints_lds_equals_direct(P, orc, n):
     """The LDS-staged constraint kernel (variant 0) against the direct one (variant 1): the
     same point arithmetic, so H and M_i agree bitwise; the norms differ only in the order of
     their sums. Grids: one workgroup per brick in XCD slabs (32^3), more bricks than partial
-    records so that workgroups stride over several bricks (20x20x12), ragged bricks (9x13x11,
-    16x20x12). The LDS variant is also checked against the oracle's fields."""
+    records so that workgroups stride over several bricks (20x20x12), ragged bricks (16x20x12,
+    and 9x13x11, whose odd n0 sends variant 0 to the direct kernel too). The LDS variant is also
+    checked against the oracle's fields."""
     L = tuple(0.25 * x for x in n)
     s = orc.Setup(n=n, L=L)
     u = to_dev(fuzz_state(n, seed=21))
