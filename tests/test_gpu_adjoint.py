@@ -52,6 +52,21 @@ def test_rhs_vjp_matches_tape(P, orc, opts):
     assert rel_err(out.cpu().numpy(), ref) < 1e-11
 
 
+def test_rhs_vjp_odd_n0_direct_pass(P, orc):
+    """Odd n0 (no aligned pairs of x-neighbours) takes the direct pass 1; against the tape too."""
+    n, L = (9, 10, 8), (2.7, 3.0, 2.4)
+    s = orc.Setup(n=n, L=L)
+    u = fuzz_state(n, seed=35)
+    kb = fuzz_direction(n, seed=36)
+    ref = orc.vjp(s, u, kb, "rhs", t=0.3)
+    grid = P.make_grid(n, L)
+    params = P.make_params()
+    ws = torch.empty(P.cosmos_adjoint_workspace_bytes(grid), dtype=torch.uint8, device="cuda")
+    out = torch.empty((25,) + u.shape[1:], dtype=torch.float64, device="cuda")
+    P.cosmos_rhs_vjp(grid, params, 0.3, torch.from_numpy(u).cuda(), torch.from_numpy(kb).cuda(), out, ws)
+    assert rel_err(out.cpu().numpy(), ref) < 1e-11
+
+
 def test_adjoint_step_matches_tape(P, orc):
     n, L = (8, 8, 10), (2.4, 2.4, 3.0)
     s = orc.Setup(n=n, L=L)
