@@ -18,8 +18,9 @@ references. This module states, in its plainest form, the scheme the library imp
   child step the buffer is refilled from the parent: in space by 6-point Lagrange interpolation
   per axis (tensor product, coincident points copied; sixth order, so that the second derivatives
   of the interpolation error, which alternates from point to point, stay fourth order), in time
-  by the cubic Hermite interpolant of the parent's trajectory over the parent step (values and
-  right-hand sides at both ends; the second child step starts at its midpoint).
+  by the continuous extension of the parent's RK4 step (its four stage slopes with the cubic
+  weights b_i(theta); third order, a local error O(dt^4) like the step's own; the second child
+  step starts at the midpoint).
 * After the two child steps the parent points that the child's interior covers take the child's
   values (injection), and the child's own children are handled the same way, recursively.
 """
@@ -89,13 +90,40 @@ def shell_mask(box: Box) -> np.ndarray:
     return ~inner
 
 
-def hermite(u0, f0, u1, f1, dt: float, theta: float):
-    """Cubic Hermite interpolant at t0 + theta dt of a trajectory with values u0, u1 and
-    derivatives f0, f1 at t0 and t0 + dt."""
+def rk4_dense_weights(theta: float):
+    """Weights b_1..b_4 of the classic RK4 step's continuous extension: u(t0 + theta dt) =
+    u0 + dt sum_i b_i(theta) k_i, with k_1..k_4 the step's stage slopes (b_i(1) = 1/6, 1/3, 1/3,
+    1/6: the step itself)."""
     t2, t3 = theta * theta, theta * theta * theta
-    h00, h10 = 2.0 * t3 - 3.0 * t2 + 1.0, t3 - 2.0 * t2 + theta
-    h01, h11 = -2.0 * t3 + 3.0 * t2, t3 - t2
-    return h00 * u0 + (h10 * dt) * f0 + h01 * u1 + (h11 * dt) * f1
+    b1 = theta - 1.5 * t2 + (2.0 / 3.0) * t3
+    b23 = t2 - (2.0 / 3.0) * t3
+    b4 = -0.5 * t2 + (2.0 / 3.0) * t3
+    return b1, b23, b23, b4
+
+
+def rk4_stages(s: Setup, u0, t: float, dt: float, parallel: bool = True):
+    """The classic RK4 step written out: slopes k_1..k_4 and the new state."""
+    k1, _ = rhs(s, u0, t, parallel=parallel)
+    k2, _ = rhs(s, u0 + (0.5 * dt) * k1, t + 0.5 * dt, parallel=parallel)
+    k3, _ = rhs(s, u0 + (0.5 * dt) * k2, t + 0.5 * dt, parallel=parallel)
+    k4, _ = rhs(s, u0 + dt * k3, t + dt, parallel=parallel)
+    return (k1, k2, k3, k4), u0 + (dt / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+
+
+def dense(u0, ks, dt: float, theta: float):
+    """The RK4 continuous extension at t0 + theta dt."""
+    b = rk4_dense_weights(theta)
+    return u0 + dt * (b[0] * ks[0] + b[1] * ks[1] + b[2] * ks[2] + b[3] * ks[3])
+
+
+def slopes_from_stage_states(u0, U2, U3, U4, u1, dt: float):
+    """The slopes of an RK4 step from its stage states U2 = u0 + dt/2 k1, U3 = u0 + dt/2 k2,
+    U4 = u0 + dt k3 and its result u1 = u0 + dt/6 (k1 + 2 k2 + 2 k3 + k4)."""
+    k1 = (U2 - u0) / (0.5 * dt)
+    k2 = (U3 - u0) / (0.5 * dt)
+    k3 = (U4 - u0) / dt
+    k4 = 6.0 * (u1 - u0) / dt - k1 - 2.0 * k2 - 2.0 * k3
+    return k1, k2, k3, k4
 
 
 def restrict(u_child: np.ndarray, u_parent: np.ndarray, box: Box) -> np.ndarray:
@@ -140,13 +168,11 @@ class Hierarchy:
         if level == len(self.boxes):
             states[level], _ = rk4(s, u0, t, dt, 1, parallel=parallel)
             return
-        f0, _ = rhs(s, u0, t, parallel=parallel)
-        u1, _ = rk4(s, u0, t, dt, 1, parallel=parallel)
-        f1, _ = rhs(s, u1, t + dt, parallel=parallel)
+        ks, u1 = rk4_stages(s, u0, t, dt, parallel=parallel)
         box = self.boxes[level]
         mask = shell_mask(box)
         for half in (0, 1):
-            src = u0 if half == 0 else hermite(u0, f0, u1, f1, dt, 0.5)
+            src = u0 if half == 0 else dense(u0, ks, dt, 0.5)
             child = states[level + 1].copy()
             child[:, mask] = prolong(src, box)[:, mask]
             states[level + 1] = child

@@ -1,7 +1,8 @@
 """The oracle's fixed mesh refinement (oracle/fmr.py; paper: nested refinement layers, "Statement of
 need" and the adiabatic-fluctuation example) pinned by what fixes it independently of itself:
-its interpolation reproduces polynomials of the degree it claims, its time interpolant is exact
-for cubics in time, restriction after prolongation returns the parent, and a refined run converges
+its interpolation reproduces polynomials of the degree it claims, its time interpolant (the RK4
+step's continuous extension) is exact for cubic solutions, restriction after prolongation returns
+the parent, and a refined run converges
 to the uniform run at the child's resolution at fourth order away from the coarse-fine interface."""
 import numpy as np
 import pytest
@@ -37,19 +38,38 @@ def test_prolongation_exact_for_quintics():
     assert err6 > 1e-9
 
 
-def test_hermite_exact_for_cubics_in_time():
+def test_rk4_continuous_extension():
+    """The time interpolant: for u' = f(t) the RK4 stages are quadrature nodes, and the continuous
+    extension reproduces the exact solution at every theta when f is quadratic (u cubic), but not
+    when f is cubic (except at theta = 1, where the step itself is exact); for u' = lam u its
+    midpoint error falls by 16 per halving of dt (local error O(dt^4)); the slopes recovered from
+    the stage states are the slopes."""
     rng = np.random.default_rng(3)
-    a = rng.standard_normal(4)
-    t0, dt = 0.7, 0.3
-    u = lambda t: a[0] + a[1] * t + a[2] * t ** 2 + a[3] * t ** 3  # noqa: E731
-    du = lambda t: a[1] + 2 * a[2] * t + 3 * a[3] * t ** 2  # noqa: E731
-    for theta in (0.0, 0.25, 0.5, 1.0):
-        v = fmr.hermite(u(t0), du(t0), u(t0 + dt), du(t0 + dt), dt, theta)
-        assert v == pytest.approx(u(t0 + theta * dt), rel=1e-14, abs=1e-14)
-    # a quartic is not (the interpolant is the cubic one)
-    q = lambda t: t ** 4  # noqa: E731
-    v = fmr.hermite(q(t0), 4 * t0 ** 3, q(t0 + dt), 4 * (t0 + dt) ** 3, dt, 0.5)
-    assert abs(v - q(t0 + 0.5 * dt)) > 1e-6
+    t0, dt = 0.3, 0.7
+    for deg, exact in ((0, True), (1, True), (2, True), (3, False)):
+        c = rng.standard_normal(deg + 1)
+        F = np.polyint(c)
+        ks = [np.polyval(c, t0), np.polyval(c, t0 + 0.5 * dt), np.polyval(c, t0 + 0.5 * dt), np.polyval(c, t0 + dt)]
+        for theta in (0.25, 0.5, 0.8):
+            err = abs(fmr.dense(0.0, ks, dt, theta) - (np.polyval(F, t0 + theta * dt) - np.polyval(F, t0)))
+            assert (err < 1e-14) == exact, (deg, theta, err)
+    errs = []
+    for h in (0.1, 0.05, 0.025):
+        lam = -1.3
+        k1 = lam
+        k2 = lam * (1.0 + 0.5 * h * k1)
+        k3 = lam * (1.0 + 0.5 * h * k2)
+        k4 = lam * (1.0 + h * k3)
+        errs.append(abs(fmr.dense(1.0, (k1, k2, k3, k4), h, 0.5) - np.exp(0.5 * lam * h)))
+    assert 14.0 < errs[0] / errs[1] < 18.0 and 14.0 < errs[1] / errs[2] < 18.0, errs
+    b = fmr.rk4_dense_weights(1.0)
+    assert np.allclose(b, (1 / 6, 1 / 3, 1 / 3, 1 / 6), rtol=0, atol=1e-15)
+    u0, ks = rng.standard_normal(5), [rng.standard_normal(5) for _ in range(4)]
+    U2, U3, U4 = u0 + 0.5 * dt * ks[0], u0 + 0.5 * dt * ks[1], u0 + dt * ks[2]
+    u1 = u0 + dt / 6 * (ks[0] + 2 * ks[1] + 2 * ks[2] + ks[3])
+    back = fmr.slopes_from_stage_states(u0, U2, U3, U4, u1, dt)
+    for a, k in zip(back, ks):
+        assert np.allclose(a, k, rtol=1e-12, atol=1e-12)
 
 
 def test_restrict_after_prolong_returns_the_parent():
