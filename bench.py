@@ -673,8 +673,8 @@ def fmr_bench(a):
     layer 0 a 128^3 periodic grid, layer 1 over its central 64^3 cells (h/2), layer 2 over the
     central 64^3 cells of layer 1 (h/4); Berger-Oliger sub-cycling (1, 2, 4 steps per layer-0
     step). Timed with HIP events on the launch stream; beside it the same RK4 steps of the three
-    padded grids run alone, whose difference is the cost of the refinement (interpolation,
-    injection, the parents' right-hand sides for the time interpolant)."""
+    padded grids run alone, whose difference is the cost of the refinement (interpolation in
+    space and time, injection, the parents' start-of-step copies)."""
     import paper_2606_02053_amd as P
     n, L = 128, 16.0
     boxes = [((32, 32, 32), (64, 64, 64)), ((44, 44, 44), (64, 64, 64))]
@@ -715,7 +715,7 @@ def fmr_bench(a):
            "timed_steps": steps, "dtype": "f64", "data": "synthetic",
            "roofline": step_roofline(padded / (ms / 1e3), BYTES_PER_POINT_STEP,
                                      "k_bssn_stage_lds + k_fluid_flux on the padded layers, k_fmr_pass_*, "
-                                     "k_fmr_restrict, right-hand sides of layers 0 and 1"),
+                                     "k_fmr_restrict"),
            "config": {"workload": "3 layers: 128^3 periodic, L = 16/H0, Gaussian zeta mu = 0.6 sigma = 2.0; layer 1 "
                                   "= central 64^3 cells at h/2 (152^3 padded), layer 2 = central 64^3 cells of layer 1 "
                                   "at h/4 (152^3 padded); buffer 12; CFL 0.25 on every layer"}}

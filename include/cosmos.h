@@ -360,9 +360,9 @@ int cosmos_batch_status(const cosmos_batch* batch, void* bws, void* stream, int6
  *     points further inwards per RK4 stage, so the outer COSMOS_FMR_BUFFER layers go stale within
  *     a step and the interior stays exact;
  *   - per parent step dt the child takes two steps dt/2; before each, cosmos_fmr_prolong refills
- *     the buffer from the parent (6-point Lagrange in space, cubic Hermite in time over the
- *     parent step), and after both cosmos_fmr_restrict copies the child's interior onto the
- *     parent points it covers.
+ *     the buffer from the parent (6-point Lagrange in space; in time the continuous extension of
+ *     the parent's RK4 step from its stage states), and after both cosmos_fmr_restrict copies the
+ *     child's interior onto the parent points it covers.
  * The driver (paper_2606_02053_amd/fmr.py) sequences these calls; every value is computed here. */
 #define COSMOS_FMR_BUFFER 12
 
@@ -380,19 +380,23 @@ int cosmos_fmr_child_grid(const cosmos_grid* parent, const cosmos_box* box, cosm
  * partially interpolated intermediates); 0 for invalid arguments. */
 size_t cosmos_fmr_workspace_bytes(const cosmos_grid* parent, const cosmos_box* box);
 
-/* Child values interpolated from the parent. The parent's values in time: theta == 0 takes u0
- * (f0, u1, f1 may be NULL); 0 < theta <= 1 takes the cubic Hermite interpolant at t0 + theta dt
- * of the parent's trajectory with values u0, u1 and right-hand sides f0, f1 (cosmos_rhs) at t0 and
- * t0 + dt. In space, per axis: a child point that coincides with a parent point copies it, a
- * midpoint takes (3, -25, 150, 150, -25, 3)/256 of the 6 parent points around it (exact for
- * quintics), applied along x, then y, then z. buffer_only != 0 writes only the child points within
- * COSMOS_FMR_BUFFER of a face; 0 writes the whole padded child (initial data). Parent arrays:
- * device, 25 x N3(parent) doubles; child_u: device, 25 x N3(child) doubles, not overlapping them;
- * ws: cosmos_fmr_workspace_bytes, 256-byte aligned. Asynchronous on `stream`. Errors: COSMOS_EINVAL
- * (invalid grid/box/pointers, theta outside [0, 1], theta > 0 without u1/f0/f1 or with dt <= 0). */
-int cosmos_fmr_prolong(const cosmos_grid* parent, const cosmos_box* box, const double* u0, const double* f0,
-                       const double* u1, const double* f1, double dt, double theta, int32_t buffer_only,
-                       double* child_u, void* ws, void* stream);
+/* Child values interpolated from the parent. The parent's values in time: theta == 0 takes u_n
+ * (stages and u_np1 may be NULL); 0 < theta <= 1 takes the continuous extension of the parent's
+ * RK4 step from u_n to u_np1 at t_n + theta dt, u_n + dt sum_i b_i(theta) k_i with
+ * b = (theta - 3/2 theta^2 + 2/3 theta^3, theta^2 - 2/3 theta^3 (twice), -1/2 theta^2 + 2/3 theta^3),
+ * the slopes k_i recovered from the step's stage states (stages: U2, U3, U4 as
+ * cosmos_rk4_step_stages keeps them, 3 x 25 x N3(parent) doubles); at theta = 1/2 this is
+ * (2 U2 + 2 U3 + U4 - u_np1) / 4. In space, per axis: a child point that coincides with a parent
+ * point copies it, a midpoint takes (3, -25, 150, 150, -25, 3)/256 of the 6 parent points around
+ * it (exact for quintics), applied along x, then y, then z. buffer_only != 0 writes only the child
+ * points within COSMOS_FMR_BUFFER of a face; 0 writes the whole padded child (initial data).
+ * Parent arrays: device, 25 x N3(parent) doubles each; child_u: device, 25 x N3(child) doubles,
+ * not overlapping them; ws: cosmos_fmr_workspace_bytes, 256-byte aligned. Asynchronous on
+ * `stream`. Errors: COSMOS_EINVAL (invalid grid/box/pointers, theta outside [0, 1], theta > 0
+ * without stages or u_np1). */
+int cosmos_fmr_prolong(const cosmos_grid* parent, const cosmos_box* box, const double* u_n, const double* stages,
+                       const double* u_np1, double theta, int32_t buffer_only, double* child_u, void* ws,
+                       void* stream);
 
 /* Injection: parent points origin + j (0 <= j < m per axis, wrapped) take the child's values at
  * its interior points 2 j (padded index COSMOS_FMR_BUFFER + 2 j). child_u and parent_u: device,

@@ -94,7 +94,7 @@ def _load():
         "cosmos_constraints_scalar": ([G, Pr, P, P, P, P, P, P, P, P], i32),
         "cosmos_fmr_child_grid": ([G, ctypes.POINTER(cosmos_box), G], i32),
         "cosmos_fmr_workspace_bytes": ([G, ctypes.POINTER(cosmos_box)], sz),
-        "cosmos_fmr_prolong": ([G, ctypes.POINTER(cosmos_box), P, P, P, P, f64, f64, ctypes.c_int32, P, P, P], i32),
+        "cosmos_fmr_prolong": ([G, ctypes.POINTER(cosmos_box), P, P, P, f64, ctypes.c_int32, P, P, P], i32),
         "cosmos_fmr_restrict": ([G, ctypes.POINTER(cosmos_box), P, P, P], i32),
         "cosmos_last_error": ([], ctypes.c_char_p),
         "cosmos_abi_version": ([], i32),
@@ -391,12 +391,11 @@ def cosmos_fmr_workspace_bytes(parent: cosmos_grid, box: cosmos_box) -> int:
     return int(lib.cosmos_fmr_workspace_bytes(ctypes.byref(parent), ctypes.byref(box)))
 
 
-def cosmos_fmr_prolong(parent, box, u0, f0, u1, f1, dt: float, theta: float, buffer_only: bool, child_u, ws,
-                       stream=None):
+def cosmos_fmr_prolong(parent, box, u_n, stages, u_np1, theta: float, buffer_only: bool, child_u, ws, stream=None):
     Np = NFIELDS * npts(parent)
     child = cosmos_fmr_child_grid(parent, box)
-    _check(lib.cosmos_fmr_prolong(ctypes.byref(parent), ctypes.byref(box), _dev(u0, "u0", Np), _dev(f0, "f0", Np),
-                                  _dev(u1, "u1", Np), _dev(f1, "f1", Np), float(dt), float(theta),
+    _check(lib.cosmos_fmr_prolong(ctypes.byref(parent), ctypes.byref(box), _dev(u_n, "u_n", Np),
+                                  _dev(stages, "stages", 3 * Np), _dev(u_np1, "u_np1", Np), float(theta),
                                   int(bool(buffer_only)), _dev(child_u, "child_u", NFIELDS * npts(child)),
                                   _dev(ws, "ws", cosmos_fmr_workspace_bytes(parent, box), dtype=torch.uint8),
                                   _stream(stream)))

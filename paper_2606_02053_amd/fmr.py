@@ -1,15 +1,15 @@
 """Fixed mesh refinement driver: Berger-Oliger sub-cycling over nested layers (paper: nested
 refinement layers, "Statement of need" and the adiabatic-fluctuation example).
 
-Sequencing only: every value is computed by the library (cosmos_rhs, cosmos_rk4_step,
-cosmos_fmr_prolong, cosmos_fmr_restrict); PyTorch holds the device arrays. The scheme is the one
+Sequencing only: every value is computed by the library (cosmos_rk4_step,
+cosmos_rk4_step_stages, cosmos_fmr_prolong, cosmos_fmr_restrict); PyTorch holds the device arrays. The scheme is the one
 stated with those entry points in include/cosmos.h:
 
-  step of layer l (dt):   f0 = f(u_l, t); keep u_l as u0; RK4 step of u_l; f1 = f(u_l, t + dt);
+  step of layer l (dt):   keep u_l as u0; RK4 step of u_l keeping its stage states;
                           for each half h = 0, 1: refill layer l + 1's buffer from layer l at
-                          theta = h / 2 (u0 alone for h = 0, the cubic Hermite interpolant for
-                          h = 1), then step layer l + 1 by dt / 2 (recursively);
-                          copy layer l + 1's interior onto u_l (injection).
+                          theta = h / 2 (u0 alone for h = 0, the step's continuous extension from
+                          its stage states for h = 1), then step layer l + 1 by dt / 2
+                          (recursively); copy layer l + 1's interior onto u_l (injection).
 """
 from __future__ import annotations
 
@@ -42,10 +42,9 @@ class RefinedRun:
         self.u = [torch.empty((C.NFIELDS, g.n[2], g.n[1], g.n[0]), **f64) for g in self.grids]
         self.ws = [torch.empty(C.cosmos_workspace_bytes(g), dtype=torch.uint8, device=self.device)
                    for g in self.grids]
-        # per refined parent: the start-of-step copy, both right-hand sides, the prolongation workspace
+        # per refined parent: the start-of-step copy, the step's stage states, the prolongation workspace
         self.u0 = [torch.empty_like(self.u[k]) for k in range(len(self.boxes))]
-        self.f0 = [torch.empty_like(self.u[k]) for k in range(len(self.boxes))]
-        self.f1 = [torch.empty_like(self.u[k]) for k in range(len(self.boxes))]
+        self.stages = [torch.empty((3,) + tuple(self.u[k].shape), **f64) for k in range(len(self.boxes))]
         self.pws = [torch.empty(C.cosmos_fmr_workspace_bytes(self.grids[k], b), dtype=torch.uint8,
                                 device=self.device) for k, b in enumerate(self.boxes)]
         for w in self.ws:
@@ -65,8 +64,7 @@ class RefinedRun:
         """Layer 0's initial data (cosmos_init_fields); finer layers interpolated from their parents."""
         C.cosmos_init_fields(self.grids[0], self.params, C.make_init(**kw), self.u[0])
         for k, b in enumerate(self.boxes):
-            C.cosmos_fmr_prolong(self.grids[k], b, self.u[k], None, None, None, 0.0, 0.0, False, self.u[k + 1],
-                                 self.pws[k])
+            C.cosmos_fmr_prolong(self.grids[k], b, self.u[k], None, None, 0.0, False, self.u[k + 1], self.pws[k])
         self.t = 0.0
 
     def _step(self, k: int, t: float, dt: float):
@@ -75,13 +73,10 @@ class RefinedRun:
             C.cosmos_rk4_step(g, self.params, t, dt, u, self.ws[k])
             return
         b = self.boxes[k]
-        C.cosmos_rhs(g, self.params, t, u, self.f0[k], self.ws[k])
         self.u0[k].copy_(u)
-        C.cosmos_rk4_step(g, self.params, t, dt, u, self.ws[k])
-        C.cosmos_rhs(g, self.params, t + dt, u, self.f1[k], self.ws[k])
+        C.cosmos_rk4_step_stages(g, self.params, t, dt, u, self.stages[k], self.ws[k])
         for half in (0, 1):
-            C.cosmos_fmr_prolong(g, b, self.u0[k], self.f0[k], u, self.f1[k], dt, 0.5 * half, True,
-                                 self.u[k + 1], self.pws[k])
+            C.cosmos_fmr_prolong(g, b, self.u0[k], self.stages[k], u, 0.5 * half, True, self.u[k + 1], self.pws[k])
             self._step(k + 1, t + 0.5 * half * dt, 0.5 * dt)
         C.cosmos_fmr_restrict(g, b, self.u[k + 1], u)
 

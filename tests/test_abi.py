@@ -180,11 +180,9 @@ def test_fmr_geometry_on_host(C):
     assert C.cosmos_fmr_workspace_bytes(g, C.make_box((0, 0, 0), (3, 6, 6))) == 0
     lib = C.lib
     fake = ctypes.c_void_p(0x100000)
-    rc = lib.cosmos_fmr_prolong(ctypes.byref(g), ctypes.byref(b), fake, None, None, None, 0.1, 0.5, 1, fake, fake,
-                                None)
-    assert rc == C.COSMOS_EINVAL and "f0" in C.last_error()
-    rc = lib.cosmos_fmr_prolong(ctypes.byref(g), ctypes.byref(b), fake, fake, fake, fake, 0.1, -0.5, 1, fake, fake,
-                                None)
+    rc = lib.cosmos_fmr_prolong(ctypes.byref(g), ctypes.byref(b), fake, None, None, 0.5, 1, fake, fake, None)
+    assert rc == C.COSMOS_EINVAL and "stages" in C.last_error()
+    rc = lib.cosmos_fmr_prolong(ctypes.byref(g), ctypes.byref(b), fake, fake, fake, -0.5, 1, fake, fake, None)
     assert rc == C.COSMOS_EINVAL and "theta" in C.last_error()
     rc = lib.cosmos_fmr_restrict(ctypes.byref(g), ctypes.byref(b), None, fake, None)
     assert rc == C.COSMOS_EINVAL and "child_u" in C.last_error()

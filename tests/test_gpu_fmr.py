@@ -1,6 +1,6 @@
 """Fixed mesh refinement on the GPU against the oracle (oracle/fmr.py): the prolongation entry point
-(whole child and buffer only, parent values at the step start and the Hermite midpoint, a box
-that wraps around the periodic parent), the injection, and a three-layer refined run (layer 0
+(whole child and buffer only, parent values at the step start and from the step's continuous
+extension, a box that wraps around the periodic parent), the injection, and a three-layer refined run (layer 0
 periodic, two nested children, Berger-Oliger sub-cycling) layer by layer after several steps."""
 import numpy as np
 import pytest
@@ -25,28 +25,35 @@ def rel(a, b, floor=1e-6):
     return (np.abs(a - b).max(axis=1) / np.maximum(np.abs(b).max(axis=1), floor)).max()
 
 
-@pytest.mark.parametrize("theta", [0.0, 0.5])
+@pytest.mark.parametrize("theta", [0.0, 0.5, 0.3])
 @pytest.mark.parametrize("buffer_only", [False, True])
 def test_prolong_matches_oracle(P, theta, buffer_only):
+    """Interpolation from a parent step's start, its continuous extension at the midpoint (the
+    refill the driver does) and at another theta, whole child or buffer only, on a box that wraps
+    around the periodic parent; the oracle forms the slopes from the stage states and takes
+    u0 + dt sum_i b_i k_i."""
     n, L = (20, 16, 24), (5.0, 4.0, 6.0)
     box = fmr.Box(origin=(15, -3, 5), m=(6, 5, 8))  # wraps in x and y
     u0 = fuzz_state(n, seed=71)
-    f0 = fuzz_direction(n, seed=72)
-    u1 = fuzz_state(n, seed=73)
-    f1 = fuzz_direction(n, seed=74)
+    stages = np.stack([u0 + 0.05 * fuzz_direction(n, seed=72 + q) for q in range(3)])
+    u1 = u0 + 0.05 * fuzz_direction(n, seed=75)
     dt = 0.13
-    src = u0 if theta == 0.0 else fmr.hermite(u0, f0, u1, f1, dt, theta)
+    if theta == 0.0:
+        src = u0
+    else:
+        ks = fmr.slopes_from_stage_states(u0, stages[0], stages[1], stages[2], u1, dt)
+        src = fmr.dense(u0, ks, dt, theta)
     ref = fmr.prolong(src, box)
     grid = P.make_grid(n, L)
     b = P._lib.make_box(box.origin, box.m)
     cg = P.cosmos_fmr_child_grid(grid, b)
     assert tuple(cg.n) == tuple(2 * box.m[a] + 2 * fmr.W for a in range(3))
-    start = fuzz_state(tuple(cg.n), seed=75)
+    start = fuzz_state(tuple(cg.n), seed=76)
     child = torch.from_numpy(start).cuda()
     ws = torch.empty(P.cosmos_fmr_workspace_bytes(grid, b), dtype=torch.uint8, device="cuda")
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
-    P.cosmos_fmr_prolong(grid, b, dev(u0), dev(f0) if theta else None, dev(u1) if theta else None,
-                         dev(f1) if theta else None, dt, theta, buffer_only, child, ws)
+    P.cosmos_fmr_prolong(grid, b, dev(u0), dev(stages) if theta else None, dev(u1) if theta else None, theta,
+                         buffer_only, child, ws)
     got = child.cpu().numpy()
     if buffer_only:
         mask = fmr.shell_mask(box)
@@ -80,10 +87,11 @@ def test_fmr_argument_checks(P):
     u = torch.zeros((25, 16, 16, 16), dtype=torch.float64, device="cuda")
     child = torch.zeros((25, cg.n[2], cg.n[1], cg.n[0]), dtype=torch.float64, device="cuda")
     ws = torch.empty(P.cosmos_fmr_workspace_bytes(grid, b), dtype=torch.uint8, device="cuda")
-    with pytest.raises(P.CosmosError):  # theta > 0 needs u1, f0, f1
-        P.cosmos_fmr_prolong(grid, b, u, None, None, None, 0.1, 0.5, True, child, ws)
+    st = torch.zeros((3, 25, 16, 16, 16), dtype=torch.float64, device="cuda")
+    with pytest.raises(P.CosmosError):  # theta > 0 needs the stage states and u_np1
+        P.cosmos_fmr_prolong(grid, b, u, None, None, 0.5, True, child, ws)
     with pytest.raises(P.CosmosError):
-        P.cosmos_fmr_prolong(grid, b, u, u, u, u, 0.1, 1.5, True, child, ws)
+        P.cosmos_fmr_prolong(grid, b, u, st, u, 1.5, True, child, ws)
 
 
 def test_three_layer_run_matches_oracle(P, orc):
