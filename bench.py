@@ -22,7 +22,7 @@ Extra modes:
                  sigma = 1.2, 200 RK4 steps, checkpoint every 20; gradient of the centre
                  lapse in (mu, sigma) by the discrete adjoint, its cost relative to the
                  plain forward run, and central finite differences (h = 1e-6)
-  --threshold    only the threshold search (32^3, box 12/H0, sigma = 1.2, 100 RK4 steps):
+  --threshold    only the threshold search (32^3, box 12/H0, sigma = 1.2, 24 RK4 steps):
                  batched multisection + Newton with the adjoint derivative for the amplitude
                  whose centre lapse equals that of mu = 0.4371, against serial bisection
   --kt           only the headline workload with the Kurganov-Tadmor fluid scheme
@@ -771,14 +771,18 @@ def cpu_baseline_adjoint():
 
 
 def threshold_bench(a):
-    """Time to locate mu* (alpha_centre(T; mu*) = alpha_centre(T; 0.4371)) in [0.3, 0.6] to 1e-10:
-    batched multisection (3 rounds of 16 runs) + Newton with the adjoint derivative, against
-    serial bisection with the plain solver (one run per bisection step, its cost measured).
-    A 32^3 run fills half the GPU, so 16 of them in one batch cost little more than one."""
+    """Time to locate the collapse threshold mu* in [0.3, 0.6] to 1e-10, with alpha_th the centre
+    lapse after T of the run with mu = 0.4371 (so that mu* = 0.4371): batched multisection on the
+    device collapse counters (3 rounds of 16 runs) + Newton with the adjoint derivative, against
+    serial bisection with the plain solver (one run per bisection step, its cost measured). T is 24
+    steps: up to there the lapse falls monotonically and is lowest at the centre, so the collapse
+    test and the centre-lapse surrogate share their root (later the centre lapse rebounds after a
+    minimum near step 30, and the two would part). A 32^3 run fills half the GPU, so 16 of them in
+    one batch cost little more than one."""
     import math
     import paper_2606_02053_amd as P
     from paper_2606_02053_amd.threshold import find_threshold
-    n, L, sigma, nsteps, mu_ref, lo, hi, tol = 32, 12.0, 1.2, 100, 0.4371, 0.3, 0.6, 1e-10
+    n, L, sigma, nsteps, mu_ref, lo, hi, tol = 32, 12.0, 1.2, 24, 0.4371, 0.3, 0.6, 1e-10
     dt = 0.25 * L / n
     s = P.Solver(n, L)
 
