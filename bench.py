@@ -781,7 +781,7 @@ def threshold_bench(a):
     one batch cost little more than one."""
     import math
     import paper_2606_02053_amd as P
-    from paper_2606_02053_amd.threshold import find_threshold
+    from paper_2606_02053_amd.threshold import find_threshold, find_threshold_interpolated
     n, L, sigma, nsteps, mu_ref, lo, hi, tol = 32, 12.0, 1.2, 24, 0.4371, 0.3, 0.6, 1e-10
     dt = 0.25 * L / n
     s = P.Solver(n, L)
@@ -801,13 +801,22 @@ def threshold_bench(a):
     res = find_threshold(sigma, lo, hi, target, n=n, L=L, nsteps=nsteps, K=16, rounds=3, tol=tol)
     torch.cuda.synchronize()
     t_search = time.perf_counter() - t0
+    # batched rounds alone, each fitting the runs' centre lapse (no adjoint)
+    t0 = time.perf_counter()
+    res_i = find_threshold_interpolated(sigma, lo, hi, target, n=n, L=L, nsteps=nsteps, K=16, rounds=2, tol=tol)
+    torch.cuda.synchronize()
+    t_interp = time.perf_counter() - t0
     bisect_runs = math.ceil(math.log2((hi - lo) / tol))
     return {"metric": "threshold search time (batched multisection + adjoint Newton)", "value": t_search,
             "unit": "s", "higher_is_better": False, "mu_found": res.mu, "mu_reference": mu_ref,
             "abs_error": abs(res.mu - mu_ref), "J_at_mu": res.J, "dJ_dmu": res.dJ_dmu,
             "batched_runs": res.batched_runs, "newton_steps": res.newton_steps,
             "serial_bisection_runs": bisect_runs, "serial_run_s": t_run,
-            "serial_bisection_s_estimate": bisect_runs * t_run, "dtype": "f64", "data": "synthetic",
+            "serial_bisection_s_estimate": bisect_runs * t_run,
+            "interpolated_search": {"s": t_interp, "mu_found": res_i.mu, "abs_error": abs(res_i.mu - mu_ref),
+                                    "batched_runs": res_i.batched_runs,
+                                    "note": "batched rounds alone, the cubic through the runs' centre lapse"},
+            "dtype": "f64", "data": "synthetic",
             "config": {"workload": f"{n}^3 periodic, L = 12/H0, Gaussian zeta sigma = 1.2, {nsteps} RK4 steps, "
                                    f"CFL 0.25; mu* in [{lo}, {hi}] with alpha_centre(T; mu*) = alpha_centre(T; "
                                    f"{mu_ref}), tolerance {tol}"}}

@@ -22,6 +22,10 @@ not. Two stages:
 
 Every evaluation runs the same stage kernel on the same grid, so the values the two
 stages see agree bitwise.
+
+find_threshold_interpolated uses the batch alone: each round's runs also give the centre lapse at
+T, and the root of the cubic through the four runs around its sign change places the next
+round's runs in a window 1e-4 as wide (two rounds reach rounding level).
 """
 from __future__ import annotations
 
@@ -136,6 +140,71 @@ def find_threshold(sigma: float, lo: float, hi: float, alpha_th: float, n: int =
         mu = new
     return ThresholdResult(mu=best[0], J=best[1], dJ_dmu=best[2], bracket=(lo, hi), batched_runs=runs,
                            newton_steps=steps, history=history)
+
+
+def _cubic_root(pts, lo: float, hi: float) -> float:
+    """Root in [lo, hi] of the cubic through four (mu, J) points, J changing sign on [lo, hi]:
+    bisection on the Lagrange form (no division by a derivative that may vanish)."""
+    def cubic(x):
+        total = 0.0
+        for i, (xi, yi) in enumerate(pts):
+            w = yi
+            for j, (xj, _) in enumerate(pts):
+                if j != i:
+                    w *= (x - xj) / (xi - xj)
+            total += w
+        return total
+    flo = cubic(lo)
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if mid == lo or mid == hi:
+            break
+        fm = cubic(mid)
+        if (fm > 0.0) == (flo > 0.0):
+            lo, flo = mid, fm
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+def find_threshold_interpolated(sigma: float, lo: float, hi: float, alpha_th: float, n: int = 32,
+                                L: float = 12.0, nsteps: int = 50, K: int = 16, rounds: int = 2, tol: float = 1e-12,
+                                params=None) -> ThresholdResult:
+    """The collapse threshold by batched rounds alone: every round runs K amplitudes in one batch and
+    reads each run's centre lapse at T from the device (cosmos_batch_outcomes); the root of
+    alpha_centre(T; mu) - alpha_th on the cubic through the four runs around its sign change is the
+    next estimate, and the next round spreads its K runs over a window 1e-4 of the previous one
+    around it. The collapse counters keep [lo, hi] a bracket (lo does not collapse, hi does); a
+    round whose runs do not change sign is repeated over the bracket. Where the centre lapse is
+    the run's lowest, the two criteria share their root."""
+    history = []
+    runs, fitted = 0, 0
+    a, b = lo, hi
+    mu = 0.5 * (lo + hi)
+    for _ in range(rounds + 4):  # a round without a sign change is repeated over the bracket
+        mus = [a + (b - a) * (k + 1) / (K + 1) for k in range(K)]
+        res = scan_batch(mus, sigma, n, L, nsteps, alpha_th, params)
+        runs += K
+        history += [("batched", m, x["collapsed"], x["alpha_centre"], x["alpha_min"]) for m, x in zip(mus, res)]
+        for m, x in zip(mus, res):
+            if x["collapsed"]:
+                hi = min(hi, m)
+            else:
+                lo = max(lo, m)
+        J = [x["alpha_centre"] - alpha_th for x in res]
+        k = next((k for k in range(K - 1) if (J[k] > 0.0) != (J[k + 1] > 0.0)), None)
+        if k is None:
+            a, b = lo, hi
+            continue
+        i0 = min(max(k - 1, 0), K - 4)
+        mu = _cubic_root(list(zip(mus[i0:i0 + 4], J[i0:i0 + 4])), mus[k], mus[k + 1])
+        fitted += 1
+        if fitted >= rounds or mus[k + 1] - mus[k] <= tol:
+            break
+        w = 1e-4 * (b - a)
+        a, b = max(lo, mu - 0.5 * w), min(hi, mu + 0.5 * w)
+    return ThresholdResult(mu=mu, J=float("nan"), dJ_dmu=float("nan"), bracket=(lo, hi), batched_runs=runs,
+                           newton_steps=0, history=history)
 
 
 def find_threshold_isocurvature(sigma: float, lo: float, hi: float, alpha_th: float, zeta=(0.0, 1.0),

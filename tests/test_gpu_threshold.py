@@ -38,6 +38,23 @@ def test_threshold_search_recovers_oracle_amplitude(orc):
     assert res.dJ_dmu == pytest.approx(float(v[17, c, c, c]), rel=1e-8)
 
 
+def test_interpolated_search_recovers_oracle_amplitude(orc):
+    """Batched rounds alone: the cubic through the runs around the sign change of the centre lapse
+    lands on the oracle's amplitude in two rounds of 8 runs; the collapse counters bracket it."""
+    from paper_2606_02053_amd.threshold import find_threshold_interpolated
+    n, L, nsteps, sigma, mu_star = 16, 6.0, 10, 1.2, 0.4137
+    s = orc.Setup(n=(n, n, n), L=(L, L, L))
+    dt = 0.25 * L / n
+    c = n // 2
+    u, _ = orc.rk4(s, orc.init_fields(s, orc.Init(mu=mu_star, sigma=sigma)), 0.0, dt, nsteps, parallel=True)
+    target = float(u[17, c, c, c])
+    res = find_threshold_interpolated(sigma, 0.3, 0.5, target, n=n, L=L, nsteps=nsteps, K=8, rounds=2)
+    assert res.batched_runs == 16
+    lo, hi = res.bracket
+    assert lo <= mu_star <= hi and hi - lo < 0.2 / 9 * 1e-4 * 2
+    assert abs(res.mu - mu_star) < 1e-9, res
+
+
 def test_isocurvature_threshold_by_multisection(orc):
     """The iso-curvature amplitude whose centre lapse matches the oracle's at a known amplitude:
     the multisection bracket (K + 1 = 9 times narrower per round) closes on it."""
