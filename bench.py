@@ -728,7 +728,7 @@ def fmr_bench(a):
 
 def cpu_baseline_fmr():
     """The oracle's refined run (oracle/fmr.py) on a bounded sample: a 24^3 periodic grid with one
-    child over its central 16^3 cells (56^3 padded), two layer-0 steps, OpenMP inside each step."""
+    child over its central 16^3 cells (56^3 padded), eight layer-0 steps, OpenMP inside each step."""
     import oracle
     from oracle import fmr
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -736,24 +736,26 @@ def cpu_baseline_fmr():
     H = fmr.Hierarchy(s, [fmr.Box((4, 4, 4), (16, 16, 16))])
     st = H.init(oracle.init_fields(s, oracle.Init(mu=0.6, sigma=2.0)))
     dt = 0.25 * s.h[0]
+    steps = 8
     t0 = time.perf_counter()
-    for m in range(2):
+    for m in range(steps):
         H.step(st, m * dt, dt)
     sec = time.perf_counter() - t0
-    interior = 2 * (24 ** 3 + 2 * 32 ** 3)
+    interior = steps * (24 ** 3 + 2 * 32 ** 3)
     return {"value": interior / sec, "unit": "point-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"2 layer-0 steps of a 24^3 grid with one child over its central 16^3 cells (56^3 padded), "
-                      f"{sec:.1f} s; interior points of both layers"}
+            "sample": f"{steps} layer-0 steps of a 24^3 grid with one child over its central 16^3 cells (56^3 "
+                      f"padded), {sec:.1f} s; interior points of both layers"}
 
 
 def cpu_baseline_adjoint():
-    """The oracle's discrete adjoint (taped reverse mode through one RK4 step) on a 12^3 grid with
+    """The oracle's discrete adjoint (taped reverse mode through one RK4 step) on a 24^3 grid with
     the differentiated run's grid spacing and data, beside its forward step: the CPU cost ratio
-    (forward + adjoint) / forward, the unit of the adjoint leg."""
+    (forward + adjoint) / forward, the unit of the adjoint leg (24^3: about 10 s of serial work on
+    the GPU host)."""
     import numpy as np
     import oracle
-    n = 12
-    s = oracle.Setup(n=(n, n, n), L=(1.5, 1.5, 1.5))  # h = 12/96, as in the 96^3 run
+    n = 24
+    s = oracle.Setup(n=(n, n, n), L=(3.0, 3.0, 3.0))  # h = 12/96, as in the 96^3 run
     u = oracle.init_fields(s, oracle.Init(mu=0.55, sigma=1.2))
     lam = np.random.default_rng(5).standard_normal(u.shape)
     dt = 0.25 * s.h[0]
@@ -765,7 +767,7 @@ def cpu_baseline_adjoint():
     oracle.vjp(s, u, lam, "step", t=0.0, dt=dt)
     t_adj = time.perf_counter() - t0
     return {"value": (t_fwd + t_adj) / t_fwd, "unit": "x forward", "cores": 1, "kind": "oracle",
-            "sample": f"one RK4 step and its taped reverse-mode adjoint on a 12^3 grid (h = 1/8, mu = 0.55, "
+            "sample": f"one RK4 step and its taped reverse-mode adjoint on a 24^3 grid (h = 1/8, mu = 0.55, "
                       f"sigma = 1.2), serial: forward {t_fwd * 1e3:.1f} ms, adjoint {t_adj:.1f} s; "
                       f"{n ** 3 / t_adj:.1f} adjoint point-steps/s"}
 
