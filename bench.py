@@ -590,7 +590,9 @@ def cpu_baseline_c2():
 def adjoint_bench(a):
     from paper_2606_02053_amd.adjoint import RunConfig, central_lapse
     import paper_2606_02053_amd as P
-    cfg = RunConfig(n=96, L=12.0, nsteps=a.adjoint_steps, checkpoint_every=20)
+    numel = P.NFIELDS * 96 ** 3
+    keep_all = 4 * a.adjoint_steps * numel * 8 < 0.6 * torch.cuda.mem_get_info()[0]
+    cfg = RunConfig(n=96, L=12.0, nsteps=a.adjoint_steps, checkpoint_every=20, keep_all=keep_all)
     t64 = lambda x, g=False: torch.tensor(x, dtype=torch.float64, requires_grad=g)  # noqa: E731
     # plain forward run (same steps, no checkpoints)
     s = P.Solver(cfg.n, cfg.L, cfg.params)
@@ -625,7 +627,9 @@ def adjoint_bench(a):
            "rel_diff_vs_fd": None if a.no_fd else [abs(g[i] - fd[i]) / abs(fd[i]) for i in range(2)],
            "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"96^3 periodic, L = 12/H0, Gaussian zeta mu = 0.55 sigma = 1.2, {cfg.nsteps} RK4 "
-                                  "steps, CFL 0.25, checkpoint every 20, J = centre lapse at the final time"}}
+                                  "steps, CFL 0.25, J = centre lapse at the final time",
+                      "states": (f"every step's start and stage states kept ({4 * cfg.nsteps * numel * 8 / 1e9:.0f} GB)"
+                                 if keep_all else "checkpoint every 20 steps, segments recomputed")}}
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline_adjoint()
     return out

@@ -2,14 +2,22 @@
 
 J is the lapse at the box centre after `nsteps` RK4 steps from the initial
 data of a Gaussian curvature perturbation (amplitude mu, width sigma). The
-forward pass stores the state every `checkpoint_every` steps; the backward
-pass recomputes each segment from its checkpoint and applies the adjoint step
-backwards through it, starting from lambda = dJ/du(T) (a unit vector on the
-centre lapse), and finally contracts lambda_0 with the derivatives of the
-initial data in mu and sigma on the device (cosmos_adjoint_gradient). Where device memory allows
-(`keep_stages`), the recomputation also keeps each step's RK4 stage states
-(cosmos_rk4_step_stages) so that the adjoint step does not evaluate them again
-(cosmos_adjoint_step_stages); the result is the same bitwise.
+backward pass applies the adjoint step backwards through every step, starting
+from lambda = dJ/du(T) (a unit vector on the centre lapse), and finally
+contracts lambda_0 with the derivatives of the initial data in mu and sigma on
+the device (cosmos_adjoint_gradient). Each adjoint step needs the step's start
+state and its RK4 stage states (cosmos_adjoint_step_stages); where they come
+from is a memory trade:
+
+* `keep_all`: the forward pass keeps every step's start state and stage states
+  (cosmos_rk4_step_stages; 4 states per step), so the backward pass evaluates
+  no forward stage at all. At 96^3 and 200 steps that is 142 GB of device memory.
+* otherwise the forward pass stores the state every `checkpoint_every` steps and
+  the backward pass recomputes each segment from its checkpoint; where memory
+  allows (`keep_stages`) the recomputation keeps the segment's stage states,
+  else the adjoint step evaluates them itself (cosmos_adjoint_step).
+
+All three give the same gradient bitwise.
 """
 from __future__ import annotations
 
@@ -30,13 +38,20 @@ class RunConfig:
     cfl: float = 0.25
     params: C.cosmos_params = field(default_factory=C.make_params)
     init_kw: dict = field(default_factory=dict)  # extra cosmos_init fields (profile, center, ...)
-    # keep the stage states of a segment (3 states per step) for the reverse sweep:
-    # True / False, or None to decide by the free device memory
+    # keep every step's start and stage states from the forward pass: True / False, or None to
+    # decide by the free device memory (kept when they take under 60 % of it)
+    keep_all: bool | None = None
+    # with checkpoints: keep the stage states of a segment (3 states per step) for the reverse
+    # sweep: True / False, or None to decide by the free device memory
     keep_stages: bool | None = None
 
     @property
     def dt(self) -> float:
         return self.cfl * self.L / self.n
+
+
+def _free_bytes(dev) -> int:
+    return torch.cuda.mem_get_info(dev)[0]
 
 
 class CosmosRun(torch.autograd.Function):
@@ -45,15 +60,29 @@ class CosmosRun(torch.autograd.Function):
         s = Solver(cfg.n, cfg.L, cfg.params)
         s.init(mu=float(mu), sigma=float(sigma), **cfg.init_kw)
         dt = cfg.dt
-        ckpts = {}
-        for m in range(cfg.nsteps):
-            if m % cfg.checkpoint_every == 0:
-                ckpts[m] = s.u.clone()
-            C.cosmos_rk4_step(s.grid, s.params, m * dt, dt, s.u, s.ws)
+        numel = s.u.numel()
+        wanted = any(ctx.needs_input_grad[:2])
+        keep_all = cfg.keep_all
+        if keep_all is None:
+            keep_all = wanted and 4 * cfg.nsteps * numel * 8 < 0.6 * _free_bytes(s.u.device)
+        ckpts, traj = {}, None
+        if wanted and keep_all:
+            states = torch.empty((cfg.nsteps, numel), dtype=torch.float64, device=s.u.device)
+            stages = torch.empty((cfg.nsteps, 3 * numel), dtype=torch.float64, device=s.u.device)
+            for m in range(cfg.nsteps):
+                states[m].copy_(s.u.view(-1))
+                C.cosmos_rk4_step_stages(s.grid, s.params, m * dt, dt, s.u, stages[m], s.ws)
+            traj = (states, stages)
+        else:
+            for m in range(cfg.nsteps):
+                if wanted and m % cfg.checkpoint_every == 0:
+                    ckpts[m] = s.u.clone()
+                C.cosmos_rk4_step(s.grid, s.params, m * dt, dt, s.u, s.ws)
         c = cfg.n // 2
         J = s.u[17, c, c, c].clone()
         ctx.cfg = cfg
         ctx.ckpts = ckpts
+        ctx.traj = traj
         ctx.mu, ctx.sigma = float(mu), float(sigma)
         return J
 
@@ -68,30 +97,37 @@ class CosmosRun(torch.autograd.Function):
         lam[17, c, c, c] = gJ.to(dev, torch.float64)
         lam_next = torch.empty_like(lam)
         ws_adj = torch.empty(C.cosmos_adjoint_workspace_bytes(grid), dtype=torch.uint8, device=dev)
-        ws_fwd = torch.empty(C.cosmos_workspace_bytes(grid), dtype=torch.uint8, device=dev)
-        seg = cfg.checkpoint_every
-        keep = cfg.keep_stages
-        if keep is None:
-            keep = 3 * seg * lam.numel() * 8 < 0.5 * torch.cuda.mem_get_info(dev)[0]
-        stages = torch.empty((seg, 3 * lam.numel()), dtype=torch.float64, device=dev) if keep else None
-        for start in sorted(ctx.ckpts, reverse=True):
-            end = min(start + seg, cfg.nsteps)
-            states = [ctx.ckpts[start]]
-            u = ctx.ckpts[start].clone()
-            for m in range(start, end):  # recompute the segment's states (and stage states)
-                if keep:
-                    C.cosmos_rk4_step_stages(grid, params, m * dt, dt, u, stages[m - start], ws_fwd)
-                elif m < end - 1:
-                    C.cosmos_rk4_step(grid, params, m * dt, dt, u, ws_fwd)
-                if m < end - 1:
-                    states.append(u.clone())
-            for m in range(end - 1, start - 1, -1):
-                if keep:
-                    C.cosmos_adjoint_step_stages(grid, params, m * dt, dt, states[m - start], stages[m - start], lam,
-                                                 lam_next, ws_adj)
-                else:
-                    C.cosmos_adjoint_step(grid, params, m * dt, dt, states[m - start], lam, lam_next, ws_adj)
+        if ctx.traj is not None:
+            states, stages = ctx.traj
+            for m in range(cfg.nsteps - 1, -1, -1):
+                C.cosmos_adjoint_step_stages(grid, params, m * dt, dt, states[m], stages[m], lam, lam_next, ws_adj)
                 lam, lam_next = lam_next, lam
+            ctx.traj = None
+        else:
+            ws_fwd = torch.empty(C.cosmos_workspace_bytes(grid), dtype=torch.uint8, device=dev)
+            seg = cfg.checkpoint_every
+            keep = cfg.keep_stages
+            if keep is None:
+                keep = 3 * seg * lam.numel() * 8 < 0.5 * _free_bytes(dev)
+            stages = torch.empty((seg, 3 * lam.numel()), dtype=torch.float64, device=dev) if keep else None
+            for start in sorted(ctx.ckpts, reverse=True):
+                end = min(start + seg, cfg.nsteps)
+                states = [ctx.ckpts[start]]
+                u = ctx.ckpts[start].clone()
+                for m in range(start, end):  # recompute the segment's states (and stage states)
+                    if keep:
+                        C.cosmos_rk4_step_stages(grid, params, m * dt, dt, u, stages[m - start], ws_fwd)
+                    elif m < end - 1:
+                        C.cosmos_rk4_step(grid, params, m * dt, dt, u, ws_fwd)
+                    if m < end - 1:
+                        states.append(u.clone())
+                for m in range(end - 1, start - 1, -1):
+                    if keep:
+                        C.cosmos_adjoint_step_stages(grid, params, m * dt, dt, states[m - start], stages[m - start],
+                                                     lam, lam_next, ws_adj)
+                    else:
+                        C.cosmos_adjoint_step(grid, params, m * dt, dt, states[m - start], lam, lam_next, ws_adj)
+                    lam, lam_next = lam_next, lam
         init = C.make_init(mu=ctx.mu, sigma=ctx.sigma, **cfg.init_kw)
         grad = torch.empty(2, dtype=torch.float64, device=dev)
         C.cosmos_adjoint_gradient(grid, params, init, lam, grad, ws_adj)

@@ -153,16 +153,19 @@ def test_stage_keeping_step_and_adjoint_bitwise(P, orc):
 
 
 def test_gradient_with_and_without_kept_stages(P):
+    """The three sources of the adjoint steps' states (the whole forward trajectory kept, segments
+    recomputed keeping their stage states, segments recomputed without them) give the same J and
+    gradient bitwise."""
     from paper_2606_02053_amd.adjoint import RunConfig, central_lapse
     g = []
-    for keep in (True, False):
-        cfg = RunConfig(n=16, L=6.0, nsteps=9, checkpoint_every=4, keep_stages=keep)
+    for keep_all, keep in ((True, None), (False, True), (False, False)):
+        cfg = RunConfig(n=16, L=6.0, nsteps=9, checkpoint_every=4, keep_all=keep_all, keep_stages=keep)
         mu = torch.tensor(0.55, dtype=torch.float64, requires_grad=True)
         sigma = torch.tensor(1.2, dtype=torch.float64, requires_grad=True)
         J = central_lapse(mu, sigma, cfg)
         J.backward()
         g.append((J.item(), mu.grad.item(), sigma.grad.item()))
-    assert g[0] == g[1]
+    assert g[0] == g[1] == g[2]
 
 
 @pytest.mark.parametrize("ini", [dict(mu=0.45, sigma=1.1, center=(0.1, -0.2, 0.05), noise_amp=1e-3, seed=7),
