@@ -25,15 +25,20 @@ def rel(a, b, floor=1e-6):
     return (np.abs(a - b).max(axis=1) / np.maximum(np.abs(b).max(axis=1), floor)).max()
 
 
-@pytest.mark.parametrize("theta", [0.0, 0.5, 0.3])
-@pytest.mark.parametrize("buffer_only", [False, True])
-def test_prolong_matches_oracle(P, theta, buffer_only):
+SMALL = ((20, 16, 24), (5.0, 4.0, 6.0), fmr.Box(origin=(15, -3, 5), m=(6, 5, 8)))  # wraps in x and y
+# a box wide enough that a buffer-only refill skips the intermediate values no shell point reads
+LARGE = ((40, 36, 44), (10.0, 9.0, 11.0), fmr.Box(origin=(3, 30, -4), m=(22, 18, 26)))  # wraps in y and z
+
+
+@pytest.mark.parametrize("case,theta,buffer_only",
+                         [("small", th, bo) for th in (0.0, 0.5, 0.3) for bo in (False, True)] +
+                         [("large", 0.5, True), ("large", 0.3, False)])
+def test_prolong_matches_oracle(P, case, theta, buffer_only):
     """Interpolation from a parent step's start, its continuous extension at the midpoint (the
-    refill the driver does) and at another theta, whole child or buffer only, on a box that wraps
+    refill the driver does) and at another theta, whole child or buffer only, on boxes that wrap
     around the periodic parent; the oracle forms the slopes from the stage states and takes
     u0 + dt sum_i b_i k_i."""
-    n, L = (20, 16, 24), (5.0, 4.0, 6.0)
-    box = fmr.Box(origin=(15, -3, 5), m=(6, 5, 8))  # wraps in x and y
+    n, L, box = SMALL if case == "small" else LARGE
     u0 = fuzz_state(n, seed=71)
     stages = np.stack([u0 + 0.05 * fuzz_direction(n, seed=72 + q) for q in range(3)])
     u1 = u0 + 0.05 * fuzz_direction(n, seed=75)
