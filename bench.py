@@ -2,8 +2,10 @@
 fluid hot path on one MI355X, on the 256^3 periodic configuration (box 16/H0,
 Gaussian curvature perturbation mu = 0.6, sigma = 2.0, CFL 0.25).
 
-One step = one classic RK4 step = 4 stages, each a pointwise flux pre-pass
-(k_fluid_flux) plus the stage kernel (k_bssn_stage_lds), inputs resident in HBM.
+One step = one classic RK4 step = 4 stages of the stage kernel (k_bssn_stage_lds), inputs
+resident in HBM; the point fluxes of the step's first stage come from a pre-pass
+(k_fluid_flux), those of the later stages from the previous stage's kernel, which writes them
+beside its new state.
 Prints one JSON line with the roofline of a stage (algorithmic bytes per stage /
 average stage time, measured with HIP events on the launch stream around the
 timed steps), the CPU oracle timed on a bounded sample of the same workload, and
@@ -903,8 +905,11 @@ def main():
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "traffic_unit": "bytes per launch", "algorithmic_bytes_per_launch": round(bytes_launch),
-            "kernel": (f"k_bssn_stage_lds<{tile[0]},{tile[1]},{tile[2]}>" if kv == 0 else "k_bssn_stage") +
-                      " + k_fluid_flux pre-pass (one RK4 stage)",
+            "kernel": (f"k_bssn_stage_lds<{tile[0]},{tile[1]},{tile[2]}> (one RK4 stage; the point fluxes of "
+                       "stages 2-4 written by the stage before, a k_fluid_flux pre-pass for stage 1)"
+                       if kv == 0 and tile == (16, 4, 4) else
+                       (f"k_bssn_stage_lds<{tile[0]},{tile[1]},{tile[2]}>" if kv == 0 else "k_bssn_stage") +
+                       " + k_fluid_flux pre-pass (one RK4 stage)"),
             "avg_launch_ms": round(launch_s * 1e3, 4),
             "fp64_tflops_algorithmic": round(fl * npts * a.steps / (ms / 1e3) / 1e12, 2),
             "fp64_frac": round(fl * npts * a.steps / (ms / 1e3) / 1e12 / FP64_PEAK_TFLOPS, 4)}

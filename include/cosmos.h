@@ -126,10 +126,11 @@ typedef struct {
 } cosmos_init;
 
 /* Bytes of device workspace needed by cosmos_rhs / cosmos_rk4_step / cosmos_constraints on this
- * grid: the status counters, the reduction partials, 3 state-sized RK4 buffers and 12 * N3
- * doubles for the fluid fluxes that every stage forms in a pre-pass (the point fluxes; with
- * fluid_scheme 1 the first 4 * N3 hold the Kurganov-Tadmor flux divergence). Returns 0 for an
- * invalid grid. */
+ * grid: the status counters, the reduction partials, 3 state-sized RK4 buffers and two arrays of
+ * 12 * N3 doubles for the fluid fluxes of a stage state (the point fluxes; with fluid_scheme 1
+ * the first 4 * N3 hold the Kurganov-Tadmor flux divergence). A stage forms them in a pre-pass,
+ * except where the previous stage's kernel wrote them into the other array beside its new state
+ * (the LDS-staged 16x4x4 kernel of the centred scheme does). Returns 0 for an invalid grid. */
 size_t cosmos_workspace_bytes(const cosmos_grid* grid);
 
 /* Zero the status counters held in the workspace (asynchronous). */

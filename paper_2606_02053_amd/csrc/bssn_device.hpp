@@ -345,27 +345,36 @@ __device__ __forceinline__ bool recover(double w, double chi, const double gi[6]
 // Formed once per point per stage (a pointwise pre-pass), so the stage kernel
 // takes the divergence from 4 loads per flux component instead of recovering
 // the primitives at all 12 axis neighbours.
-__device__ __forceinline__ void fluid_flux_point(const double* U, size_t fs, int c, double w, double* F) {
-  const double chi = ldq(U + F_CHI * fs, c);
-  double g[6], gi[6], St[3];
-#pragma unroll
-  for (int s = 0; s < 6; ++s) g[s] = ldq(U + (F_GT + s) * fs, c);
-#pragma unroll
-  for (int i = 0; i < 3; ++i) St[i] = ldq(U + (F_ST + i) * fs, c);
+// The same from the 15 values it depends on (chi, gt_ij, alpha, beta^a, Et, St_i), which the stage
+// kernel holds at the end of a point's evaluation for the state it has just written.
+__device__ __forceinline__ void fluid_flux_values(double chi, const double g[6], double alpha, const double beta[3],
+                                                  double Et, const double St[3], double w, double* F, size_t fs,
+                                                  int c) {
+  double gi[6];
   inv_sym(g, gi);
   Fluid fl;
-  recover(w, chi, gi, ldq(U + F_ET * fs, c), St, fl);
-  const double alpha = ldq(U + F_ALP * fs, c);
+  recover(w, chi, gi, Et, St, fl);
   const double im32 = 1.0 / (chi * sqrt(chi));
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const double ba = ldq(U + (F_BET + a) * fs, c);
+    const double ba = beta[a];
     stq(F + (4 * a) * fs, c, im32 * (alpha * fl.Sup[a] - ba * fl.E));
     const double t = alpha * fl.Sup[a] * fl.invX;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
       stq(F + (4 * a + 1 + i) * fs, c, im32 * ((t * fl.S[i] + (i == a ? alpha * fl.P : 0.0)) - ba * fl.S[i]));
   }
+}
+
+__device__ __forceinline__ void fluid_flux_point(const double* U, size_t fs, int c, double w, double* F) {
+  double g[6], St[3], beta[3];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) g[s] = ldq(U + (F_GT + s) * fs, c);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) St[i] = ldq(U + (F_ST + i) * fs, c);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) beta[a] = ldq(U + (F_BET + a) * fs, c);
+  fluid_flux_values(ldq(U + F_CHI * fs, c), g, ldq(U + F_ALP * fs, c), beta, ldq(U + F_ET * fs, c), St, w, F, fs, c);
 }
 
 // Divergence of the fluxes at point c, div[q] = sum_a D1_a F^a_q (4th-order centred),

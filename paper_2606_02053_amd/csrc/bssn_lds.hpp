@@ -215,6 +215,9 @@ struct DBrick {
 };
 constexpr int kRing = 5;      // LDS halo buffers of the direct-load ring (25 phases = 5 rounds of the ring)
 constexpr int kDmaAhead = 4;  // fields whose loads are in flight ahead of the one being processed
+// With the scalar field, its 10 source values at the point are loaded in phase kSrcPhase (the
+// second connection-function phase), three phases before the first use.
+constexpr int kSrcPhase = 10, kSrcLoads = 10;
 static_assert(NF % kRing == 0 && kDmaAhead == kRing - 1, "ring slot = phase mod kRing, across bricks");
 
 // Wait until at most n vector-memory operations of this wave are outstanding (expcnt and
@@ -229,6 +232,7 @@ __device__ __forceinline__ void wait_vm(int n) {
     case 12: __builtin_amdgcn_s_waitcnt(0x0F7C); break;
     case 15: __builtin_amdgcn_s_waitcnt(0x0F7F); break;
     case 18: __builtin_amdgcn_s_waitcnt(0x4F72); break;
+    case 25: __builtin_amdgcn_s_waitcnt(0x4F79); break;
     default: __builtin_amdgcn_s_waitcnt(0x0F70); break;  // any other count: wait for everything
   }
 }
@@ -461,7 +465,10 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
       // each, except past the brick's last field when there is no next brick
       const int v = nx.valid ? 1 : 0;
       const int newer = phase <= NF - 1 - kDmaAhead ? 3 : (phase == NF - kDmaAhead ? 2 + v : (phase == NF - 3 ? 1 + 2 * v : 3 * v));
-      wait_vm(newer * B::NR);
+      // the scalar field's source loads, issued in phase kSrcPhase after that phase's halo
+      // loads, are newer than the field awaited at the end of the phases kSrcPhase .. kSrcPhase + 2
+      const int extra = (SC != 0 && phase >= kSrcPhase && phase < kSrcPhase + 3) ? kSrcLoads : 0;
+      wait_vm(newer * B::NR + extra);
     } else {
       if (phase + 1 < NF) hc.commit_and_rotate((phase & 1) ? buf0 : buf1);
     }
@@ -549,9 +556,19 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
   }
 
   // ---- connection functions
+  double xs[kSrcLoads];  // the scalar field's sources at this point: E + S, S_j, S_ij
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     prefetch();
+    if constexpr (SC != 0) {
+      if (9 + k == kSrcPhase) {  // every thread of the wave issues them (inactive ones hold a valid point)
+        xs[0] = xsrc(SRC_EPS);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) xs[1 + j] = xsrc(SRC_S + j);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) xs[4 + q] = xsrc(SRC_SIJ + q);
+      }
+    }
     if (active) {
       FieldDerivs d;
       lds_derivs<B, false, true>(cur(), P, beta, d);
@@ -623,7 +640,7 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
       double Sij = R[R3_S + SI(s)] * R[R3_S + SJ(s)] * ix + pr * gt[s] * ichi;
-      if constexpr (SC != 0) Sij += xsrc(SRC_SIJ + s);
+      if constexpr (SC != 0) Sij += xs[4 + s];
       R[R3_RX + s] = -DDa[s] + alpha * (R[R3_RX + s] - 8.0 * PI_D * Sij);
     }
 #pragma unroll
@@ -660,7 +677,7 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
     const double AA = contract_sym(At, Aup);
     const double Str = (Sup[0] * R[R3_S + 0] + Sup[1] * R[R3_S + 1] + Sup[2] * R[R3_S + 2]) * R[R3_IX] + 3.0 * R[R3_P];
     double EpS = R[R3_E] + Str;
-    if constexpr (SC != 0) EpS += xsrc(SRC_EPS);
+    if constexpr (SC != 0) EpS += xs[0];
     sink.put(F_K, d.advko + (-R[R3_D2A] + alpha * (AA + K * K * (1.0 / 3.0)) + 4.0 * PI_D * alpha * EpS), ep[0][0]);
     // Gt^i: every remaining term
     const double divb = R[R3_DB + 0] + R[R3_DB + 4] + R[R3_DB + 8];
@@ -688,7 +705,7 @@ __device__ __forceinline__ void bssn_rhs_lds(const double* U, const double* F, s
       if constexpr (SC != 0) {
         double Sj[3];
 #pragma unroll
-        for (int j = 0; j < 3; ++j) Sj[j] = R[R3_S + j] + xsrc(SRC_S + j);
+        for (int j = 0; j < 3; ++j) Sj[j] = R[R3_S + j] + xs[1 + j];
         r -= 16.0 * PI_D * alpha * (gi[S(i, 0)] * Sj[0] + gi[S(i, 1)] * Sj[1] + gi[S(i, 2)] * Sj[2]);
       } else {
         r -= 16.0 * PI_D * alpha * (gi[S(i, 0)] * R[R3_S + 0] + gi[S(i, 1)] * R[R3_S + 1] + gi[S(i, 2)] * R[R3_S + 2]);

@@ -52,7 +52,7 @@ constexpr int kBlock = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t status, partials, acc, A, B, F, total;
+  size_t status, partials, acc, A, B, F, F2, total;
 };
 constexpr int kFluxFields = 12;  // F^a_q, a = axis, q = (Et, St_x, St_y, St_z)
 
@@ -77,7 +77,8 @@ Layout layout(const cosmos_grid* g) {
   L.A = align_up(L.acc + state);
   L.B = align_up(L.A + state);
   L.F = align_up(L.B + state);
-  L.total = align_up(L.F + (size_t)kFluxFields * npts(g) * sizeof(double));
+  L.F2 = align_up(L.F + (size_t)kFluxFields * npts(g) * sizeof(double));  // the next stage's fluxes
+  L.total = align_up(L.F2 + (size_t)kFluxFields * npts(g) * sizeof(double));
   return L;
 }
 
@@ -168,6 +169,26 @@ DevParams dev_params(const cosmos_grid* g, const cosmos_params* p) {
 #include "stage.hip.inc"
 
 namespace {
+// The two flux arrays of an RK4 step: a stage reads `cur`; where its kernel also writes the next
+// stage's fluxes (into `nxt`), the two swap and the next stage skips its pre-pass.
+struct FluxPair {
+  double* cur;
+  double* nxt;
+  bool ready = false;
+  int stage(const cosmos_params* p, const Tile& T, hipStream_t s, const double* U, const double* un, double* acc,
+            double* out, size_t fs, const DevParams& P, double t, double ca, double cn, int mode,
+            unsigned long long* status) {
+    bool wrote = false;
+    const int rc = launch_stage(p, T, s, U, cur, un, acc, out, fs, P, t, ca, cn, mode, status,
+                                (mode == 1 || mode == 2) ? nxt : nullptr, ready, &wrote);
+    if (wrote) std::swap(cur, nxt);
+    ready = wrote;
+    return rc;
+  }
+};
+}  // namespace
+
+namespace {
 // One RK4 step in place on u; the stage states go to U2, U3, U4 (U4 may be U2: it is
 // written after U2 has been read for the last time).
 int rk4_step(const cosmos_grid* grid, const cosmos_params* params, double t, double dt, double* u, double* U2,
@@ -183,10 +204,11 @@ int rk4_step(const cosmos_grid* grid, const cosmos_params* params, double t, dou
   if ((rc = make_tile(grid, params, T))) return rc;
   const size_t fs = npts(grid);
   hipStream_t s = (hipStream_t)stream;
-  if ((rc = launch_stage(params, T, s, u, F, u, acc, U2, fs, P, t, dt / 6.0, dt / 2.0, 1, status))) return rc;
-  launch_stage(params, T, s, U2, F, u, acc, U3, fs, P, t + dt / 2.0, dt / 3.0, dt / 2.0, 2, status);
-  launch_stage(params, T, s, U3, F, u, acc, U4, fs, P, t + dt / 2.0, dt / 3.0, dt, 2, status);
-  launch_stage(params, T, s, U4, F, nullptr, acc, u, fs, P, t + dt, dt / 6.0, 0.0, 3, status);
+  FluxPair fx{F, (double*)(w + L.F2)};
+  if ((rc = fx.stage(params, T, s, u, u, acc, U2, fs, P, t, dt / 6.0, dt / 2.0, 1, status))) return rc;
+  fx.stage(params, T, s, U2, u, acc, U3, fs, P, t + dt / 2.0, dt / 3.0, dt / 2.0, 2, status);
+  fx.stage(params, T, s, U3, u, acc, U4, fs, P, t + dt / 2.0, dt / 3.0, dt, 2, status);
+  fx.stage(params, T, s, U4, nullptr, acc, u, fs, P, t + dt, dt / 6.0, 0.0, 3, status);
   HIP_TRY(hipGetLastError());
   return COSMOS_OK;
 }
