@@ -68,11 +68,12 @@ FP64_PEAK_TFLOPS = 78.6
 #  stage 4 reads U4, acc and writes u): 16 * 25 * 8
 BYTES_PER_POINT_STEP = 3200.0
 LAUNCHES_PER_STEP = 4
-# with the scalar field, per point and RK4 step: the plain 3200 B; k_scalar_stage reads the 15
-# geometry fields and (phi, Pi) in every stage (136 B), acc and u_n of (phi, Pi) as its mode needs
-# (0 / 32 / 32 / 16 B), and writes the 11 source arrays and the field's acc and next state
-# (120 / 120 / 120 / 104 B): 1088 B; the stage kernel reads 10 source arrays per stage (320 B)
-SCALAR_BYTES_PER_POINT_STEP = 3200.0 + 1088.0 + 320.0
+# with the scalar field, per point and RK4 step: the plain 3200 B; the scalar stage reads 12
+# geometry fields (chi, gt_ij, K, alpha, beta^i) and (phi, Pi) in every stage (112 B), acc and u_n
+# of (phi, Pi) as its mode needs (0 / 32 / 32 / 16 B), and writes the 11 source arrays and the
+# field's acc and next state (120 / 120 / 120 / 104 B): 992 B; the stage kernel reads 10 source
+# arrays per stage (320 B)
+SCALAR_BYTES_PER_POINT_STEP = 3200.0 + 992.0 + 320.0
 
 
 def step_roofline(point_updates_per_s, bytes_per_point_step, kernels):
@@ -458,9 +459,9 @@ def kt_bench(a, kv=0, tile=(16, 4, 4), order=2):
 def scalar_bench(a, kv=0, tile=(16, 4, 4), order=2):
     """The headline workload with the massless scalar field (iso-curvature mode Upsilon =
     0.1 x Gaussian of width 2 on the same zeta): RK4 steps per second on 256^3, each stage
-    k_scalar_stage (the field's stage update and its 11 source arrays) + the flux pre-pass +
-    the stage kernel with the sources; timed like the headline, against the plain run on the
-    same configuration."""
+    k_scalar_stage_lds (the field's stage update and its 11 source arrays) + the stage kernel
+    with the sources (the flux pre-pass before the first stage); timed like the headline,
+    against the plain run on the same configuration."""
     import paper_2606_02053_amd as P
     from paper_2606_02053_amd import autotune
     n, L = a.n, 16.0
@@ -493,8 +494,8 @@ def scalar_bench(a, kv=0, tile=(16, 4, 4), order=2):
             "value": n ** 3 / (ms[True] / 1e3), "unit": "point-updates/s", "ms_per_step": ms[True],
             "plain_ms_per_step": ms[False], "cost_vs_plain": ms[True] / ms[False], "steps": a.steps,
             "roofline": step_roofline(n ** 3 / (ms[True] / 1e3), SCALAR_BYTES_PER_POINT_STEP,
-                                      "k_scalar_stage + flux pre-pass + stage kernel with the sources, whole RK4 "
-                                      "steps"),
+                                      "k_scalar_stage_lds + stage kernel with the sources (+ one flux pre-pass), "
+                                      "whole RK4 steps"),
             **({} if a.no_cpu else {"cpu_baseline": cpu_baseline(5, "scalar")}),
             "higher_is_better": True, "dtype": "f64", "data": "synthetic",
             "config": {"workload": f"as the headline ({n}^3, L = 16/H0, zeta mu = 0.6, sigma = 2.0, CFL 0.25) with "

@@ -21,6 +21,7 @@
 #include "constraints_lds.hpp"
 #include "kt_device.hpp"
 #include "scalar_device.hpp"
+#include "scalar_lds.hpp"
 #include "adjoint_point.hpp"
 
 using namespace cosmos;

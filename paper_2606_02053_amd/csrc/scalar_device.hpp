@@ -17,20 +17,40 @@
 
 namespace cosmos {
 
-// One RK4 stage of the scalar field at grid point (i, j, k) from the stage state
-// (U, Sc), with direct loads; also writes the geometry's source arrays `src`
-// (kScalarSrc x fs doubles, layout of DevParams::xsrc) for the stage kernel that
-// follows. MODE as the stage kernel's epilogue: 0 sout = f; 1 sacc = Sc + ca f,
-// sout = Sc + cn f; 2 sacc += ca f, sout = sun + cn f; 3 sout = sacc + ca f.
-template <int MODE>
-__device__ __forceinline__ void scalar_point(const double* __restrict__ U, const double* __restrict__ Sc,
-                                             double* __restrict__ src, const double* __restrict__ sun,
-                                             double* __restrict__ sacc, double* __restrict__ sout, size_t fs,
-                                             const DevParams& P, int i, int j, int k, double ca, double cn) {
-  const size_t p = (size_t)i + (size_t)P.n[0] * ((size_t)j + (size_t)P.n[1] * k);
-  Nbr nb;
-  make_nbr(nb, i, j, k, P.n);
-  const int c = (int)p;
+// Derivative source of scalar_stage_point reading every stencil tap from global memory. Field q
+// of the fixed request order: gt_ij (q = 0..5), chi, alpha, phi, Pi.
+struct ScDirect {
+  const double* U;
+  const double* Sc;
+  size_t fs;
+  const Nbr& nb;
+  const DevParams& P;
+  __device__ __forceinline__ void pin(double& x) { asm volatile("" : "+v"(x)); }
+  template <bool SECOND, bool ADV, bool KO>
+  __device__ __forceinline__ void get(int q, const double beta[3], FieldDerivs& d) {
+    // a compiler-level fence per field: the stencil loads of later fields stay after it
+    asm volatile("" ::: "memory");
+    const double* F = q < 6 ? U + (size_t)(F_GT + q) * fs
+                            : (q == 6 ? U + (size_t)F_CHI * fs : (q == 7 ? U + (size_t)F_ALP * fs : Sc + (size_t)(q - 8) * fs));
+    field_derivs<SECOND, ADV, KO>(F, nb, P, beta, d);
+  }
+};
+
+// One RK4 stage of the scalar field at the grid point with linear index c from the stage state
+// (U, Sc); also writes the geometry's source arrays `src` (kScalarSrc x fs doubles, layout of
+// DevParams::xsrc) for the stage kernel that follows. MODE as the stage kernel's epilogue:
+// 0 sout = f; 1 sacc = Sc + ca f, sout = Sc + cn f; 2 sacc += ca f, sout = sun + cn f;
+// 3 sout = sacc + ca f. Der supplies the fields' derivatives in the order gt_ij (6, first), chi
+// and alpha (first), phi (second, with shift advection and dissipation), Pi (first, with
+// advection and dissipation); der.pin(x) keeps a running value in a register where it is final
+// for the current field (it changes no value). Nothing is stored unless `active`.
+template <int MODE, class Der>
+__device__ __forceinline__ void scalar_stage_point(const double* __restrict__ U, const double* __restrict__ Sc,
+                                                   double* __restrict__ src, const double* __restrict__ sun,
+                                                   double* __restrict__ sacc, double* __restrict__ sout, size_t fs,
+                                                   const DevParams& P, int c, bool active, Der& der, double ca,
+                                                   double cn) {
+  const size_t p = (size_t)c;
   const double chi = ldq(U + F_CHI * fs, c), K = ldq(U + F_K * fs, c), alpha = ldq(U + F_ALP * fs, c);
   double gt[6], gi[6], beta[3];
 #pragma unroll
@@ -50,7 +70,7 @@ __device__ __forceinline__ void scalar_point(const double* __restrict__ U, const
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
       FieldDerivs d;
-      field_derivs<false, false, false>(U + (F_GT + q) * fs, nb, P, nob, d);
+      der.template get<false, false, false>(q, nob, d);
       const int a = SI(q), b = SJ(q);
       const double w = (a == b) ? 1.0 : 2.0;
 #pragma unroll
@@ -58,6 +78,11 @@ __device__ __forceinline__ void scalar_point(const double* __restrict__ U, const
         A[a] += gi[S(cc, b)] * d.d1[cc];
         if (a != b) A[b] += gi[S(cc, a)] * d.d1[cc];
         B[cc] += w * gi[q] * d.d1[cc];
+      }
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) {
+        der.pin(A[cc]);
+        der.pin(B[cc]);
       }
     }
 #pragma unroll
@@ -68,17 +93,21 @@ __device__ __forceinline__ void scalar_point(const double* __restrict__ U, const
   double dchi[3], dal[3];
   {
     FieldDerivs d;
-    field_derivs<false, false, false>(U + F_CHI * fs, nb, P, nob, d);
+    der.template get<false, false, false>(6, nob, d);
 #pragma unroll
     for (int a = 0; a < 3; ++a) dchi[a] = d.d1[a];
-    field_derivs<false, false, false>(U + F_ALP * fs, nb, P, nob, d);
+    der.template get<false, false, false>(7, nob, d);
 #pragma unroll
     for (int a = 0; a < 3; ++a) dal[a] = d.d1[a];
   }
   FieldDerivs dphi;
-  field_derivs<true, true, true>(Sc, nb, P, beta, dphi);  // d1, d2, upwind advection + KO of phi
-  double d1pi[3];
-  const double advko_pi = field_advko<true>(Sc + fs, nb, P, beta, d1pi);
+  der.template get<true, true, true>(8, beta, dphi);  // d1, d2, upwind advection + KO of phi
+  double advko_pi;
+  {
+    FieldDerivs d;
+    der.template get<false, true, true>(9, beta, d);  // upwind advection + KO of Pi
+    advko_pi = d.advko;
+  }
   const double Pi = ldq(Sc + fs, c);
 
   // sources of the geometry
@@ -89,13 +118,15 @@ __device__ __forceinline__ void scalar_point(const double* __restrict__ U, const
   const double P2 = Pi * Pi;
   const double E = 0.5 * (P2 + g2);
   const double Str = 1.5 * P2 - 0.5 * g2;
-  stq(src + SRC_EPS * fs, c, E + Str);
-  stq(src + SRC_E * fs, c, E);
-#pragma unroll
-  for (int a = 0; a < 3; ++a) stq(src + (SRC_S + a) * fs, c, -Pi * dphi.d1[a]);
   const double ichi = 1.0 / chi;
+  if (active) {
+    stq(src + SRC_EPS * fs, c, E + Str);
+    stq(src + SRC_E * fs, c, E);
 #pragma unroll
-  for (int s = 0; s < 6; ++s) stq(src + (SRC_SIJ + s) * fs, c, dd[s] - 0.5 * (gt[s] * ichi) * (g2 - P2));
+    for (int a = 0; a < 3; ++a) stq(src + (SRC_S + a) * fs, c, -Pi * dphi.d1[a]);
+#pragma unroll
+    for (int s = 0; s < 6; ++s) stq(src + (SRC_SIJ + s) * fs, c, dd[s] - 0.5 * (gt[s] * ichi) * (g2 - P2));
+  }
 
   // right-hand side of (phi, Pi)
   double lap = contract_sym(gi, dphi.d2);
@@ -109,6 +140,7 @@ __device__ __forceinline__ void scalar_point(const double* __restrict__ U, const
   for (int a = 0; a < 3; ++a)
     dad += dal[a] * (gi[S(a, 0)] * dphi.d1[0] + gi[S(a, 1)] * dphi.d1[1] + gi[S(a, 2)] * dphi.d1[2]);
   const double r[2] = {alpha * Pi + dphi.advko, ((alpha * K * Pi + alpha * chi * lap) + chi * dad) + advko_pi};
+  if (!active) return;
 #pragma unroll
   for (int f = 0; f < 2; ++f) {
     const size_t q = (size_t)f * fs + p;
@@ -125,6 +157,20 @@ __device__ __forceinline__ void scalar_point(const double* __restrict__ U, const
       sout[q] = sacc[q] + ca * r[f];
     }
   }
+}
+
+// The same at grid point (i, j, k) with direct loads (the batched form and grids the LDS-staged
+// kernel does not take).
+template <int MODE>
+__device__ __forceinline__ void scalar_point(const double* __restrict__ U, const double* __restrict__ Sc,
+                                             double* __restrict__ src, const double* __restrict__ sun,
+                                             double* __restrict__ sacc, double* __restrict__ sout, size_t fs,
+                                             const DevParams& P, int i, int j, int k, double ca, double cn) {
+  const int c = i + P.n[0] * (j + P.n[1] * k);
+  Nbr nb;
+  make_nbr(nb, i, j, k, P.n);
+  ScDirect der{U, Sc, fs, nb, P};
+  scalar_stage_point<MODE>(U, Sc, src, sun, sacc, sout, fs, P, c, true, der, ca, cn);
 }
 
 // The scalar stage of one grid: one thread per point of a 16x4x4 brick (bricks in XCD

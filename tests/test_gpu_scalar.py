@@ -45,7 +45,8 @@ def test_scalar_init_parity(P, orc, profile):
 
 
 @pytest.mark.parametrize("variant,scheme", [(0, 0), (1, 0), (0, 1), (1, 1)])
-@pytest.mark.parametrize("n,L", [((20, 12, 10), (4.0, 2.5, 2.0)), ((32, 32, 32), (10.0, 10.0, 10.0))])
+@pytest.mark.parametrize("n,L", [((20, 12, 10), (4.0, 2.5, 2.0)), ((32, 32, 32), (10.0, 10.0, 10.0)),
+                                 ((15, 12, 10), (3.0, 2.5, 2.0))])  # odd n0: the direct scalar kernel
 def test_scalar_rhs(P, orc, n, L, variant, scheme):
     s, sol = mk(P, orc, n, L, fluid_scheme=scheme)
     sol.params.variant = variant
@@ -57,6 +58,30 @@ def test_scalar_rhs(P, orc, n, L, variant, scheme):
     assert e < 1e-11, per
     e2, per2 = err2(ds.cpu().numpy(), rs)
     assert e2 < 1e-11, per2
+
+
+def test_scalar_lds_kernel_equals_direct_bitwise(P, orc):
+    """The scalar stage on state arrays that are 8- but not 16-byte aligned runs the direct
+    kernel (no aligned pairs for the LDS-direct loads); both kernels evaluate the same point
+    routine, so the field's right-hand side and the sources it hands the geometry agree bitwise
+    (the geometry's own right-hand side then comes from the direct stage kernel: equal to
+    round-off)."""
+    n, L = (20, 12, 18), (4.0, 2.5, 3.5)
+    s, sol = mk(P, orc, n, L)
+    u, sc = fuzz_state(n, seed=43), fuzz_scalar(n, seed=44)
+    sol.set_state(to_dev(u), s=to_dev(sc))
+    du0, ds0 = sol.rhs(t=0.2)
+    N = int(np.prod(n))
+    ub = torch.empty(25 * N + 1, dtype=torch.float64, device="cuda")
+    sb = torch.empty(2 * N + 1, dtype=torch.float64, device="cuda")
+    um, sm = ub[1:], sb[1:]  # 8-byte aligned views, 16-byte misaligned
+    assert um.data_ptr() % 16 == 8 and sm.data_ptr() % 16 == 8
+    um.copy_(sol.u.reshape(-1))
+    sm.copy_(sol.s.reshape(-1))
+    du1, ds1 = torch.empty_like(um), torch.empty_like(sm)
+    P.cosmos_rhs_scalar(sol.grid, sol.params, 0.2, um, sm, du1, ds1, sol.ws, sol.sws)
+    assert torch.equal(ds1, ds0.reshape(-1))
+    assert err_fields(du1.reshape(25, *du0.shape[1:]).cpu().numpy(), du0.cpu().numpy())[0] < 1e-13
 
 
 def test_zero_scalar_field_equals_plain_path(P, orc):
