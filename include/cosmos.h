@@ -219,6 +219,15 @@ int cosmos_constraints_scalar(const cosmos_grid* grid, const cosmos_params* para
 int cosmos_rk4_step(const cosmos_grid* grid, const cosmos_params* params, double t, double dt,
                     double* u, void* ws, void* stream);
 
+/* nsteps (>= 0) RK4 steps of size dt from time t, in place on u: the same u bitwise as nsteps calls
+ * of cosmos_rk4_step at t, t + dt, t + dt + dt, ... (the time advanced by repeated addition).
+ * Within the call the last stage of a step also writes the fluid fluxes of the new u for the next
+ * step (the LDS-staged 16x4x4 kernel of the centred scheme; others run the pre-pass), which a
+ * step of its own cannot do: its caller may change u before the next call. Errors as
+ * cosmos_rk4_step, and COSMOS_EINVAL for nsteps < 0. */
+int cosmos_rk4_steps(const cosmos_grid* grid, const cosmos_params* params, double t, double dt, int32_t nsteps,
+                     double* u, void* ws, void* stream);
+
 /* One RK4 step as cosmos_rk4_step (bitwise the same u), keeping the stage states for a reverse
  * sweep: stages (device, caller-owned, 3 * 25 * N3 doubles, must not overlap u or ws) receives
  * U2, U3, U4 in that order, each in the state layout, where U_{s+1} = u_n + c_s dt k_s

@@ -171,17 +171,20 @@ DevParams dev_params(const cosmos_grid* g, const cosmos_params* p) {
 
 namespace {
 // The two flux arrays of an RK4 step: a stage reads `cur`; where its kernel also writes the next
-// stage's fluxes (into `nxt`), the two swap and the next stage skips its pre-pass.
+// stage's fluxes (into `nxt`), the two swap and the next stage skips its pre-pass. The last stage
+// of a step writes them only when `chain` is set: for the next step of the same call, whose u
+// nobody else can have changed in between.
 struct FluxPair {
   double* cur;
   double* nxt;
   bool ready = false;
+  bool chain = false;
   int stage(const cosmos_params* p, const Tile& T, hipStream_t s, const double* U, const double* un, double* acc,
             double* out, size_t fs, const DevParams& P, double t, double ca, double cn, int mode,
             unsigned long long* status) {
     bool wrote = false;
     const int rc = launch_stage(p, T, s, U, cur, un, acc, out, fs, P, t, ca, cn, mode, status,
-                                (mode == 1 || mode == 2) ? nxt : nullptr, ready, &wrote);
+                                (mode == 1 || mode == 2 || (mode == 3 && chain)) ? nxt : nullptr, ready, &wrote);
     if (wrote) std::swap(cur, nxt);
     ready = wrote;
     return rc;
@@ -191,9 +194,10 @@ struct FluxPair {
 
 namespace {
 // One RK4 step in place on u; the stage states go to U2, U3, U4 (U4 may be U2: it is
-// written after U2 has been read for the last time).
+// written after U2 has been read for the last time). fx carries the flux arrays from one step of
+// a call to the next (see FluxPair); nullptr: a step of its own.
 int rk4_step(const cosmos_grid* grid, const cosmos_params* params, double t, double dt, double* u, double* U2,
-             double* U3, double* U4, void* ws, void* stream) {
+             double* U3, double* U4, void* ws, void* stream, FluxPair* carry = nullptr) {
   const Layout L = layout(grid);
   char* w = (char*)ws;
   double* acc = (double*)(w + L.acc);
@@ -205,7 +209,8 @@ int rk4_step(const cosmos_grid* grid, const cosmos_params* params, double t, dou
   if ((rc = make_tile(grid, params, T))) return rc;
   const size_t fs = npts(grid);
   hipStream_t s = (hipStream_t)stream;
-  FluxPair fx{F, (double*)(w + L.F2)};
+  FluxPair own{F, (double*)(w + L.F2)};
+  FluxPair& fx = carry ? *carry : own;
   if ((rc = fx.stage(params, T, s, u, u, acc, U2, fs, P, t, dt / 6.0, dt / 2.0, 1, status))) return rc;
   fx.stage(params, T, s, U2, u, acc, U3, fs, P, t + dt / 2.0, dt / 3.0, dt / 2.0, 2, status);
   fx.stage(params, T, s, U3, u, acc, U4, fs, P, t + dt / 2.0, dt / 3.0, dt, 2, status);
@@ -313,6 +318,26 @@ int cosmos_rk4_step(const cosmos_grid* grid, const cosmos_params* params, double
   double* A = (double*)((char*)ws + L.A);
   double* B = (double*)((char*)ws + L.B);
   return rk4_step(grid, params, t, dt, u, A, B, A, ws, stream);
+}
+
+int cosmos_rk4_steps(const cosmos_grid* grid, const cosmos_params* params, double t, double dt, int32_t nsteps,
+                     double* u, void* ws, void* stream) {
+  int rc;
+  if ((rc = check_common(grid, params)) || (rc = check_state(u, "u")) || (rc = check_ws(grid, ws))) return rc;
+  if (!(dt > 0.0) || !std::isfinite(dt) || !std::isfinite(t)) return set_error(COSMOS_EINVAL, "dt must be > 0, t finite");
+  if (nsteps < 0) return set_error(COSMOS_EINVAL, "nsteps %d < 0", (int)nsteps);
+  const Layout L = layout(grid);
+  char* w = (char*)ws;
+  double* A = (double*)(w + L.A);
+  double* B = (double*)(w + L.B);
+  FluxPair fx{(double*)(w + L.F), (double*)(w + L.F2)};
+  double tm = t;
+  for (int32_t m = 0; m < nsteps; ++m) {
+    fx.chain = m + 1 < nsteps;
+    if ((rc = rk4_step(grid, params, tm, dt, u, A, B, A, ws, stream, &fx))) return rc;
+    tm += dt;  // as a caller stepping one call at a time would advance it
+  }
+  return COSMOS_OK;
 }
 
 int cosmos_rk4_step_stages(const cosmos_grid* grid, const cosmos_params* params, double t, double dt, double* u,

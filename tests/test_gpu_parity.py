@@ -397,3 +397,36 @@ def test_c2_trajectory_100_steps_against_stored_oracle(P):
     assert norms[5] == g["norms"][5] and norms[6] == pytest.approx(g["norms"][6], rel=1e-12)
     st = sol.status()
     assert st["steps"] == 100 and st["nonfinite"] == 0 and st["prim_fail"] == g["prim_fail"]
+
+
+@pytest.mark.parametrize("kv,tile,order,scheme", [(0, (16, 4, 4), 2, 0), (0, (16, 8, 2), 1, 0), (1, (16, 4, 4), 0, 0),
+                                                  (0, (16, 4, 4), 1, 1)])
+def test_rk4_steps_equals_single_steps_bitwise(P, orc, kv, tile, order, scheme):
+    """cosmos_rk4_steps carries the fluid fluxes from the last stage of a step to the next step
+    (the LDS-staged 16x4x4 kernel of the centred scheme; the other bricks, the direct variant
+    and the Kurganov-Tadmor scheme run the pre-pass): the same state bitwise as single steps at
+    t, t + dt, ..., with the step counter advanced once per step; 5 steps on a 32 x 16 x 24 grid
+    whose step-5 state also matches the oracle."""
+    from paper_2606_02053_amd import autotune
+    n, L = (32, 16, 24), (8.0, 4.0, 6.0)
+    s, sol = mk(P, orc, n, L, fluid_scheme=scheme)
+    params = autotune.with_tile(sol.params, kv, tile, order)
+    u = fuzz_state(n, seed=91)
+    dt, t0 = 0.25 * min(s.h), 0.3
+    single = to_dev(u)
+    t = t0
+    for _ in range(5):
+        P.cosmos_rk4_step(sol.grid, params, t, dt, single, sol.ws)
+        t += dt
+    P.cosmos_status_reset(sol.ws)
+    multi = to_dev(u)
+    P.cosmos_rk4_steps(sol.grid, params, t0, dt, 5, multi, sol.ws)
+    assert torch.equal(multi, single)
+    assert sol.status()["steps"] == 5
+    P.cosmos_rk4_steps(sol.grid, params, t0, dt, 0, multi, sol.ws)  # no step
+    assert torch.equal(multi, single)
+    with pytest.raises(P.CosmosError):
+        P.cosmos_rk4_steps(sol.grid, params, t0, dt, -1, multi, sol.ws)
+    if kv == 0 and tile == (16, 4, 4) and scheme == 0:
+        ref, _ = orc.rk4(s, u, t0, dt, 5, parallel=True)
+        assert err_fields(multi.cpu().numpy(), ref)[0] < 1e-10
