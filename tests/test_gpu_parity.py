@@ -246,6 +246,15 @@ def test_bench_configuration_sampled(P, orc, nn):
     r1 = orc.rk4_at_points(s, u0, pts[:8], 0.0, dt)
     scale = np.maximum(np.abs(r1).max(axis=0), 1e-3)
     assert (np.abs(g1 - r1).max(axis=0) / scale).max() < 1e-11
+    if nn == 256:
+        # the benchmark times its steps as one cosmos_rk4_steps call (fluxes carried across the
+        # steps): from the initial data, two steps in one call equal two single steps bitwise
+        one = sol.u.clone()  # after the single step above
+        P.cosmos_rk4_step(sol.grid, sol.params, dt, dt, one, sol.ws)
+        two = torch.empty_like(sol.u)
+        P.cosmos_init_fields(sol.grid, sol.params, P.make_init(**ini), two)
+        P.cosmos_rk4_steps(sol.grid, sol.params, 0.0, dt, 2, two, sol.ws)
+        assert torch.equal(two, one)
 
 
 def test_tile_invariance_bitwise(P, orc):
