@@ -68,6 +68,19 @@ __device__ __forceinline__ void lds_barrier() {
   asm volatile("" ::: "memory");
 }
 
+// Brick of round `it` for workgroup `blk` in the XCD-blocked order (T.order 2, set up by the
+// launcher): XCD blk % 8 owns a slab of T.zr brick layers, and its workgroups take one
+// T.gx x T.gy x T.gz block of bricks per round. False when the workgroup's slot lies outside the
+// grid's bricks in this round.
+__device__ __forceinline__ bool blocked_brick(const Tile& T, int it, int blk, int& bxi, int& byi, int& bzi) {
+  const int l = blk >> 3, gxy = T.ngx * T.ngy;
+  bxi = (it % T.ngx) * T.gx + l % T.gx;
+  byi = ((it / T.ngx) % T.ngy) * T.gy + (l / T.gx) % T.gy;
+  const int bzl = (it / gxy) * T.gz + l / (T.gx * T.gy);
+  bzi = (blk & 7) * T.zr + bzl;
+  return bxi < T.nbx && byi < T.nby && bzl < T.zr && bzi < T.nbz;
+}
+
 // Stencil taps read from the LDS halo box: c points at the thread's centre.
 template <class B>
 __device__ __forceinline__ void lds_line(const double* c, int a, double v[7]) {

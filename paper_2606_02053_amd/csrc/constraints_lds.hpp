@@ -76,10 +76,12 @@ struct LdsDerivs {
   }
 };
 
-// T: 16x4x4 bricks; with T.xcd_order, workgroup w takes brick (w mod 8) * T.per + w / 8,
-// so each XCD walks its own slab of brick layers (launched with one workgroup per
-// brick); otherwise workgroups stride over the bricks in linear order. One partial
-// record per workgroup (its bricks folded in walk order). Two waves per SIMD: 256 registers.
+// T: 16x4x4 bricks. T.order 2: the XCD-blocked order (a persistent grid of the resident
+// workgroups; each round, an XCD's workgroups take one compact block of bricks, whose halos
+// overlap in its L2); else with T.xcd_order, workgroup w takes brick (w mod 8) * T.per + w / 8,
+// so each XCD walks its own slab of brick layers (launched with one workgroup per brick);
+// otherwise workgroups stride over the bricks in linear order. One partial record per workgroup
+// (its bricks folded in walk order). Two waves per SIMD: 256 registers.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_constraints_lds(
     const double* __restrict__ U, size_t fs, DevParams P, Tile T, double* __restrict__ Hout,
     double* __restrict__ Mout, double* __restrict__ part) {
@@ -88,13 +90,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   const int t = threadIdx.x;
   const int tx = t % 16, ty = (t / 16) % 4, tz = t / 64;
   const int cidx = (tx + ConsBrick::XO) + ConsBrick::SY * ((ty + 3) + ConsBrick::HY * (tz + 3));
-  const int nslots = T.xcd_order ? 8 * T.per : T.nbricks;
   Red mine = red_neutral();
   HaloDma<ConsBrick> hc;
-  for (int w = blockIdx.x; w < nslots; w += gridDim.x) {
-    const int brick = T.xcd_order ? (w & 7) * T.per + (w >> 3) : w;
-    if (brick >= T.nbricks) continue;  // uniform over the workgroup
-    const int i0 = (brick % T.nbx) * 16, j0 = ((brick / T.nbx) % T.nby) * 4, k0 = (brick / T.nbx / T.nby) * 4;
+  // T.order 2: round w of the XCD-blocked order; else brick slot w of the slab or linear order
+  const bool blocked = T.order == 2;
+  const int nslots = blocked ? T.ngroups : (T.xcd_order ? 8 * T.per : T.nbricks);
+  const int first = blocked ? 0 : (int)blockIdx.x, stride = blocked ? 1 : (int)gridDim.x;
+  for (int w = first; w < nslots; w += stride) {
+    int bxi, byi, bzi;
+    if (blocked) {
+      if (!blocked_brick(T, w, blockIdx.x, bxi, byi, bzi)) continue;  // uniform over the workgroup
+    } else {
+      const int brick = T.xcd_order ? (w & 7) * T.per + (w >> 3) : w;
+      if (brick >= T.nbricks) continue;  // uniform over the workgroup
+      bxi = brick % T.nbx, byi = (brick / T.nbx) % T.nby, bzi = brick / T.nbx / T.nby;
+    }
+    const int i0 = bxi * 16, j0 = byi * 4, k0 = bzi * 4;
     const int i = i0 + tx, j = j0 + ty, k = k0 + tz;
     const bool active = i < P.n[0] && j < P.n[1] && k < P.n[2];
     const int p = active ? i + P.n[0] * (j + P.n[1] * k) : 0;

@@ -374,8 +374,16 @@ void launch_constraints(const cosmos_grid* grid, const cosmos_params* params, co
     bp.tile_x = 16, bp.tile_y = 4, bp.tile_z = 4, bp.tile_order = 0;
     Tile T;
     make_tile(grid, &bp, T);
-    if (tile_blocks(T) > nb) T.xcd_order = 0;
-    nparts = (unsigned)std::min<size_t>(T.xcd_order ? tile_blocks(T) : (size_t)T.nbricks, nb);
+    // the XCD-blocked order where the resident workgroups split evenly into blocks (a persistent
+    // grid of G workgroups, so G partial records); else one workgroup per brick in XCD slabs
+    const unsigned G = resident_groups(k_constraints_lds);
+    if (G <= nb && T.nbricks >= (int)G && blocked_order(T, G / 8)) {
+      T.order = 2;
+      nparts = G;
+    } else {
+      if (tile_blocks(T) > nb) T.xcd_order = 0;
+      nparts = (unsigned)std::min<size_t>(T.xcd_order ? tile_blocks(T) : (size_t)T.nbricks, nb);
+    }
     hipLaunchKernelGGL(k_constraints_lds, dim3(nparts), dim3(kBlock), 0, s, u, npts(grid), P, T, H_out, M_out, part);
   } else {
     hipLaunchKernelGGL(k_constraints, dim3(nparts), dim3(kBlock), 0, s, u, npts(grid), P, H_out, M_out, part);
