@@ -67,9 +67,11 @@ struct ScLds {
   }
 };
 
-// T: 16x4x4 bricks; with T.xcd_order, workgroup w takes brick (w mod 8) * T.per + w / 8, so each
-// XCD walks its own slab of brick layers; otherwise workgroups stride over the bricks. Needs
-// n0 even and U, Sc 16-byte aligned (aligned pairs of x-neighbours).
+// T: 16x4x4 bricks. T.order 2: the XCD-blocked order (a persistent grid of the resident
+// workgroups; each round, an XCD's workgroups take one compact block of bricks); else with
+// T.xcd_order, slot w is brick (w mod 8) * T.per + w / 8, so each XCD walks its own slab of brick
+// layers, and the workgroups stride over the slots. Needs n0 even and U, Sc 16-byte aligned
+// (aligned pairs of x-neighbours).
 template <int MODE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_scalar_stage_lds(
     const double* __restrict__ U, const double* __restrict__ Sc, double* __restrict__ src,
@@ -80,12 +82,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   const int t = threadIdx.x;
   const int tx = t % 16, ty = (t / 16) % 4, tz = t / 64;
   const int cidx = (tx + ScBrick::XO) + ScBrick::SY * ((ty + 3) + ScBrick::HY * (tz + 3));
-  const int nslots = T.xcd_order ? 8 * T.per : T.nbricks;
   HaloDma<ScBrick> hc;
-  for (int w = blockIdx.x; w < nslots; w += gridDim.x) {
-    const int brick = T.xcd_order ? (w & 7) * T.per + (w >> 3) : w;
-    if (brick >= T.nbricks) continue;  // uniform over the workgroup
-    const int i0 = (brick % T.nbx) * 16, j0 = ((brick / T.nbx) % T.nby) * 4, k0 = (brick / T.nbx / T.nby) * 4;
+  const bool blocked = T.order == 2;
+  const int nslots = blocked ? T.ngroups : (T.xcd_order ? 8 * T.per : T.nbricks);
+  const int first = blocked ? 0 : (int)blockIdx.x, stride = blocked ? 1 : (int)gridDim.x;
+  for (int w = first; w < nslots; w += stride) {
+    int bxi, byi, bzi;
+    if (blocked) {
+      if (!blocked_brick(T, w, blockIdx.x, bxi, byi, bzi)) continue;  // uniform over the workgroup
+    } else {
+      const int brick = T.xcd_order ? (w & 7) * T.per + (w >> 3) : w;
+      if (brick >= T.nbricks) continue;  // uniform over the workgroup
+      bxi = brick % T.nbx, byi = (brick / T.nbx) % T.nby, bzi = brick / T.nbx / T.nby;
+    }
+    const int i0 = bxi * 16, j0 = byi * 4, k0 = bzi * 4;
     const int i = i0 + tx, j = j0 + ty, k = k0 + tz;
     const bool active = i < P.n[0] && j < P.n[1] && k < P.n[2];
     const int p = active ? i + P.n[0] * (j + P.n[1] * k) : 0;  // inactive threads evaluate point 0
