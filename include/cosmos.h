@@ -334,6 +334,14 @@ int cosmos_batch_setup(const cosmos_batch* batch, const cosmos_params* params, v
 int cosmos_rk4_step_batched(const cosmos_batch* batch, const cosmos_params* params, double* arena,
                             double* t_dev, const double* dt_dev, void* bws, void* stream);
 
+/* nsteps (>= 1) batched steps in one call, graph-capturable as one step is: every run ends in the
+ * same state bitwise as after nsteps calls of cosmos_rk4_step_batched. Within the call the last
+ * stage of a step also writes the fluid fluxes of the new states for the next step (the 16x4x4
+ * brick of the centred scheme; other bricks and schemes run the pre-pass every step). Errors as
+ * cosmos_rk4_step_batched, and COSMOS_EINVAL for nsteps < 1. */
+int cosmos_rk4_steps_batched(const cosmos_batch* batch, const cosmos_params* params, double* arena, double* t_dev,
+                             const double* dt_dev, int32_t nsteps, void* bws, void* stream);
+
 /* Bytes of the batch's scalar-field workspace (256-byte aligned device memory, used besides bws by
  * cosmos_rk4_step_batched_scalar): the field's RK4 buffers and source arrays of every run, laid out
  * like the state arena. 0 for an invalid batch. */

@@ -84,6 +84,7 @@ def _load():
         "cosmos_batch_workspace_bytes": ([B], sz),
         "cosmos_batch_setup": ([B, Pr, P, P], i32),
         "cosmos_rk4_step_batched": ([B, Pr, P, P, P, P, P], i32),
+        "cosmos_rk4_steps_batched": ([B, Pr, P, P, P, i32, P, P], i32),
         "cosmos_batch_status": ([B, P, P, ctypes.POINTER(ctypes.c_int64)], i32),
         "cosmos_batch_outcomes": ([B, P, P, P, P], i32),
         "cosmos_batch_scalar_workspace_bytes": ([B], sz),
@@ -352,6 +353,14 @@ def cosmos_rk4_step_batched(batch, params, arena, t_dev, dt_dev, bws, stream=Non
                                        _dev(t_dev, "t_dev", batch.nruns), _dev(dt_dev, "dt_dev", batch.nruns),
                                        _dev(bws, "bws", cosmos_batch_workspace_bytes(batch), dtype=torch.uint8),
                                        _stream(stream)))
+
+
+def cosmos_rk4_steps_batched(batch, params, arena, t_dev, dt_dev, nsteps: int, bws, stream=None):
+    _check(lib.cosmos_rk4_steps_batched(ctypes.byref(batch), ctypes.byref(params), _dev(arena, "arena"),
+                                        _dev(t_dev, "t_dev", batch.nruns), _dev(dt_dev, "dt_dev", batch.nruns),
+                                        int(nsteps),
+                                        _dev(bws, "bws", cosmos_batch_workspace_bytes(batch), dtype=torch.uint8),
+                                        _stream(stream)))
 
 
 def cosmos_batch_scalar_workspace_bytes(batch) -> int:

@@ -58,6 +58,7 @@ class Batch:
         self.t = torch.zeros(len(self.runs), dtype=torch.float64, device=self.device)
         self.dt = torch.tensor([cfl * r.L / r.n for r in self.runs], dtype=torch.float64, device=self.device)
         self.graph = None
+        self.graph_steps = 1
         self.scalar = scalar
         if scalar:  # laid out like the state arena: run r's (phi, Pi) at its state offset
             self.sarena = torch.zeros(o, dtype=torch.float64, device=self.device)
@@ -84,32 +85,41 @@ class Batch:
         self.t.zero_()
         C.cosmos_batch_setup(self.batch, self.params, self.bws)
 
-    def _step(self, stream=None):
+    def _step(self, stream=None, nsteps: int = 1):
         if self.scalar:
-            C.cosmos_rk4_step_batched_scalar(self.batch, self.params, self.arena, self.sarena, self.t, self.dt,
-                                             self.bws, self.sbws, stream=stream)
-        else:
+            for _ in range(nsteps):
+                C.cosmos_rk4_step_batched_scalar(self.batch, self.params, self.arena, self.sarena, self.t, self.dt,
+                                                 self.bws, self.sbws, stream=stream)
+        elif nsteps == 1:
             C.cosmos_rk4_step_batched(self.batch, self.params, self.arena, self.t, self.dt, self.bws, stream=stream)
+        else:  # one call: the fluid fluxes carried from step to step
+            C.cosmos_rk4_steps_batched(self.batch, self.params, self.arena, self.t, self.dt, nsteps, self.bws,
+                                       stream=stream)
 
     def step(self):
         self._step()
 
-    def capture(self):
-        """Capture one batched RK4 step in a graph (after init)."""
+    def capture(self, steps: int = 1):
+        """Capture `steps` batched RK4 steps in a graph (after init); run() replays it."""
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
         self.graph = torch.cuda.CUDAGraph()
+        self.graph_steps = steps
         with torch.cuda.graph(self.graph, stream=s):
-            self._step(stream=torch.cuda.current_stream())
+            self._step(stream=torch.cuda.current_stream(), nsteps=steps)
         torch.cuda.current_stream().wait_stream(s)
         return self.graph
 
     def run(self, nsteps: int, use_graph: bool = True):
+        """nsteps steps: replays of the captured graph, then single steps for the remainder."""
         if use_graph:
             if self.graph is None:
                 raise RuntimeError("call capture() first")
-            for _ in range(nsteps):
+            reps, rest = divmod(nsteps, self.graph_steps)
+            for _ in range(reps):
                 self.graph.replay()
+            for _ in range(rest):
+                self.step()
         else:
             for _ in range(nsteps):
                 self.step()

@@ -67,7 +67,7 @@ def scan_batch(mus, sigma: float, n: int, L: float, nsteps: int, alpha_th: float
         b = Batch([RunSpec(n=n, mu=zmu, sigma=zsg, L=L, sc_mu=float(m), sc_sigma=sigma) for m in mus], p,
                   scalar=True)
     b.init()
-    b.capture()
+    b.capture(steps=nsteps)  # the whole run as one graph: fluid fluxes carried from step to step
     b.run(nsteps)
     out = b.outcomes()
     st = b.status()

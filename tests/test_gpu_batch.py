@@ -63,6 +63,40 @@ def test_graph_replay_equals_eager(P):
         assert torch.equal(eager.t, g.t)
 
 
+@pytest.mark.parametrize("tile,scheme", [((16, 4, 4), 0), ((8, 8, 4), 0), ((16, 4, 4), 1)])
+def test_multi_step_graph_equals_single_steps(P, tile, scheme):
+    """cosmos_rk4_steps_batched: a graph of 3 steps in one call (the last stage of a step writes
+    the next step's fluxes with the 16x4x4 brick of the centred scheme; the 8x8x4 brick and the
+    KT scheme run a pre-pass per step), replayed twice with eager work between the replays, equals
+    6 eager single steps bitwise, step counters and times included; a 7th step (run(7) = two
+    replays and one single step) as well."""
+    from paper_2606_02053_amd.batch import Batch
+    runs = small_runs()
+    params = P.make_params(tile=tile, tile_order=1, variant=0, fluid_scheme=scheme)
+    eager = Batch(runs, params)
+    eager.init()
+    g = Batch(runs, params)
+    g.init()
+    g.capture(steps=3)
+    for rep in range(2):
+        eager.run(3, use_graph=False)
+        g.run(3)
+        torch.cuda.synchronize()
+        _ = g.arena.sum().item()  # eager work between replays
+        for r in range(len(runs)):
+            assert torch.equal(eager.state(r), g.state(r)), (rep, r)
+        assert torch.equal(eager.t, g.t)
+    eager.run(1, use_graph=False)
+    g2 = Batch(runs, params)
+    g2.init()
+    g2.capture(steps=3)
+    g2.run(7)
+    for r in range(len(runs)):
+        assert torch.equal(eager.state(r), g2.state(r)), r
+    assert [x["steps"] for x in g2.status()] == [7] * len(runs)
+    assert g2.status() == eager.status()
+
+
 def test_poisoned_run_is_isolated(P):
     from paper_2606_02053_amd.batch import Batch
     runs = small_runs()
