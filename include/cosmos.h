@@ -235,6 +235,14 @@ int cosmos_rk4_steps(const cosmos_grid* grid, const cosmos_params* params, doubl
 int cosmos_rk4_step_stages(const cosmos_grid* grid, const cosmos_params* params, double t, double dt,
                            double* u, double* stages, void* ws, void* stream);
 
+/* nsteps (>= 0) RK4 steps as cosmos_rk4_steps (the same u bitwise as single steps at t, t + dt,
+ * t + dt + dt, ...), keeping the whole trajectory for a reverse sweep: states (nsteps * 25 * N3
+ * doubles) receives the start state of step m at offset m * 25 * N3, stages (nsteps * 3 * 25 * N3
+ * doubles) the stage states of step m at offset m * 3 * 25 * N3, as cosmos_rk4_step_stages writes
+ * them. Device, caller-owned; states, stages, u and ws must not overlap (COSMOS_EINVAL). */
+int cosmos_rk4_steps_stages(const cosmos_grid* grid, const cosmos_params* params, double t, double dt,
+                            int32_t nsteps, double* u, double* states, double* stages, void* ws, void* stream);
+
 /* Hamiltonian and momentum constraints of u and their grid norms:
  *   H   = R + 2/3 K^2 - At_ij At^ij - 16 pi E
  *   M_i = gt^jk (d_j At_ki - Gt^l_jk At_li - Gt^l_ji At_kl) - 3/(2 chi) At^j_i d_j chi - 2/3 d_i K - 8 pi S_i

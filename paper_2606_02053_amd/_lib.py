@@ -73,6 +73,7 @@ def _load():
         "cosmos_kt_divergence": ([G, Pr, P, P, P], i32),
         "cosmos_rk4_step": ([G, Pr, f64, f64, P, P, P], i32),
         "cosmos_rk4_steps": ([G, Pr, f64, f64, i32, P, P, P], i32),
+        "cosmos_rk4_steps_stages": ([G, Pr, f64, f64, i32, P, P, P, P, P], i32),
         "cosmos_rk4_step_stages": ([G, Pr, f64, f64, P, P, P, P], i32),
         "cosmos_constraints": ([G, Pr, P, P, P, P, P, P], i32),
         "cosmos_constraints_noalloc": ([G, Pr, P, P, P, P, P], i32),
@@ -225,6 +226,15 @@ def cosmos_rk4_steps(grid, params, t: float, dt: float, nsteps: int, u, ws, stre
     _check(lib.cosmos_rk4_steps(ctypes.byref(grid), ctypes.byref(params), float(t), float(dt), int(nsteps),
                                 _dev(u, "u", NFIELDS * npts(grid)), _dev(ws, "ws", cosmos_workspace_bytes(grid),
                                                                          dtype=torch.uint8), _stream(stream)))
+
+
+def cosmos_rk4_steps_stages(grid, params, t: float, dt: float, nsteps: int, u, states, stages, ws, stream=None):
+    N = NFIELDS * npts(grid)
+    _check(lib.cosmos_rk4_steps_stages(ctypes.byref(grid), ctypes.byref(params), float(t), float(dt), int(nsteps),
+                                       _dev(u, "u", N), _dev(states, "states", int(nsteps) * N),
+                                       _dev(stages, "stages", 3 * int(nsteps) * N),
+                                       _dev(ws, "ws", cosmos_workspace_bytes(grid), dtype=torch.uint8),
+                                       _stream(stream)))
 
 
 def cosmos_rk4_step_stages(grid, params, t: float, dt: float, u, stages, ws, stream=None):

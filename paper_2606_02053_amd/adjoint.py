@@ -10,14 +10,16 @@ state and its RK4 stage states (cosmos_adjoint_step_stages); where they come
 from is a memory trade:
 
 * `keep_all`: the forward pass keeps every step's start state and stage states
-  (cosmos_rk4_step_stages; 4 states per step), so the backward pass evaluates
-  no forward stage at all. At 96^3 and 200 steps that is 142 GB of device memory.
+  (one cosmos_rk4_steps_stages call; 4 states per step), so the backward pass
+  evaluates no forward stage at all. At 96^3 and 200 steps that is 142 GB of
+  device memory.
 * otherwise the forward pass stores the state every `checkpoint_every` steps and
   the backward pass recomputes each segment from its checkpoint; where memory
   allows (`keep_stages`) the recomputation keeps the segment's stage states,
   else the adjoint step evaluates them itself (cosmos_adjoint_step).
 
-All three give the same gradient bitwise.
+All three give the same gradient bitwise. Step m starts at the time t_m reached by
+adding dt m times (as a multi-step library call advances it), on every path.
 """
 from __future__ import annotations
 
@@ -54,6 +56,15 @@ def _free_bytes(dev) -> int:
     return torch.cuda.mem_get_info(dev)[0]
 
 
+def _step_times(nsteps: int, dt: float) -> list[float]:
+    """t_0 = 0 and t_{m+1} = t_m + dt: the start time of every step."""
+    ts, t = [], 0.0
+    for _ in range(nsteps):
+        ts.append(t)
+        t += dt
+    return ts
+
+
 class CosmosRun(torch.autograd.Function):
     @staticmethod
     def forward(ctx, mu: torch.Tensor, sigma: torch.Tensor, cfg: RunConfig):
@@ -66,18 +77,17 @@ class CosmosRun(torch.autograd.Function):
         if keep_all is None:
             keep_all = wanted and 4 * cfg.nsteps * numel * 8 < 0.6 * _free_bytes(s.u.device)
         ckpts, traj = {}, None
+        ts = _step_times(cfg.nsteps, dt)
         if wanted and keep_all:
             states = torch.empty((cfg.nsteps, numel), dtype=torch.float64, device=s.u.device)
             stages = torch.empty((cfg.nsteps, 3 * numel), dtype=torch.float64, device=s.u.device)
-            for m in range(cfg.nsteps):
-                states[m].copy_(s.u.view(-1))
-                C.cosmos_rk4_step_stages(s.grid, s.params, m * dt, dt, s.u, stages[m], s.ws)
+            C.cosmos_rk4_steps_stages(s.grid, s.params, 0.0, dt, cfg.nsteps, s.u, states, stages, s.ws)
             traj = (states, stages)
         else:
             for m in range(cfg.nsteps):
                 if wanted and m % cfg.checkpoint_every == 0:
                     ckpts[m] = s.u.clone()
-                C.cosmos_rk4_step(s.grid, s.params, m * dt, dt, s.u, s.ws)
+                C.cosmos_rk4_step(s.grid, s.params, ts[m], dt, s.u, s.ws)
         c = cfg.n // 2
         J = s.u[17, c, c, c].clone()
         ctx.cfg = cfg
@@ -97,10 +107,11 @@ class CosmosRun(torch.autograd.Function):
         lam[17, c, c, c] = gJ.to(dev, torch.float64)
         lam_next = torch.empty_like(lam)
         ws_adj = torch.empty(C.cosmos_adjoint_workspace_bytes(grid), dtype=torch.uint8, device=dev)
+        ts = _step_times(cfg.nsteps, dt)
         if ctx.traj is not None:
             states, stages = ctx.traj
             for m in range(cfg.nsteps - 1, -1, -1):
-                C.cosmos_adjoint_step_stages(grid, params, m * dt, dt, states[m], stages[m], lam, lam_next, ws_adj)
+                C.cosmos_adjoint_step_stages(grid, params, ts[m], dt, states[m], stages[m], lam, lam_next, ws_adj)
                 lam, lam_next = lam_next, lam
             ctx.traj = None
         else:
@@ -116,17 +127,17 @@ class CosmosRun(torch.autograd.Function):
                 u = ctx.ckpts[start].clone()
                 for m in range(start, end):  # recompute the segment's states (and stage states)
                     if keep:
-                        C.cosmos_rk4_step_stages(grid, params, m * dt, dt, u, stages[m - start], ws_fwd)
+                        C.cosmos_rk4_step_stages(grid, params, ts[m], dt, u, stages[m - start], ws_fwd)
                     elif m < end - 1:
-                        C.cosmos_rk4_step(grid, params, m * dt, dt, u, ws_fwd)
+                        C.cosmos_rk4_step(grid, params, ts[m], dt, u, ws_fwd)
                     if m < end - 1:
                         states.append(u.clone())
                 for m in range(end - 1, start - 1, -1):
                     if keep:
-                        C.cosmos_adjoint_step_stages(grid, params, m * dt, dt, states[m - start], stages[m - start],
+                        C.cosmos_adjoint_step_stages(grid, params, ts[m], dt, states[m - start], stages[m - start],
                                                      lam, lam_next, ws_adj)
                     else:
-                        C.cosmos_adjoint_step(grid, params, m * dt, dt, states[m - start], lam, lam_next, ws_adj)
+                        C.cosmos_adjoint_step(grid, params, ts[m], dt, states[m - start], lam, lam_next, ws_adj)
                     lam, lam_next = lam_next, lam
         init = C.make_init(mu=ctx.mu, sigma=ctx.sigma, **cfg.init_kw)
         grad = torch.empty(2, dtype=torch.float64, device=dev)

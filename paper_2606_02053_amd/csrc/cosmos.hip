@@ -355,13 +355,46 @@ int cosmos_rk4_step_stages(const cosmos_grid* grid, const cosmos_params* params,
   return rk4_step(grid, params, t, dt, u, stages, stages + n, stages + 2 * n, ws, stream);
 }
 
+int cosmos_rk4_steps_stages(const cosmos_grid* grid, const cosmos_params* params, double t, double dt,
+                            int32_t nsteps, double* u, double* states, double* stages, void* ws, void* stream) {
+  int rc;
+  if ((rc = check_common(grid, params)) || (rc = check_state(u, "u")) || (rc = check_state(states, "states")) ||
+      (rc = check_state(stages, "stages")) || (rc = check_ws(grid, ws)))
+    return rc;
+  if (!(dt > 0.0) || !std::isfinite(dt) || !std::isfinite(t)) return set_error(COSMOS_EINVAL, "dt must be > 0, t finite");
+  if (nsteps < 0) return set_error(COSMOS_EINVAL, "nsteps %d < 0", (int)nsteps);
+  const size_t n = (size_t)NF * npts(grid);
+  const char *ua = (const char*)u, *ub = ua + n * sizeof(double);
+  const char *wa = (const char*)ws, *wb = wa + cosmos_workspace_bytes(grid);
+  const char *sa = (const char*)states, *sb = sa + (size_t)nsteps * n * sizeof(double);
+  const char *ga = (const char*)stages, *gb = ga + (size_t)nsteps * 3 * n * sizeof(double);
+  auto apart = [](const char* a0, const char* a1, const char* b0, const char* b1) { return a1 <= b0 || b1 <= a0; };
+  if (!apart(sa, sb, ua, ub) || !apart(sa, sb, wa, wb) || !apart(ga, gb, ua, ub) || !apart(ga, gb, wa, wb) ||
+      !apart(sa, sb, ga, gb))
+    return set_error(COSMOS_EINVAL, "states, stages, u and ws must not overlap");
+  const Layout L = layout(grid);
+  char* w = (char*)ws;
+  FluxPair fx{(double*)(w + L.F), (double*)(w + L.F2)};
+  hipStream_t s = (hipStream_t)stream;
+  double tm = t;
+  for (int32_t m = 0; m < nsteps; ++m) {
+    HIP_TRY(hipMemcpyAsync(states + (size_t)m * n, u, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    double* st = stages + (size_t)m * 3 * n;
+    fx.chain = m + 1 < nsteps;
+    if ((rc = rk4_step(grid, params, tm, dt, u, st, st + n, st + 2 * n, ws, stream, &fx))) return rc;
+    tm += dt;
+  }
+  return COSMOS_OK;
+}
+
 }  // extern "C"
 
 namespace {
 
-// Constraint norms of u: the LDS-staged kernel (variant 0 with n0 even; 16x4x4 bricks in XCD
-// slabs where one workgroup per brick fits the `cap` partial records at `part`, else workgroups
-// stride over the bricks) or the direct one (variant 1, and grids with odd n0: one workgroup per
+// Constraint norms of u: the LDS-staged kernel (variant 0 with n0 even; 16x4x4 bricks, a
+// persistent grid in the XCD-blocked order where the resident workgroups split evenly into blocks
+// and fit the `cap` partial records at `part`, else XCD slabs, workgroups striding over the
+// bricks when there are more than `cap`) or the direct one (variant 1, and grids with odd n0: one workgroup per
 // 256 points, or at most `cap` of them striding over the blocks), then the fixed-order fold of
 // the per-workgroup partials.
 void launch_constraints(const cosmos_grid* grid, const cosmos_params* params, const DevParams& P, const double* u,

@@ -152,6 +152,41 @@ def test_stage_keeping_step_and_adjoint_bitwise(P, orc):
         P.cosmos_rk4_step_stages(grid, params, 0.2, dt, stages[0], stages, ws)  # stages overlaps u
 
 
+@pytest.mark.parametrize("tile", [(16, 4, 4), (8, 8, 4)])
+def test_rk4_steps_stages_equals_single_steps(P, orc, tile):
+    """cosmos_rk4_steps_stages (the fluid fluxes carried from step to step with the 16x4x4 brick):
+    u, every step's start state and its stage states equal single cosmos_rk4_step_stages calls at
+    t, t + dt, t + dt + dt bitwise; overlapping arrays are refused."""
+    from paper_2606_02053_amd import autotune
+    n, L = (16, 12, 20), (4.0, 3.0, 5.0)
+    s = orc.Setup(n=n, L=L)
+    dt = 0.25 * min(s.h)
+    grid = P.make_grid(n, L)
+    params = autotune.with_tile(P.make_params(), 0, tile, 1)
+    ws = torch.empty(P.cosmos_workspace_bytes(grid), dtype=torch.uint8, device="cuda")
+    u0 = torch.from_numpy(fuzz_state(n, seed=53)).cuda()
+    N = u0.numel()
+    one = u0.clone()
+    ref_states, ref_stages = [], []
+    t = 0.2
+    for _ in range(3):
+        ref_states.append(one.clone())
+        st = torch.empty(3 * N, dtype=torch.float64, device="cuda")
+        P.cosmos_rk4_step_stages(grid, params, t, dt, one, st, ws)
+        ref_stages.append(st)
+        t += dt
+    multi = u0.clone()
+    states = torch.full((3, N), float("nan"), dtype=torch.float64, device="cuda")
+    stages = torch.full((3, 3 * N), float("nan"), dtype=torch.float64, device="cuda")
+    P.cosmos_rk4_steps_stages(grid, params, 0.2, dt, 3, multi, states, stages, ws)
+    assert torch.equal(multi, one)
+    for m in range(3):
+        assert torch.equal(states[m], ref_states[m].reshape(-1)), m
+        assert torch.equal(stages[m], ref_stages[m]), m
+    with pytest.raises(P.CosmosError):  # the states overlap the stage states
+        P.cosmos_rk4_steps_stages(grid, params, 0.2, dt, 1, multi, stages[0, :N], stages[0], ws)
+
+
 def test_gradient_with_and_without_kept_stages(P):
     """The three sources of the adjoint steps' states (the whole forward trajectory kept, segments
     recomputed keeping their stage states, segments recomputed without them) give the same J and
