@@ -827,7 +827,7 @@ def threshold_bench(a):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py runs on exactly one GPU (this build has no multi-GPU path); got --gpus {a.gpus}",
+        print(f"bench.py runs on exactly one GPU (the library has no multi-GPU path); got --gpus {a.gpus}",
               file=sys.stderr)
         sys.exit(2)
     if a.source_hash:
