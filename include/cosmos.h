@@ -209,6 +209,12 @@ int cosmos_rhs_scalar(const cosmos_grid* grid, const cosmos_params* params, doub
 int cosmos_rk4_step_scalar(const cosmos_grid* grid, const cosmos_params* params, double t, double dt, double* u,
                            double* s, void* ws, void* sws, void* stream);
 
+/* nsteps (>= 0) RK4 steps of (u, s) in one call: the same states bitwise as nsteps calls of
+ * cosmos_rk4_step_scalar at t, t + dt, t + dt + dt, ..., the fluid fluxes carried from step to
+ * step as in cosmos_rk4_steps. COSMOS_EINVAL for nsteps < 0. */
+int cosmos_rk4_steps_scalar(const cosmos_grid* grid, const cosmos_params* params, double t, double dt, int32_t nsteps,
+                            double* u, double* s, void* ws, void* sws, void* stream);
+
 /* cosmos_constraints with the scalar field's energy and momentum in H and M_i. */
 int cosmos_constraints_scalar(const cosmos_grid* grid, const cosmos_params* params, const double* u, const double* s,
                               double* norms_dev, double* H_out, double* M_out, void* ws, void* sws, void* stream);

@@ -94,6 +94,7 @@ def _load():
         "cosmos_init_fields_scalar": ([G, Pr, In, f64, f64, P, P, P], i32),
         "cosmos_rhs_scalar": ([G, Pr, f64, P, P, P, P, P, P, P], i32),
         "cosmos_rk4_step_scalar": ([G, Pr, f64, f64, P, P, P, P, P], i32),
+        "cosmos_rk4_steps_scalar": ([G, Pr, f64, f64, i32, P, P, P, P, P], i32),
         "cosmos_constraints_scalar": ([G, Pr, P, P, P, P, P, P, P, P], i32),
         "cosmos_fmr_child_grid": ([G, ctypes.POINTER(cosmos_box), G], i32),
         "cosmos_fmr_workspace_bytes": ([G, ctypes.POINTER(cosmos_box)], sz),
@@ -288,6 +289,15 @@ def cosmos_rk4_step_scalar(grid, params, t: float, dt: float, u, s, ws, sws, str
                                       _dev(ws, "ws", cosmos_workspace_bytes(grid), dtype=torch.uint8),
                                       _dev(sws, "sws", cosmos_scalar_workspace_bytes(grid), dtype=torch.uint8),
                                       _stream(stream)))
+
+
+def cosmos_rk4_steps_scalar(grid, params, t: float, dt: float, nsteps: int, u, s, ws, sws, stream=None):
+    n = npts(grid)
+    _check(lib.cosmos_rk4_steps_scalar(ctypes.byref(grid), ctypes.byref(params), float(t), float(dt), int(nsteps),
+                                       _dev(u, "u", NFIELDS * n), _dev(s, "s", 2 * n),
+                                       _dev(ws, "ws", cosmos_workspace_bytes(grid), dtype=torch.uint8),
+                                       _dev(sws, "sws", cosmos_scalar_workspace_bytes(grid), dtype=torch.uint8),
+                                       _stream(stream)))
 
 
 def cosmos_constraints_scalar(grid, params, u, s, norms_dev, H_out=None, M_out=None, ws=None, sws=None, stream=None):

@@ -69,14 +69,13 @@ class Solver:
         self.t += dt
 
     def run(self, nsteps: int, dt: float | None = None):
-        """nsteps steps; without the scalar field in one library call (cosmos_rk4_steps: the same
+        """nsteps steps in one library call (cosmos_rk4_steps, cosmos_rk4_steps_scalar: the same
         state bitwise as nsteps calls of step, the fluid fluxes carried from step to step)."""
         dt = self.default_dt() if dt is None else dt
         if self.scalar:
-            for _ in range(nsteps):
-                self.step(dt)
-            return
-        C.cosmos_rk4_steps(self.grid, self.params, self.t, dt, nsteps, self.u, self.ws)
+            C.cosmos_rk4_steps_scalar(self.grid, self.params, self.t, dt, nsteps, self.u, self.s, self.ws, self.sws)
+        else:
+            C.cosmos_rk4_steps(self.grid, self.params, self.t, dt, nsteps, self.u, self.ws)
         for _ in range(nsteps):
             self.t += dt
 

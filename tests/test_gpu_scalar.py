@@ -84,6 +84,24 @@ def test_scalar_lds_kernel_equals_direct_bitwise(P, orc):
     assert err_fields(du1.reshape(25, *du0.shape[1:]).cpu().numpy(), du0.cpu().numpy())[0] < 1e-13
 
 
+def test_scalar_rk4_steps_equals_single_steps(P, orc):
+    """cosmos_rk4_steps_scalar (fluid fluxes carried from step to step): 4 steps in one call equal
+    4 single steps at t, t + dt, ... bitwise, geometry and field; nsteps < 0 is refused."""
+    n, L = (20, 12, 18), (4.0, 2.5, 3.5)
+    s, sol = mk(P, orc, n, L)
+    u, sc = fuzz_state(n, seed=45), fuzz_scalar(n, seed=46)
+    dt = 0.25 * min(s.h)
+    sol.set_state(to_dev(u), t=0.1, s=to_dev(sc))
+    for _ in range(4):
+        sol.step(dt)
+    one_u, one_s = sol.u.clone(), sol.s.clone()
+    sol.set_state(to_dev(u), t=0.1, s=to_dev(sc))
+    sol.run(4, dt)
+    assert torch.equal(sol.u, one_u) and torch.equal(sol.s, one_s)
+    with pytest.raises(P.CosmosError):
+        P.cosmos_rk4_steps_scalar(sol.grid, sol.params, 0.1, dt, -1, sol.u, sol.s, sol.ws, sol.sws)
+
+
 def test_zero_scalar_field_equals_plain_path(P, orc):
     n, L = (20, 12, 18), (4.0, 2.5, 3.5)
     u = fuzz_state(n, seed=3)
