@@ -262,8 +262,8 @@ int cosmos_constraints(const cosmos_grid* grid, const cosmos_params* params, con
 
 /* cosmos_constraints without a workspace, for callers that cannot allocate device memory (code
  * under graph capture, monitoring loops and harnesses that forbid allocation). Same arguments and
- * results as cosmos_constraints (always the LDS-staged kernel; params->variant is not consulted),
- * minus ws: the per-workgroup reduction partials go to a fixed device array inside the library,
+ * results as cosmos_constraints (the LDS-staged kernel, or the direct one on grids with odd n0 or u
+ * not 16-byte aligned, as there; params->variant is not consulted), minus ws: the per-workgroup reduction partials go to a fixed device array inside the library,
  * 4096 records of 8 doubles (256 KiB) per GPU, held from the first call on that GPU until the
  * process ends. At most 4096 workgroups are launched and they stride over the grid's bricks, so
  * every grid the library accepts fits; grids beyond its limits (8 <= n <= 2048, n0 n1 n2 < 2^29)
