@@ -194,8 +194,8 @@ struct FluxPair {
 
 namespace {
 // One RK4 step in place on u; the stage states go to U2, U3, U4 (U4 may be U2: it is
-// written after U2 has been read for the last time). fx carries the flux arrays from one step of
-// a call to the next (see FluxPair); nullptr: a step of its own.
+// written after U2 has been read for the last time). carry: the flux arrays carried from one step
+// of a call to the next (see FluxPair); nullptr: a step of its own.
 int rk4_step(const cosmos_grid* grid, const cosmos_params* params, double t, double dt, double* u, double* U2,
              double* U3, double* U4, void* ws, void* stream, FluxPair* carry = nullptr) {
   const Layout L = layout(grid);
