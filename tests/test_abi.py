@@ -186,3 +186,38 @@ def test_fmr_geometry_on_host(C):
     assert rc == C.COSMOS_EINVAL and "theta" in C.last_error()
     rc = lib.cosmos_fmr_restrict(ctypes.byref(g), ctypes.byref(b), None, fake, None)
     assert rc == C.COSMOS_EINVAL and "child_u" in C.last_error()
+
+
+def test_multi_step_entry_points_validate_on_host(C):
+    g = C.make_grid(16, 4.0)
+    p = C.make_params()
+    lib = C.lib
+    n = 25 * 16 ** 3 * 8
+    u = ctypes.c_void_p(0x10000000)  # never dereferenced: validation fails first, or no step runs
+    ws = ctypes.c_void_p(0x40000000)
+    G, Pp = ctypes.byref(g), ctypes.byref(p)
+    assert lib.cosmos_rk4_steps(G, Pp, 0.0, 0.1, -1, u, ws, None) == C.COSMOS_EINVAL
+    assert "nsteps -1" in C.last_error()
+    assert lib.cosmos_rk4_steps(G, Pp, 0.0, 0.0, 3, u, ws, None) == C.COSMOS_EINVAL
+    assert lib.cosmos_rk4_steps(G, Pp, 0.0, float("nan"), 3, u, ws, None) == C.COSMOS_EINVAL
+    assert lib.cosmos_rk4_steps(G, Pp, 0.0, 0.1, 0, u, ws, None) == C.COSMOS_OK  # zero steps: nothing launched
+    states = ctypes.c_void_p(0x80000000)
+    stages = ctypes.c_void_p(0xC0000000)
+    rc = lib.cosmos_rk4_steps_stages(G, Pp, 0.0, 0.1, -2, u, states, stages, ws, None)
+    assert rc == C.COSMOS_EINVAL and "nsteps -2" in C.last_error()
+    # the third of three kept states would reach into u
+    below_u = ctypes.c_void_p(0x10000000 - 2 * n)
+    rc = lib.cosmos_rk4_steps_stages(G, Pp, 0.0, 0.1, 3, u, below_u, stages, ws, None)
+    assert rc == C.COSMOS_EINVAL and "must not overlap" in C.last_error()
+    rc = lib.cosmos_rk4_steps_stages(G, Pp, 0.0, 0.1, 2, u, states, ctypes.c_void_p(0x80000000 + n), ws, None)
+    assert rc == C.COSMOS_EINVAL and "must not overlap" in C.last_error()
+    assert lib.cosmos_rk4_steps_stages(G, Pp, 0.0, 0.1, 0, u, states, stages, ws, None) == C.COSMOS_OK
+    b = C.cosmos_batch()
+    rc = lib.cosmos_rk4_steps_batched(ctypes.byref(b), Pp, u, u, u, 0, ws, None)
+    assert rc == C.COSMOS_EINVAL and "nsteps 0 < 1" in C.last_error()
+    base = 0x100000
+    m = 16 ** 3 * 8
+    us, s, wss, sws = (ctypes.c_void_p(base), ctypes.c_void_p(base + 25 * m), ctypes.c_void_p(base + 64 * m),
+                       ctypes.c_void_p(base + 128 * m))
+    rc = lib.cosmos_rk4_steps_scalar(G, Pp, 0.0, 0.1, -1, us, s, wss, sws, None)
+    assert rc == C.COSMOS_EINVAL and "nsteps -1" in C.last_error()
