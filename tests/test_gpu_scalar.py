@@ -84,11 +84,13 @@ def test_scalar_lds_kernel_equals_direct_bitwise(P, orc):
     assert err_fields(du1.reshape(25, *du0.shape[1:]).cpu().numpy(), du0.cpu().numpy())[0] < 1e-13
 
 
-def test_scalar_rk4_steps_equals_single_steps(P, orc):
+@pytest.mark.parametrize("n,scheme", [((20, 12, 18), 0), ((20, 12, 18), 1), ((17, 12, 18), 0)])
+def test_scalar_rk4_steps_equals_single_steps(P, orc, n, scheme):
     """cosmos_rk4_steps_scalar (fluid fluxes carried from step to step): 4 steps in one call equal
-    4 single steps at t, t + dt, ... bitwise, geometry and field; nsteps < 0 is refused."""
-    n, L = (20, 12, 18), (4.0, 2.5, 3.5)
-    s, sol = mk(P, orc, n, L)
+    4 single steps at t, t + dt, ... bitwise, geometry and field, for both fluid schemes and for an
+    odd n0 (the direct kernels); nsteps < 0 is refused."""
+    L = (4.0, 2.5, 3.5)
+    s, sol = mk(P, orc, n, L, fluid_scheme=scheme)
     u, sc = fuzz_state(n, seed=45), fuzz_scalar(n, seed=46)
     dt = 0.25 * min(s.h)
     sol.set_state(to_dev(u), t=0.1, s=to_dev(sc))
