@@ -241,6 +241,15 @@ int cosmos_rk4_steps(const cosmos_grid* grid, const cosmos_params* params, doubl
 int cosmos_rk4_step_stages(const cosmos_grid* grid, const cosmos_params* params, double t, double dt,
                            double* u, double* stages, void* ws, void* stream);
 
+/* One RK4 step as cosmos_rk4_step_stages, out of place: u (read only) keeps u_n and u_next
+ * (device, caller-owned, 25 * N3 doubles) receives u_{n+1}, bitwise the state
+ * cosmos_rk4_step_stages leaves in u; stages receives U2, U3, U4 as there. For drivers that need
+ * the step's start state afterwards (the refined layers' interpolation in time below; the paper's
+ * fixed mesh refinement, "Statement of need"): alternating two state arrays saves a copy of u.
+ * u, u_next, stages and ws must not overlap (COSMOS_EINVAL); other errors as cosmos_rk4_step. */
+int cosmos_rk4_step_stages_to(const cosmos_grid* grid, const cosmos_params* params, double t, double dt,
+                              const double* u, double* u_next, double* stages, void* ws, void* stream);
+
 /* nsteps (>= 0) RK4 steps as cosmos_rk4_steps (the same u bitwise as single steps at t, t + dt,
  * t + dt + dt, ...), keeping the whole trajectory for a reverse sweep: states (nsteps * 25 * N3
  * doubles) receives the start state of step m at offset m * 25 * N3, stages (nsteps * 3 * 25 * N3

@@ -75,6 +75,7 @@ def _load():
         "cosmos_rk4_steps": ([G, Pr, f64, f64, i32, P, P, P], i32),
         "cosmos_rk4_steps_stages": ([G, Pr, f64, f64, i32, P, P, P, P, P], i32),
         "cosmos_rk4_step_stages": ([G, Pr, f64, f64, P, P, P, P], i32),
+        "cosmos_rk4_step_stages_to": ([G, Pr, f64, f64, P, P, P, P, P], i32),
         "cosmos_constraints": ([G, Pr, P, P, P, P, P, P], i32),
         "cosmos_constraints_noalloc": ([G, Pr, P, P, P, P, P], i32),
         "cosmos_adjoint_step": ([G, Pr, f64, f64, P, P, P, P, P], i32),
@@ -244,6 +245,14 @@ def cosmos_rk4_step_stages(grid, params, t: float, dt: float, u, stages, ws, str
                                       _dev(stages, "stages", 3 * N),
                                       _dev(ws, "ws", cosmos_workspace_bytes(grid), dtype=torch.uint8),
                                       _stream(stream)))
+
+
+def cosmos_rk4_step_stages_to(grid, params, t: float, dt: float, u, u_next, stages, ws, stream=None):
+    N = NFIELDS * npts(grid)
+    _check(lib.cosmos_rk4_step_stages_to(ctypes.byref(grid), ctypes.byref(params), float(t), float(dt),
+                                         _dev(u, "u", N), _dev(u_next, "u_next", N), _dev(stages, "stages", 3 * N),
+                                         _dev(ws, "ws", cosmos_workspace_bytes(grid), dtype=torch.uint8),
+                                         _stream(stream)))
 
 
 def cosmos_constraints(grid, params, u, norms_dev, H_out=None, M_out=None, ws=None, stream=None):

@@ -197,7 +197,7 @@ namespace {
 // written after U2 has been read for the last time). carry: the flux arrays carried from one step
 // of a call to the next (see FluxPair); nullptr: a step of its own.
 int rk4_step(const cosmos_grid* grid, const cosmos_params* params, double t, double dt, double* u, double* U2,
-             double* U3, double* U4, void* ws, void* stream, FluxPair* carry = nullptr) {
+             double* U3, double* U4, void* ws, void* stream, FluxPair* carry = nullptr, double* unew = nullptr) {
   const Layout L = layout(grid);
   char* w = (char*)ws;
   double* acc = (double*)(w + L.acc);
@@ -214,7 +214,8 @@ int rk4_step(const cosmos_grid* grid, const cosmos_params* params, double t, dou
   if ((rc = fx.stage(params, T, s, u, u, acc, U2, fs, P, t, dt / 6.0, dt / 2.0, 1, status))) return rc;
   fx.stage(params, T, s, U2, u, acc, U3, fs, P, t + dt / 2.0, dt / 3.0, dt / 2.0, 2, status);
   fx.stage(params, T, s, U3, u, acc, U4, fs, P, t + dt / 2.0, dt / 3.0, dt, 2, status);
-  fx.stage(params, T, s, U4, nullptr, acc, u, fs, P, t + dt, dt / 6.0, 0.0, 3, status);
+  // the last stage writes u_{n+1} over u, or into unew (u itself then keeps u_n)
+  fx.stage(params, T, s, U4, nullptr, acc, unew ? unew : u, fs, P, t + dt, dt / 6.0, 0.0, 3, status);
   HIP_TRY(hipGetLastError());
   return COSMOS_OK;
 }
@@ -353,6 +354,27 @@ int cosmos_rk4_step_stages(const cosmos_grid* grid, const cosmos_params* params,
   const char *c = (const char*)ws, *c1 = c + cosmos_workspace_bytes(grid);
   if ((a < b1 && b < a1) || (a < c1 && c < a1)) return set_error(COSMOS_EINVAL, "stages overlaps u or ws");
   return rk4_step(grid, params, t, dt, u, stages, stages + n, stages + 2 * n, ws, stream);
+}
+
+int cosmos_rk4_step_stages_to(const cosmos_grid* grid, const cosmos_params* params, double t, double dt,
+                              const double* u, double* u_next, double* stages, void* ws, void* stream) {
+  int rc;
+  if ((rc = check_common(grid, params)) || (rc = check_state(u, "u")) || (rc = check_state(u_next, "u_next")) ||
+      (rc = check_state(stages, "stages")) || (rc = check_ws(grid, ws)))
+    return rc;
+  if (!(dt > 0.0) || !std::isfinite(dt) || !std::isfinite(t)) return set_error(COSMOS_EINVAL, "dt must be > 0, t finite");
+  const size_t n = (size_t)NF * npts(grid);
+  const char *ua = (const char*)u, *ub = ua + n * sizeof(double);
+  const char *va = (const char*)u_next, *vb = va + n * sizeof(double);
+  const char *ga = (const char*)stages, *gb = ga + 3 * n * sizeof(double);
+  const char *wa = (const char*)ws, *wb = wa + cosmos_workspace_bytes(grid);
+  auto apart = [](const char* a0, const char* a1, const char* b0, const char* b1) { return a1 <= b0 || b1 <= a0; };
+  if (!apart(ua, ub, va, vb) || !apart(ua, ub, ga, gb) || !apart(ua, ub, wa, wb) || !apart(va, vb, ga, gb) ||
+      !apart(va, vb, wa, wb) || !apart(ga, gb, wa, wb))
+    return set_error(COSMOS_EINVAL, "u, u_next, stages and ws must not overlap");
+  // u is only read: every stage takes it as u_n, and the last one writes u_next
+  double* U = const_cast<double*>(u);
+  return rk4_step(grid, params, t, dt, U, stages, stages + n, stages + 2 * n, ws, stream, nullptr, u_next);
 }
 
 int cosmos_rk4_steps_stages(const cosmos_grid* grid, const cosmos_params* params, double t, double dt,

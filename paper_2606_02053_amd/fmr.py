@@ -2,10 +2,10 @@
 refinement layers, "Statement of need" and the adiabatic-fluctuation example).
 
 Sequencing only: every value is computed by the library (cosmos_rk4_step,
-cosmos_rk4_step_stages, cosmos_fmr_prolong, cosmos_fmr_restrict); PyTorch holds the device arrays. The scheme is the one
+cosmos_rk4_step_stages_to, cosmos_fmr_prolong, cosmos_fmr_restrict); PyTorch holds the device arrays. The scheme is the one
 stated with those entry points in include/cosmos.h:
 
-  step of layer l (dt):   keep u_l as u0; RK4 step of u_l keeping its stage states;
+  step of layer l (dt):   RK4 step of u_l keeping its stage states, out of place (u_n stays as u0);
                           for each half h = 0, 1: refill layer l + 1's buffer from layer l at
                           theta = h / 2 (u0 alone for h = 0, the step's continuous extension from
                           its stage states for h = 1), then step layer l + 1 by dt / 2
@@ -42,7 +42,9 @@ class RefinedRun:
         self.u = [torch.empty((C.NFIELDS, g.n[2], g.n[1], g.n[0]), **f64) for g in self.grids]
         self.ws = [torch.empty(C.cosmos_workspace_bytes(g), dtype=torch.uint8, device=self.device)
                    for g in self.grids]
-        # per refined parent: the start-of-step copy, the step's stage states, the prolongation workspace
+        # per refined parent: a second state array (the step runs out of place, so the two alternate:
+        # after a step one holds u_n for the child's interpolation in time, the other u_{n+1}), the
+        # step's stage states, the prolongation workspace
         self.u0 = [torch.empty_like(self.u[k]) for k in range(len(self.boxes))]
         self.stages = [torch.empty((3,) + tuple(self.u[k].shape), **f64) for k in range(len(self.boxes))]
         self.pws = [torch.empty(C.cosmos_fmr_workspace_bytes(self.grids[k], b), dtype=torch.uint8,
@@ -73,8 +75,9 @@ class RefinedRun:
             C.cosmos_rk4_step(g, self.params, t, dt, u, self.ws[k])
             return
         b = self.boxes[k]
-        self.u0[k].copy_(u)
-        C.cosmos_rk4_step_stages(g, self.params, t, dt, u, self.stages[k], self.ws[k])
+        C.cosmos_rk4_step_stages_to(g, self.params, t, dt, u, self.u0[k], self.stages[k], self.ws[k])
+        self.u[k], self.u0[k] = self.u0[k], u  # u_{n+1} is the layer's state now; u_n stays beside it
+        u = self.u[k]
         for half in (0, 1):
             C.cosmos_fmr_prolong(g, b, self.u0[k], self.stages[k], u, 0.5 * half, True, self.u[k + 1], self.pws[k])
             self._step(k + 1, t + 0.5 * half * dt, 0.5 * dt)
@@ -90,7 +93,8 @@ class RefinedRun:
             self.step(dt)
 
     def interior(self, k: int) -> torch.Tensor:
-        """Layer k's interior points (a view of its padded array; the whole grid for k = 0)."""
+        """Layer k's interior points (a view of its padded array; the whole grid for k = 0). A refined
+        parent's state alternates between two arrays from step to step: take the view after stepping."""
         if k == 0:
             return self.u[0]
         W = C.COSMOS_FMR_BUFFER

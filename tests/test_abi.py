@@ -221,3 +221,20 @@ def test_multi_step_entry_points_validate_on_host(C):
                        ctypes.c_void_p(base + 128 * m))
     rc = lib.cosmos_rk4_steps_scalar(G, Pp, 0.0, 0.1, -1, us, s, wss, sws, None)
     assert rc == C.COSMOS_EINVAL and "nsteps -1" in C.last_error()
+
+
+def test_out_of_place_step_validates_on_host(C):
+    g = C.make_grid(16, 4.0)
+    p = C.make_params()
+    lib = C.lib
+    n = 25 * 16 ** 3 * 8
+    u, nxt, stages = ctypes.c_void_p(0x10000000), ctypes.c_void_p(0x20000000), ctypes.c_void_p(0x30000000)
+    ws = ctypes.c_void_p(0x40000000)
+    G, Pp = ctypes.byref(g), ctypes.byref(p)
+    rc = lib.cosmos_rk4_step_stages_to(G, Pp, 0.0, 0.1, u, None, stages, ws, None)
+    assert rc == C.COSMOS_EINVAL and "u_next is NULL" in C.last_error()
+    rc = lib.cosmos_rk4_step_stages_to(G, Pp, 0.0, 0.1, u, ctypes.c_void_p(0x10000000 + n // 2), stages, ws, None)
+    assert rc == C.COSMOS_EINVAL and "must not overlap" in C.last_error()
+    rc = lib.cosmos_rk4_step_stages_to(G, Pp, 0.0, 0.1, u, nxt, ctypes.c_void_p(0x20000000 + 8), ws, None)
+    assert rc == C.COSMOS_EINVAL and "must not overlap" in C.last_error()
+    assert lib.cosmos_rk4_step_stages_to(G, Pp, 0.0, -0.1, u, nxt, stages, ws, None) == C.COSMOS_EINVAL

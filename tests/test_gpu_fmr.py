@@ -155,3 +155,23 @@ def test_benchmark_shaped_hierarchy_matches_oracle(P, orc):
         assert e < 1e-9 and a < 1e-13, (k, e, a)
     for k in range(3):
         assert run.status(k)["nonfinite"] == 0
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_out_of_place_stage_keeping_step_equals_in_place(P, variant):
+    """cosmos_rk4_step_stages_to (the refined run's parent step): u is left as it was, u_next and
+    the stage states equal what cosmos_rk4_step_stages leaves in u and its stages, bitwise."""
+    n, L = (20, 12, 18), (4.0, 2.5, 3.5)
+    grid = P.make_grid(n, L)
+    params = P.make_params(variant=variant)
+    u0 = torch.from_numpy(fuzz_state(n, seed=91)).cuda()
+    ws = torch.empty(P.cosmos_workspace_bytes(grid), dtype=torch.uint8, device="cuda")
+    dt = 0.25 * min(L[a] / n[a] for a in range(3))
+    inplace, st_in = u0.clone(), torch.empty((3,) + tuple(u0.shape), dtype=torch.float64, device="cuda")
+    P.cosmos_rk4_step_stages(grid, params, 0.3, dt, inplace, st_in, ws)
+    u, nxt = u0.clone(), torch.full_like(u0, float("nan"))
+    st = torch.full_like(st_in, float("nan"))
+    P.cosmos_rk4_step_stages_to(grid, params, 0.3, dt, u, nxt, st, ws)
+    assert torch.equal(u, u0) and torch.equal(nxt, inplace) and torch.equal(st, st_in)
+    with pytest.raises(P.CosmosError):
+        P.cosmos_rk4_step_stages_to(grid, params, 0.3, dt, u, u, st, ws)
