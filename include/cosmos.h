@@ -426,7 +426,8 @@ size_t cosmos_fmr_workspace_bytes(const cosmos_grid* parent, const cosmos_box* b
  * RK4 step from u_n to u_np1 at t_n + theta dt, u_n + dt sum_i b_i(theta) k_i with
  * b = (theta - 3/2 theta^2 + 2/3 theta^3, theta^2 - 2/3 theta^3 (twice), -1/2 theta^2 + 2/3 theta^3),
  * the slopes k_i recovered from the step's stage states (stages: U2, U3, U4 as
- * cosmos_rk4_step_stages keeps them, 3 x 25 x N3(parent) doubles); at theta = 1/2 this is
+ * cosmos_rk4_step_stages or cosmos_rk4_step_stages_to keeps them, 3 x 25 x N3(parent) doubles);
+ * at theta = 1/2 this is
  * (2 U2 + 2 U3 + U4 - u_np1) / 4. In space, per axis: a child point that coincides with a parent
  * point copies it, a midpoint takes (3, -25, 150, 150, -25, 3)/256 of the 6 parent points around
  * it (exact for quintics), applied along x, then y, then z. buffer_only != 0 writes only the child
